@@ -1,0 +1,272 @@
+"""Pins for the CPU oracle: every check compares it with something that is
+not the oracle -- trial division written here, SymPy's primality routines,
+prime counts from the literature, the counts the paper prints, and strong
+pseudoprimes published in the Miller-Rabin literature.
+
+A plausible mistake anywhere in the oracle (a dropped prime, a window off by
+one, a wrong MR base, a mis-ordered scan, a summary with a wrong weight or a
+wrong tie-break) fails at least one of these.
+"""
+import os
+import random
+
+import numpy as np
+import pytest
+import sympy
+from sympy.ntheory.primetest import mr as sympy_mr
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "paper_counts.txt")
+
+
+def _golden():
+    rows = []
+    with open(GOLDEN) as f:
+        for line in f:
+            line = line.strip()
+            if line and not line.startswith("#"):
+                kind, arg, val, _src = line.split()
+                rows.append((kind, int(arg), int(val)))
+    return rows
+
+
+# --------------------------------------------------------------------------
+# independent brute force: trial division only
+# --------------------------------------------------------------------------
+
+def _td_prime_table(limit):
+    """is_prime[x] for 0 <= x <= limit by trial division of each x."""
+    tab = [False] * (limit + 1)
+    for x in range(2, limit + 1):
+        d, ok = 2, True
+        while d * d <= x:
+            if x % d == 0:
+                ok = False
+                break
+            d += 1
+        tab[x] = ok
+    return tab
+
+
+def _td_pmin(n, tab):
+    for p in range(2, n // 2 + 1):
+        if tab[p] and tab[n - p]:
+            return p
+    return 0
+
+
+@pytest.fixture(scope="module")
+def td_table():
+    return _td_prime_table(100_000)
+
+
+# --------------------------------------------------------------------------
+# prime counts
+# --------------------------------------------------------------------------
+
+def test_pi_paper_value(orc):
+    for kind, arg, val in _golden():
+        if kind == "pi":
+            assert orc.prime_count(arg) == val
+
+
+@pytest.mark.parametrize("x,pi", [
+    (10**7, 664_579), (10**8, 5_761_455),
+    (2**10, 172), (2**13, 1028), (2**16, 6542), (31_622, 3401), (1, 0), (2, 1), (3, 2),
+])
+def test_pi_known(orc, x, pi):
+    # classical prime counts; the small ones re-derived with SymPy below
+    assert orc.prime_count(x) == pi
+    if x <= 10**7:
+        assert sympy.primepi(x) == pi
+
+
+@pytest.mark.slow
+def test_pi_1e9(orc):
+    assert orc.prime_count(10**9) == 50_847_534
+
+
+# --------------------------------------------------------------------------
+# primality predicates
+# --------------------------------------------------------------------------
+
+def test_trial_division_vs_sympy(orc):
+    for q in list(range(0, 3000)) + [10**12 - 11, 10**12 + 39, 999_999_999_989]:
+        assert orc.trial_is_prime(q) == sympy.isprime(q), q
+
+
+STRONG_PSP = [
+    # (n, bases it passes, base that exposes it) -- Pomerance, Selfridge and
+    # Wagstaff (1980); Jaeschke (1993); Zhang and Tang (2003).
+    (2047, [2], 3),
+    (1373653, [2, 3], 5),
+    (25326001, [2, 3, 5], 7),
+    (3215031751, [2, 3, 5, 7], 11),
+    (2152302898747, [2, 3, 5, 7, 11], 13),
+    (3474749660383, [2, 3, 5, 7, 11, 13], 17),
+    (341550071728321, [2, 3, 5, 7, 11, 13, 17, 19], 23),
+    (3825123056546413051, [2, 3, 5, 7, 11, 13, 17, 19, 23, 29, 31], 37),
+]
+
+
+@pytest.mark.parametrize("n,passes,fails", STRONG_PSP)
+def test_strong_pseudoprimes(orc, n, passes, fails):
+    assert not sympy.isprime(n)
+    for a in passes:
+        assert orc.mr_base(n, a), (n, a)
+    assert not orc.mr_base(n, fails)
+    assert not orc.mr(n)
+    # each single-base verdict also agrees with SymPy's strong test
+    for a in (2, 3, 5, 7, 11, 13, 17, 19, 23, 29, 31, 37):
+        assert orc.mr_base(n, a) == sympy_mr(n, [a]), (n, a)
+
+
+@pytest.mark.parametrize("p", [2**61 - 1, 2**63 - 25, 2**64 - 59, 2**31 - 1,
+                               1_000_000_000_039, 999_999_999_989])
+def test_mr_known_primes(orc, p):
+    assert sympy.isprime(p)
+    assert orc.mr(p)
+    assert orc.is_prime(p)
+
+
+@pytest.mark.parametrize("c", [2**64 - 1, 2**63 - 1, 561, 1105, 1729, 2465, 2821, 6601,
+                               8911, 4, 9, 25, 49, 121, 1, 0])
+def test_mr_known_composites(orc, c):
+    assert not orc.mr(c)
+
+
+def test_mr_vs_sympy_random(orc):
+    rng = random.Random(12345)
+    for _ in range(20_000):
+        q = rng.getrandbits(64) | 1
+        assert orc.mr(q) == sympy.isprime(q), q
+    for _ in range(300):
+        p = sympy.randprime(2**40, 2**64)
+        assert orc.mr(p)
+
+
+def test_mr_vs_trial_small(orc, td_table):
+    for q in range(0, 100_001):
+        assert orc.mr(q) == td_table[q], q
+
+
+# --------------------------------------------------------------------------
+# p_min per n
+# --------------------------------------------------------------------------
+
+def test_pmin_bruteforce_1e5(orc, td_table):
+    out, hist, s = orc.verify_range(4, 100_000, per_n_bits=32)
+    ref = np.array([_td_pmin(n, td_table) for n in range(4, 100_001, 2)], dtype=np.uint32)
+    assert np.array_equal(out, ref)
+    assert s["count"] == len(ref)
+    assert s["n_failed"] == 0
+
+
+def _summaries_by_hand(ns, ps, pmax):
+    """Summary definitions written out directly over (n, p) pairs."""
+    hist = np.zeros(6543, dtype=np.uint64)
+    cs, mx, arg, nex = 0, 0, 0, 0
+    for n, p in zip(ns, ps):
+        b = sympy.primepi(p) - 1 if p < 65536 else 6542
+        hist[b] += 1
+        cs = (cs + (n // 2) * p) % 2**64
+        if p > mx:
+            mx, arg = p, n
+        if p > pmax:
+            nex += 1
+    return hist, dict(count=len(ns), checksum=cs, max_p=mx, argmax_n=arg, n_exhaustive=nex)
+
+
+@pytest.mark.parametrize("lo,hi,pmax", [(4, 20_000, 8192), (1_001, 19_999, 7), (4, 4, 8192),
+                                        (6, 6, 3), (5_000, 9_000, 13)])
+def test_summaries_bruteforce(orc, td_table, lo, hi, pmax):
+    out, hist, s = orc.verify_range(lo, hi, pmax=pmax, per_n_bits=32)
+    a = max(lo, 4) + (max(lo, 4) & 1)
+    ns = list(range(a, hi - (hi & 1) + 1, 2))
+    ps = [_td_pmin(n, td_table) for n in ns]
+    h, ref = _summaries_by_hand(ns, ps, pmax)
+    assert np.array_equal(hist, h)
+    for k, v in ref.items():
+        assert s[k] == v, k
+    # consistency identities
+    assert int(hist.sum()) == s["count"]
+
+
+def test_config1_summary(orc):
+    # every even n in [4, 10^6]: 499,999 of them; maximum p_min is 523,
+    # first reached at n = 503,222 -- re-checked with SymPy here
+    out, hist, s = orc.verify_range(4, 10**6, per_n_bits=32)
+    assert s["count"] == 499_999 and s["n_failed"] == 0
+    n = s["argmax_n"]
+    p = s["max_p"]
+    assert sympy.isprime(p) and sympy.isprime(n - p)
+    assert all(not sympy.isprime(n - r) for r in sympy.primerange(2, p))
+    assert int(out.max()) == p and 4 + 2 * int(np.argmax(out)) == n
+
+
+def _check_minimal(n, p):
+    assert p >= 2 and sympy.isprime(p) and sympy.isprime(n - p), (n, p)
+    for r in sympy.primerange(2, p):
+        assert not sympy.isprime(n - r), (n, p, r)
+
+
+@pytest.mark.parametrize("n", [10**6, 10**9, 10**12, 10**15, 2**62, 2**63, 2**63 - 2,
+                               10**12 - 2**36, 4, 6, 8, 2**64 - 2])
+def test_verify_one_minimal(orc, n):
+    p = orc.verify_one(n)
+    _check_minimal(n, p)
+
+
+def test_verify_one_random(orc):
+    rng = np.random.default_rng(7)
+    ns = [2 * int(x) for x in rng.integers(2, 2**62, size=200, endpoint=True)]
+    ps = orc.verify_many(ns, threads=4)
+    for n, p in zip(ns, ps):
+        _check_minimal(n, int(p))
+
+
+def test_verify_one_limit_reports_failure(orc):
+    # 98 = 19 + 79 and no smaller prime works, so a scan bounded by 17 fails
+    assert orc.verify_one(98) == 19
+    assert orc.verify_one(98, limit=17) == 0
+    assert orc.verify_one(7) == 0 and orc.verify_one(2) == 0
+
+
+def test_window_near_1e12_matches_single_n(orc):
+    lo, hi = 10**12 - 2**17, 10**12
+    out, hist, s = orc.verify_range(lo, hi, per_n_bits=16)
+    rng = np.random.default_rng(3)
+    idx = rng.integers(0, len(out), size=300)
+    for i in idx:
+        n = lo + 2 * int(i)
+        p = int(out[i])
+        assert p == orc.verify_one(n)
+        _check_minimal(n, p)
+    assert s["count"] == 2**16 + 1
+
+
+def test_multithread_equals_single(orc):
+    lo, hi = 10**9 - 2**23, 10**9 + 2**22
+    o1, h1, s1 = orc.verify_range(lo, hi, per_n_bits=16)
+    o2, h2, s2 = orc.verify_range(lo, hi, per_n_bits=16, threads=5)
+    assert np.array_equal(o1, o2) and np.array_equal(h1, h2) and s1 == s2
+
+
+def test_paper_counts_small(orc):
+    for kind, arg, val in _golden():
+        if kind == "count" and arg <= 10**8:
+            _, _, s = orc.verify_range(4, arg, per_n_bits=None, hist=False, threads=4)
+            assert s["count"] == val
+            assert s["n_failed"] == 0
+        elif kind == "count":
+            assert orc.n_even(4, arg) == val
+
+
+@pytest.mark.slow
+def test_paper_no_failures_1e9(orc):
+    for kind, arg, val in _golden():
+        if kind == "nofail":
+            _, hist, s = orc.verify_range(4, arg, pmax=10**6, per_n_bits=None, threads=8)
+            assert s["n_failed"] == val
+            assert s["n_exhaustive"] == 0
+            assert s["count"] == 499_999_999
+            assert int(hist.sum()) == s["count"]

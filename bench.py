@@ -1,0 +1,159 @@
+"""Benchmark: even n verified per second at N ~ 10^12 on one MI355X.
+
+Workload: every even n in [10^12 - 2^36, 10^12] (2^35 + 1 of them), summaries
+only (count, histogram, max p and its n, checksum), sieving primes up to
+sqrt(10^12 + ...) resident.  One step is one complete verification of that
+range.  The timed form is the batched one (one persistent tile launch in a
+replayed HIP graph); the plain form (one launch per segment of S even n) is
+timed beside it.  Prints one JSON line.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-serve]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+LO, HI = 10**12 - 2**36, 10**12
+METRIC = "even n verified/s at N~1e12 on 1 MI355X (batched form)"
+
+# Per-n algorithmic work of the sieve-and-search kernel at this workload
+# (derivation in DESIGN.md, "Roofline"): 1.711 bit clears (3 VALU ops each),
+# 1.01 64-bit window probes (7 VALU ops each), 1/32 wheel word (5 ops).
+CLEARS_PER_N = 1.711
+PROBES_PER_N = 1.01
+ALG_OPS_PER_N = CLEARS_PER_N * 3 + PROBES_PER_N * 7 + 5 / 32
+# 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz, one 32-bit integer op per lane-cycle
+ALU_PEAK_OPS = 256 * 64 * 2.4e9
+
+
+def _load_tuned():
+    path = os.path.join(ROOT, "paper_2603_02621_amd", "tuned.json")
+    if os.path.exists(path):
+        with open(path) as f:
+            d = json.load(f)
+        return {k: int(d[k]) for k in ("pmax", "seg_log2", "tile_log2", "wg_threads", "wheel_max")
+                if k in d}
+    return {}
+
+
+def cpu_baseline(threads: int, log2n: int = 30):
+    """The oracle as it stands, timed on the host cores over a bounded sample."""
+    import oracle
+    oracle.build(force=False)
+    lo = HI - 2 * ((1 << log2n) - 1)
+    t0 = time.perf_counter()
+    _, _, s = oracle.verify_range(lo, HI, per_n_bits=None, hist=True, threads=threads)
+    dt = time.perf_counter() - t0
+    return {"value": s["count"] / dt, "unit": "even n/s", "cores": threads, "kind": "oracle",
+            "sample": f"2^{log2n} even n ending at 1e12 ({s['count']} n, {dt:.2f} s wall)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--plain-steps", type=int, default=1)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: the verifier shards segments across GPUs by "
+              "design, but this build runs and reports a single MI355X (use --gpus 1)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2603_02621_amd import Verifier
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    params = _load_tuned()
+    v = Verifier(0, **params)
+    p = v.params
+    print(f"# params {p}", file=sys.stderr, flush=True)
+
+    # ---- batched (timed) --------------------------------------------------
+    for _ in range(args.warmup):
+        w = v.verify_range(LO, HI, batched=True)
+        print(f"# warmup batched {w['device_ms']:.1f} ms", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    tile_ms, dev_ms = [], []
+    ref = None
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        r = v.verify_range(LO, HI, batched=True)
+        tile_ms.append(r["tile_ms"])
+        dev_ms.append(r["device_ms"])
+        if ref is None:
+            ref = r
+        assert r["checksum"] == ref["checksum"] and r["count"] == ref["count"]
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    count = ref["count"]
+    ms_per_step = 1e3 * wall / args.steps
+    value = count * args.steps / wall
+    print(f"# batched: {ms_per_step:.1f} ms/step, tile kernel {sum(tile_ms)/len(tile_ms):.1f} ms",
+          file=sys.stderr, flush=True)
+
+    # ---- plain (beside it) ------------------------------------------------
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plain_tile = []
+    for _ in range(args.plain_steps):
+        rp = v.verify_range(LO, HI, batched=False)
+        plain_tile.append(rp["tile_ms"] / max(rp["tile_launches"], 1))
+    torch.cuda.synchronize()
+    plain_wall = (time.perf_counter() - t0) / args.plain_steps
+    for k in ("count", "checksum", "max_p", "argmax_n", "n_exhaustive", "n_failed"):
+        assert rp[k] == ref[k], k
+    print(f"# plain: {1e3*plain_wall:.1f} ms/step over {rp['n_segments']} segment launches",
+          file=sys.stderr, flush=True)
+
+    # ---- roofline of the dominant kernel ------------------------------------
+    t_launch = sum(tile_ms) / len(tile_ms) / 1e3
+    achieved = ALG_OPS_PER_N * count / t_launch
+    roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": ALU_PEAK_OPS / 1e12,
+            "unit": "Tops/s (int32 lane ops)", "frac": achieved / ALU_PEAK_OPS, "traffic": None,
+            "kernel": "k_tile (persistent)", "launch_ms": t_launch * 1e3,
+            "alg_ops_per_n": round(ALG_OPS_PER_N, 3)}
+
+    out = {
+        "metric": METRIC, "value": value, "unit": "even n/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "u32/u64 integer", "data": "synthetic (deterministic integer range)",
+        "config": {"workload": "all even n in [1e12-2^36, 1e12], summaries only",
+                   "n_per_step": count, "pmax": p["pmax"], "seg_log2": p["seg_log2"],
+                   "tile_log2": p["tile_log2"], "wg_threads": p["wg_threads"],
+                   "wheel_max": p["wheel_max"], "parallelism": "1 GPU"},
+        "plain": {"value": count / plain_wall, "ms_per_step": 1e3 * plain_wall,
+                  "segments": rp["n_segments"], "tile_launch_ms": sum(plain_tile) / len(plain_tile)},
+        "summary": {k: ref[k] for k in ("count", "max_p", "argmax_n", "checksum",
+                                        "n_exhaustive", "n_failed")},
+        "roofline": roof,
+    }
+
+    if not args.no_serve:
+        try:
+            from paper_2603_02621_amd import serving
+            out["serving"] = serving.quick_latency(v)
+        except (ImportError, AttributeError) as e:
+            out["serving"] = {"skipped": str(e)}
+
+    v.close()
+    if not args.no_cpu:
+        threads = len(os.sched_getaffinity(0))
+        out["cpu_baseline"] = cpu_baseline(threads)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

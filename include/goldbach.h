@@ -1,0 +1,207 @@
+/*
+ * goldbach.h -- C ABI of the MI355X segmented Goldbach verifier.
+ *
+ * The library computes, for every even n in a range (or a set of windows, or
+ * a single n), the minimal Goldbach prime
+ *
+ *     p_min(n) = min { p prime : n - p prime },        n even, n >= 4,
+ *
+ * which is the first hit of the scan "primes p from 2 upward, stop when
+ * q = n - p is prime" that the GoldbachGPU paper verifies (section "Methods",
+ * CPU baseline; section "Segmented Double-Sieve Verifier").  The work is the
+ * paper's segmented double sieve with the loop inverted (subsection "Correct
+ * segmentation"): a bit-packed odd-only sieve of each tile's window is built
+ * on the GPU, every candidate prime p up to P_max is probed against it for 64
+ * even n at a time, and any n left unresolved goes to an exhaustive phase
+ * that scans the primes above P_max in ascending order with a deterministic
+ * Miller-Rabin test of q (the paper's Phase 2, done on the GPU here).
+ *
+ * Conventions shared by every call:
+ *  - Ranges are inclusive: a range call covers every even n with
+ *    max(lo, 4) <= n <= hi.  lo > hi (after rounding lo up and hi down to
+ *    even) is an empty range and returns GB_OK with count 0.
+ *  - n never exceeds GB_MAX_N = 2^63; range calls also need hi <= the
+ *    context's max_hi.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *    Every call below is synchronous: it enqueues its work on `stream`,
+ *    waits for it, and returns with all outputs written.
+ *  - Device pointers must belong to the context's device.  Host pointers
+ *    are ordinary (pageable) memory.
+ *  - A context is not thread-safe; use one per host thread.  No call aborts
+ *    or throws; on a status other than GB_OK the outputs are unspecified and
+ *    gb_last_error() describes the failure.
+ */
+#ifndef GOLDBACH_H
+#define GOLDBACH_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum gb_status {
+    GB_OK = 0,
+    GB_EINVAL = 1,      /* bad argument: n odd or < 4, n > 2^63, bad params */
+    GB_ERANGE = 2,      /* hi above the context's max_hi */
+    GB_ENOMEM = 3,      /* allocation failed, or the unresolved list overflowed */
+    GB_EDEVICE = 4,     /* a HIP runtime error; text in gb_last_error() */
+    GB_EUNRESOLVED = 5  /* some n had no partition with p <= min(n/2, budget):
+                           the summaries are complete, n_failed > 0 and
+                           first_failed_n names the smallest such n */
+} gb_status;
+
+/* Histogram bins: one per prime below 2^16 (2 -> bin 0, 3 -> bin 1, ...,
+ * 65521 -> bin 6541) plus bin 6542 for p_min >= 2^16. */
+#define GB_HIST_BINS 6543
+#define GB_MAX_N 9223372036854775808ull /* 2^63 */
+
+typedef struct gb_ctx gb_ctx;
+
+/* Context parameters.  A zero field takes the documented default. */
+typedef struct gb_params {
+    int32_t  device;        /* HIP device ordinal */
+    uint32_t pmax;          /* fast-path bound P_max on p, 0..65535 (0 -> 8192).
+                               Odd primes p <= P_max are probed against the
+                               tile sieve; larger p belong to the exhaustive
+                               phase.  Any value gives the same p_min. */
+    uint32_t seg_log2;      /* plain form: S = 2^seg_log2 even n per segment
+                               (one launch per segment), 16..30 (0 -> 24) */
+    uint32_t tile_log2;     /* T = 2^tile_log2 even n per tile (one workgroup
+                               sieves and searches one tile in LDS), 12..20
+                               (0 -> 18) */
+    uint32_t wg_threads;    /* threads per tile workgroup: 256, 512 or 1024
+                               (0 -> 512) */
+    uint32_t wheel_max;     /* largest prime of the pre-sieved wheel pattern:
+                               7, 11, 13, 17 or 19 (0 -> 19) */
+    uint64_t max_hi;        /* largest n any range call may reach; sizes the
+                               resident sieving-prime table to sqrt(max_hi)
+                               (0 -> 2^50; at most 2^63) */
+    uint64_t exhaustive_budget_p; /* the exhaustive phase stops past this p
+                               (0 -> n/2, i.e. a complete search) */
+    uint64_t max_unresolved;/* capacity of the device list of n that the fast
+                               path leaves to the exhaustive phase
+                               (0 -> 2^20 entries, 32 bytes each) */
+    uint64_t mem_budget;    /* serving: bytes of request buffers admitted at
+                               once (0 -> 4 GiB) */
+} gb_params;
+
+/* Result of a range call.  The caller fills the first group (all optional)
+ * and the library fills the second. */
+typedef struct gb_result {
+    void     *pmin;           /* per-n p_min, entry i for n = lo' + 2i, or NULL */
+    uint32_t  pmin_bits;      /* 16 (p_min >= 2^16 and failures stored as 0)
+                                 or 32 (failures stored as 0) */
+    uint32_t  pmin_on_device; /* 1: pmin is device memory; 0: host memory */
+    uint64_t *hist;           /* host, GB_HIST_BINS entries, or NULL */
+    uint64_t *seg_hist;       /* host, seg_hist_rows * GB_HIST_BINS entries:
+                                 one histogram per segment of S even n, or NULL */
+    uint64_t  seg_hist_rows;
+    /* filled by the library */
+    uint64_t count;           /* even n examined */
+    uint64_t max_p;           /* largest p_min */
+    uint64_t argmax_n;        /* smallest n attaining max_p */
+    uint64_t checksum;        /* sum of (n/2) * p_min(n) modulo 2^64 */
+    uint64_t n_exhaustive;    /* n that no odd prime p <= P_max resolved */
+    uint64_t n_failed;        /* n without a partition within the budget */
+    uint64_t first_failed_n;  /* smallest such n, or 0 */
+    uint64_t n_segments;      /* segments (plain) or windows (batched) used */
+    double   device_ms;       /* device time of the call, from HIP events */
+    double   tile_ms;         /* device time of the sieve-and-search tile
+                                 launches alone (HIP events on the same
+                                 stream, around those launches) */
+    uint64_t tile_launches;   /* tile kernel launches in the call */
+} gb_result;
+
+/* One window of the batched form: the even n start, start+2, ...,
+ * start + 2*(len-1).  start is even and >= 4. */
+typedef struct gb_window {
+    uint64_t start;
+    uint64_t len;
+} gb_window;
+
+/* Per-window summary of the batched form (fields as in gb_result). */
+typedef struct gb_summary {
+    uint64_t count, max_p, argmax_n, checksum, n_exhaustive, n_failed,
+             first_failed_n;
+} gb_summary;
+
+/* Create a context on prm->device: builds the resident table of odd primes
+ * up to sqrt(max_hi) (plus per-prime reciprocals), the wheel pattern and the
+ * fast-path prime list, and keeps them in device memory until gb_destroy.
+ * prm may be NULL (all defaults).  On failure *ctx is NULL. */
+gb_status gb_create(gb_ctx **ctx, const gb_params *prm);
+void      gb_destroy(gb_ctx *ctx);
+
+/* The parameters in effect (defaults resolved). */
+gb_status gb_get_params(const gb_ctx *ctx, gb_params *out);
+
+/* Plain form: p_min for every even n in [max(lo,4), hi], one kernel launch
+ * per segment of S even n, in order, on `stream`; then the exhaustive phase
+ * and the summary reduction.  (Problem statement: section "Methods"; the
+ * segment loop: subsection "Correct segmentation".)  Returns GB_EUNRESOLVED
+ * when some n has no partition within the budget. */
+gb_status gb_verify_range(gb_ctx *ctx, uint64_t lo, uint64_t hi,
+                          gb_result *res, void *stream);
+
+/* Batched form of the same computation: all segments' tiles go to one
+ * persistent launch that pulls tiles from a device work queue, captured with
+ * the exhaustive phase and the reduction in one HIP graph, replayed on later
+ * calls of the same shape.  Same results as gb_verify_range, bit for bit. */
+gb_status gb_verify_range_batched(gb_ctx *ctx, uint64_t lo, uint64_t hi,
+                                  gb_result *res, void *stream);
+
+/* Batched windows: k windows of uneven length in one persistent graph
+ * launch.  pmin (nullable) is device memory of sum(len) uint16 entries,
+ * window j's n at offset sum_{i<j} len_i.  sums (nullable, host, k entries)
+ * receives each window's summary; hist (nullable, host, GB_HIST_BINS) the
+ * histogram over all windows.  Windows may overlap. */
+gb_status gb_verify_windows(gb_ctx *ctx, const gb_window *w, size_t k,
+                            uint16_t *pmin, gb_summary *sums, uint64_t *hist,
+                            void *stream);
+
+/* Single n (section "GPU Single-Number Checker", but returning the minimal
+ * p): one wavefront scans odd primes from 3 upward, 64 candidates at a time,
+ * testing q = n - p with deterministic Miller-Rabin (bases 2..37), and takes
+ * the lowest passing lane.  n must be even, 4 <= n <= 2^63.  *p receives
+ * p_min(n), or 0 with GB_EUNRESOLVED if none exists within the budget. */
+gb_status gb_verify_one(gb_ctx *ctx, uint64_t n, uint64_t *p, void *stream);
+
+/* Many single n in one launch (one wavefront per n).  n and p are arrays of
+ * k uint64 entries, both in device memory when on_device is 1, else both in
+ * host memory.  Entries with no partition within the budget get 0 and the
+ * call returns GB_EUNRESOLVED; odd or out-of-range n give GB_EINVAL. */
+gb_status gb_verify_many(gb_ctx *ctx, const uint64_t *n, uint64_t *p, size_t k,
+                         int on_device, void *stream);
+
+/* The sieve alone: bit i of the output (LSB-first uint32 words) is 1 iff the
+ * odd number w0 + 2i is prime, for 0 <= i < nbits, built by the same LDS tile
+ * sieve the range calls use (wheel pattern, then strided marking of the odd
+ * multiples of each sieving prime from max(p^2, w0)).  w0 is odd, w0 >= 1,
+ * w0 + 2*nbits <= max_hi; nbits is a multiple of 64; bits is device memory of
+ * nbits/32 words. */
+gb_status gb_sieve_window(gb_ctx *ctx, uint64_t w0, uint64_t nbits,
+                          uint32_t *bits, void *stream);
+
+/* The (n, p) pairs the last range or window call sent to the exhaustive
+ * phase (p = 0 for a failure), at most cap of them, into host arrays;
+ * *count receives the total number. */
+gb_status gb_exhaustive_list(gb_ctx *ctx, uint64_t *n, uint64_t *p, size_t cap,
+                             size_t *count);
+
+/* Autotuner: time the batched form over a sample of windows for every
+ * combination of the candidate tile sizes, workgroup sizes, P_max and wheel
+ * values, check that every combination gives bit-identical results, keep the
+ * fastest in the context and, when cache_path is not NULL, write it there as
+ * one JSON object.  best (nullable) receives the chosen parameters. */
+gb_status gb_autotune(gb_ctx *ctx, const gb_window *sample, size_t k,
+                      const char *cache_path, gb_params *best);
+
+const char *gb_status_str(gb_status st);
+const char *gb_last_error(const gb_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GOLDBACH_H */

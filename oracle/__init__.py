@@ -71,6 +71,7 @@ def lib():
         L.orc_verify_many.argtypes = [vp, vp, u64, u64, ip]
         L.orc_verify_many.restype = None
         L.orc_hist_bins.argtypes, L.orc_hist_bins.restype = [], u32
+        L.orc_odd_primality.argtypes, L.orc_odd_primality.restype = [u64, u64, vp], ip
         _lib = L
     return _lib
 
@@ -131,6 +132,14 @@ def verify_range(lo: int, hi: int, pmax: int = 8192, per_n_bits: int | None = 32
     if rc != 0:
         raise MemoryError("oracle allocation failed")
     return out, h, s.as_dict()
+
+
+def odd_primality(w0: int, count: int) -> np.ndarray:
+    """uint8 array: 1 where w0 + 2i (w0 odd) is prime, for 0 <= i < count."""
+    out = np.zeros(count, dtype=np.uint8)
+    if count and lib().orc_odd_primality(w0, count, out.ctypes.data) != 0:
+        raise MemoryError("oracle allocation failed")
+    return out
 
 
 def verify_one(n: int, limit: int = 0) -> int:

@@ -456,3 +456,18 @@ void orc_verify_many(const uint64_t *n, uint64_t *p, uint64_t count,
 }
 
 uint32_t orc_hist_bins(void) { return ORC_HIST_BINS; }
+
+/* Primality byte (1 = prime) of each odd number w0, w0+2, ..., w0+2(count-1)
+ * from the same plain byte sieve, for comparing with a sieved bitset.
+ * w0 odd, w0 >= 1.  Returns 0, or -1 on allocation failure. */
+int orc_odd_primality(uint64_t w0, uint64_t count, uint8_t *out)
+{
+    if (count == 0) return 0;
+    uint64_t whi = w0 + 2 * (count - 1);
+    uint64_t nbase;
+    uint32_t *base = odd_primes_upto(orc_isqrt(whi) + 1, &nbase);
+    if (!base) return -1;
+    sieve_window(out, w0, whi, base, nbase);
+    free(base);
+    return 0;
+}

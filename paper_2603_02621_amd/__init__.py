@@ -1,0 +1,201 @@
+"""MI355X-native segmented Goldbach verifier (GoldbachGPU, arXiv 2603.02621).
+
+Python face of the C ABI in ``include/goldbach.h``.  Every step of the
+computation runs in the HIP library ``libgoldbach.so``; PyTorch only provides
+device buffers and the current stream.  There is no CPU fallback: using the
+verifier without the built library raises.
+"""
+from __future__ import annotations
+
+import ctypes
+
+from ._binding import (HIST_BINS, MAX_N, GoldbachError, Params, Result, Summary, Window,
+                       lib)
+
+__all__ = ["Verifier", "GoldbachError", "HIST_BINS", "MAX_N"]
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        import torch
+        if torch.cuda.is_available():
+            return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+        return ctypes.c_void_p(0)
+    if isinstance(stream, int):
+        return ctypes.c_void_p(stream)
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+class Verifier:
+    """One library context on one GPU (resident prime table, buffers, graphs)."""
+
+    def __init__(self, device: int = 0, **params):
+        self._lib = lib()
+        p = Params()
+        p.device = device
+        for k, v in params.items():
+            if not hasattr(p, k):
+                raise TypeError(f"unknown parameter {k}")
+            setattr(p, k, int(v))
+        h = ctypes.c_void_p()
+        st = self._lib.gb_create(ctypes.byref(h), ctypes.byref(p))
+        if st != 0:
+            raise GoldbachError(st, "gb_create failed")
+        self._h = h
+
+    # -- plumbing -----------------------------------------------------------
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.gb_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def _check(self, st, allow=()):
+        if st != 0 and st not in allow:
+            raise GoldbachError(st, self._lib.gb_last_error(self._h).decode())
+        return st
+
+    @property
+    def params(self) -> dict:
+        p = Params()
+        self._check(self._lib.gb_get_params(self._h, ctypes.byref(p)))
+        return p.as_dict()
+
+    @property
+    def last_error(self) -> str:
+        return self._lib.gb_last_error(self._h).decode()
+
+    # -- calls ----------------------------------------------------------------
+    def verify_range(self, lo: int, hi: int, pmin=None, hist=True, seg_hist_rows=0,
+                     batched=False, stream=None, allow_unresolved=False):
+        """Minimal p for every even n in [max(lo,4), hi].
+
+        ``pmin``: None, or a torch tensor (uint16/int32 on the GPU, or a numpy
+        array on the host) with one entry per even n.  Returns a dict with the
+        summaries, ``hist`` (numpy uint64), ``seg_hist`` and ``status``.
+        """
+        import numpy as np
+        r = Result()
+        keep = []
+        if pmin is not None:
+            r.pmin, r.pmin_bits, r.pmin_on_device = _buffer(pmin)
+            keep.append(pmin)
+        h = np.zeros(HIST_BINS, dtype=np.uint64) if hist else None
+        if h is not None:
+            r.hist = h.ctypes.data
+        sh = None
+        if seg_hist_rows:
+            sh = np.zeros((seg_hist_rows, HIST_BINS), dtype=np.uint64)
+            r.seg_hist = sh.ctypes.data
+            r.seg_hist_rows = seg_hist_rows
+        fn = self._lib.gb_verify_range_batched if batched else self._lib.gb_verify_range
+        st = fn(self._h, lo, hi, ctypes.byref(r), _stream_ptr(stream))
+        self._check(st, allow=(5,) if allow_unresolved else ())
+        out = r.summary()
+        out.update(status=st, hist=h, seg_hist=sh, n_segments=int(r.n_segments),
+                   device_ms=float(r.device_ms), tile_ms=float(r.tile_ms),
+                   tile_launches=int(r.tile_launches))
+        return out
+
+    def verify_windows(self, windows, pmin=None, sums=True, hist=True, stream=None,
+                       allow_unresolved=False):
+        """Batched windows: ``windows`` is a sequence of (start, len)."""
+        import numpy as np
+        k = len(windows)
+        W = (Window * max(k, 1))()
+        for i, (s, ln) in enumerate(windows):
+            W[i].start, W[i].len = int(s), int(ln)
+        S = (Summary * max(k, 1))() if sums else None
+        h = np.zeros(HIST_BINS, dtype=np.uint64) if hist else None
+        ptr = None
+        if pmin is not None:
+            ptr, bits, on_dev = _buffer(pmin)
+            if bits != 16 or not on_dev:
+                raise ValueError("windows output must be a uint16 tensor on the GPU")
+        st = self._lib.gb_verify_windows(self._h, W, k, ptr, S,
+                                         h.ctypes.data if h is not None else None,
+                                         _stream_ptr(stream))
+        self._check(st, allow=(5,) if allow_unresolved else ())
+        return {"status": st, "hist": h,
+                "sums": [S[i].as_dict() for i in range(k)] if S is not None else None}
+
+    def verify_one(self, n: int, stream=None, allow_unresolved=False) -> int:
+        p = ctypes.c_uint64()
+        st = self._lib.gb_verify_one(self._h, n, ctypes.byref(p), _stream_ptr(stream))
+        self._check(st, allow=(5,) if allow_unresolved else ())
+        return int(p.value)
+
+    def verify_many(self, ns, stream=None, allow_unresolved=False):
+        """Minimal p for each even n of a numpy uint64 array (host) or a
+        torch int64/uint64 tensor on the GPU (result has the same kind)."""
+        import numpy as np
+        if hasattr(ns, "data_ptr"):
+            import torch
+            out = torch.empty_like(ns)
+            st = self._lib.gb_verify_many(self._h, ns.data_ptr(), out.data_ptr(), ns.numel(), 1,
+                                          _stream_ptr(stream))
+        else:
+            arr = np.ascontiguousarray(np.asarray(ns, dtype=np.uint64))
+            out = np.zeros_like(arr)
+            st = self._lib.gb_verify_many(self._h, arr.ctypes.data, out.ctypes.data, arr.size, 0,
+                                          _stream_ptr(stream))
+        self._check(st, allow=(5,) if allow_unresolved else ())
+        return out
+
+    def sieve_window(self, w0: int, nbits: int, out, stream=None):
+        """Sieve bits of the odd numbers w0, w0+2, ... into ``out`` (a torch
+        int32 tensor of nbits/32 words on the GPU)."""
+        self._check(self._lib.gb_sieve_window(self._h, w0, nbits, out.data_ptr(),
+                                              _stream_ptr(stream)))
+        return out
+
+    def exhaustive_list(self):
+        import numpy as np
+        cnt = ctypes.c_size_t()
+        self._check(self._lib.gb_exhaustive_list(self._h, None, None, 0, ctypes.byref(cnt)))
+        n = np.zeros(cnt.value, dtype=np.uint64)
+        p = np.zeros(cnt.value, dtype=np.uint64)
+        if cnt.value:
+            self._check(self._lib.gb_exhaustive_list(self._h, n.ctypes.data, p.ctypes.data,
+                                                      cnt.value, ctypes.byref(cnt)))
+        return n, p
+
+    def autotune(self, windows, cache_path=None):
+        k = len(windows)
+        W = (Window * max(k, 1))()
+        for i, (s, ln) in enumerate(windows):
+            W[i].start, W[i].len = int(s), int(ln)
+        best = Params()
+        self._check(self._lib.gb_autotune(self._h, W, k,
+                                          cache_path.encode() if cache_path else None,
+                                          ctypes.byref(best)))
+        return best.as_dict()
+
+
+def _buffer(x):
+    """(pointer, bits, on_device) of a torch tensor or numpy array."""
+    import numpy as np
+    if hasattr(x, "data_ptr"):
+        import torch
+        bits = {torch.uint16: 16, torch.int16: 16, torch.int32: 32, torch.uint32: 32}.get(x.dtype)
+        if bits is None or not x.is_contiguous():
+            raise ValueError("pmin tensor must be contiguous 16- or 32-bit integers")
+        return x.data_ptr(), bits, 1 if x.is_cuda else 0
+    a = x
+    if not isinstance(a, np.ndarray) or not a.flags.c_contiguous:
+        raise ValueError("pmin array must be a contiguous numpy array")
+    bits = {np.dtype(np.uint16): 16, np.dtype(np.uint32): 32}.get(a.dtype)
+    if bits is None:
+        raise ValueError("pmin array must be uint16 or uint32")
+    return a.ctypes.data, bits, 0

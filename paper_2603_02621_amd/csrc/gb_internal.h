@@ -1,0 +1,104 @@
+// gb_internal.h -- device-side data layout shared by the kernels and the
+// host runtime of the Goldbach verifier (not part of the public ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define GB_HIST_BINS_I 6543u
+
+// One window of consecutive even n.  A range call uses one window per
+// segment; the batched forms put many windows in one table.
+struct GbWindow {
+    uint64_t first_n;    // even, >= 4
+    uint64_t count;      // even n in the window
+    uint64_t tile_base;  // global index of the window's first tile
+    uint64_t out_off;    // index of first_n in the per-n output
+    uint32_t slot;       // summary slot of the window
+    uint32_t np_sieve;   // odd primes p of the table with p*p <= window top
+};
+
+// Per-slot summary accumulators, combined with 64-bit atomics (sums, max,
+// min), so the result does not depend on the order tiles finish in.
+struct GbSlot {
+    unsigned long long count, max_p, argmax_n, checksum, n_exhaustive,
+        n_failed, first_failed_n, pad;
+};
+
+// Per-tile record for the argmax pass: the tile's largest p_min and the
+// smallest n in the tile that has it.
+struct GbTileRec {
+    unsigned long long argmax_n;
+    uint32_t max_p;
+    uint32_t slot;
+};
+
+// One n sent to the exhaustive phase (or one single-n query).
+struct GbExh {
+    unsigned long long n;
+    unsigned long long out_index;  // index into the per-n output, or ~0
+    uint32_t slot;
+    uint32_t start_k;              // first odd-prime index to try
+    unsigned long long p;          // result: p_min, or 0 for a failure
+};
+
+struct GbTileArgs {
+    const GbWindow *win;
+    uint32_t nwin;
+    uint32_t tile_n;        // T, even n per tile (multiple of 64)
+    uint64_t ntiles;        // tiles in the whole table (persistent mode)
+    uint64_t tile0;         // first tile of this launch (non-persistent)
+    uint32_t halo_bits;     // HB: bits below the tile's first n (multiple of 64)
+    uint32_t np_search;     // odd primes <= P_max
+    const uint32_t *primes; // odd primes 3, 5, 7, ... ascending
+    const unsigned long long *magic;  // floor((2^64-1)/p) per prime
+    uint32_t k_first;       // first prime index above the wheel
+    uint32_t k_wg_end;      // primes [k_first, k_wg_end): whole-workgroup marking
+    uint32_t k_wave_end;    // primes [k_wg_end, k_wave_end): one wave per prime
+    const uint32_t *wheel;  // wheel pattern bits, period wheel_len, padded by 64
+    uint32_t wheel_len;     // product of the odd wheel primes
+    uint32_t wheel_max;     // largest wheel prime
+    void *pmin;             // per-n output (nullable)
+    GbSlot *slots;
+    unsigned long long *hist;  // rows of GB_HIST_BINS_I
+    uint32_t hist_per_slot;    // 1: row = slot, 0: row 0
+    GbTileRec *recs;           // one per global tile
+    GbExh *list;
+    unsigned long long *list_count;
+    unsigned long long list_cap;
+    unsigned long long *queue; // persistent work counter
+    uint32_t *sieve_out;       // sieve-only mode: bitset dump
+};
+
+struct GbMrArgs {
+    GbExh *list;
+    const unsigned long long *list_count;
+    unsigned long long list_cap;
+    const uint32_t *primes;
+    uint64_t ntab;
+    unsigned long long budget;   // 0 = n/2
+    void *pmin;                  // per-n output of the range call (nullable)
+    uint32_t pmin_bits;
+    GbSlot *slots;               // nullable (queries)
+    unsigned long long *hist;
+    uint32_t hist_per_slot;
+};
+
+// Kernel launchers (gb_kernels.hip).
+hipError_t gb_launch_tiles(const GbTileArgs &a, uint32_t grid, uint32_t threads,
+                           size_t lds_bytes, int pmin_bits, bool persistent,
+                           bool sieve_only, hipStream_t st);
+hipError_t gb_prepare_tiles(uint32_t threads, size_t lds_bytes);
+hipError_t gb_tile_occupancy(uint32_t threads, size_t lds_bytes, int *blocks_per_cu);
+size_t gb_tile_lds_bytes(uint32_t tile_n, uint32_t halo_bits, uint32_t np_search,
+                         uint32_t threads);
+hipError_t gb_launch_mr(const GbMrArgs &a, uint32_t grid, hipStream_t st);
+hipError_t gb_launch_argmax(GbSlot *slots, const GbTileRec *recs, uint64_t nrecs,
+                            const GbExh *list, const unsigned long long *list_count,
+                            unsigned long long list_cap, hipStream_t st);
+hipError_t gb_launch_init(GbSlot *slots, uint64_t nslots, unsigned long long *hist,
+                          uint64_t hist_words, unsigned long long *counters,
+                          uint32_t ncounters, hipStream_t st);
+hipError_t gb_launch_finish_queries(const GbExh *list, uint64_t k,
+                                    unsigned long long *p_out, hipStream_t st);
+hipError_t gb_launch_make_queries(GbExh *list, const unsigned long long *n, uint64_t k,
+                                  unsigned long long *list_count, hipStream_t st);

@@ -1,0 +1,696 @@
+// gb_kernels.hip -- HIP kernels (gfx950, wave64) of the segmented Goldbach
+// verifier.
+//
+// k_tile: one workgroup owns one tile of T consecutive even n, n = N0 + 2j.
+// It sieves the odd numbers w0 + 2i, w0 = N0 + 1 - 2*HB, 0 <= i < T + HB, into
+// an LDS bitset (bit = 1 for a prime), then runs the paper's inverted loop
+// (section "Segmented Double-Sieve Verifier", subsection "Correct
+// segmentation": iterate over candidate primes p and mark the n for which
+// n - p is prime) on it: for a fixed p the bits of q = n - p for the 64 even n
+// of one block n0, n0+2, ..., n0+126 are 64 consecutive bits of the window,
+// starting at bit j0 + HB - (p+1)/2, so one 64-bit funnel extract ANDed with
+// the block's mask of still-unresolved n probes 64 n at once.  Primes are
+// taken in ascending order, so the first p that hits an n is p_min(n).
+// The halo HB >= (P_max+1)/2 keeps every q = n - p with p <= P_max inside
+// the window, which is the paper's three-way primality oracle (small-prime
+// table, segment bitset, Miller-Rabin) collapsed into one lookup.
+// n that no p <= P_max resolves go to a device list for k_mr, the
+// exhaustive phase (the paper's Phase 2; on the GPU here).
+//
+// k_mr: one wavefront per listed n.  Lane l takes the l-th next candidate
+// prime p, screens q = n - p with a base-2 strong probable-prime test in
+// Montgomery arithmetic, and the lowest passing lane (ballot + first set bit)
+// is confirmed with the other eleven bases of the deterministic 64-bit test
+// (bases 2..37), one base per lane.
+#include "gb_internal.h"
+
+namespace {
+
+__device__ __forceinline__ unsigned long long fastmod64(unsigned long long x, uint32_t p,
+                                                        unsigned long long magic)
+{
+    // magic = floor((2^64-1)/p) underestimates 2^64/p by less than 1, so the
+    // quotient estimate is floor(x/p) or one less: one correction step.
+    unsigned long long q = __umul64hi(x, magic);
+    unsigned long long r = x - q * (unsigned long long)p;
+    return r >= p ? r - p : r;
+}
+
+// Smallest bit index t >= 0 such that w0 + 2t is an odd multiple of p and at
+// least p*p (the first composite the prime p strikes in the window).
+__device__ __forceinline__ unsigned long long first_index(long long w0, uint32_t p,
+                                                          unsigned long long magic)
+{
+    unsigned long long pp = (unsigned long long)p * p;
+    if (w0 <= 0 || (unsigned long long)w0 <= pp)
+        return (pp - (unsigned long long)w0) >> 1;
+    unsigned long long r = fastmod64((unsigned long long)w0, p, magic);
+    uint32_t d = r ? p - (uint32_t)r : 0u;  // w0 + d is the next multiple
+    return (d & 1u) ? ((unsigned long long)d + p) >> 1 : (unsigned long long)(d >> 1);
+}
+
+// Sum of the positions of the set bits of the 64-bit word (hi:lo).
+__device__ __forceinline__ uint32_t bitpos_sum(uint32_t lo, uint32_t hi)
+{
+    uint32_t s = __popc(hi) << 5;
+    s += (__popc(lo & 0xAAAAAAAAu) + __popc(hi & 0xAAAAAAAAu));
+    s += (__popc(lo & 0xCCCCCCCCu) + __popc(hi & 0xCCCCCCCCu)) << 1;
+    s += (__popc(lo & 0xF0F0F0F0u) + __popc(hi & 0xF0F0F0F0u)) << 2;
+    s += (__popc(lo & 0xFF00FF00u) + __popc(hi & 0xFF00FF00u)) << 3;
+    s += (__popc(lo & 0xFFFF0000u) + __popc(hi & 0xFFFF0000u)) << 4;
+    return s;
+}
+
+__device__ __forceinline__ bool is_wheel_prime(long long v, uint32_t wmax)
+{
+    return v <= (long long)wmax &&
+           (v == 3 || v == 5 || v == 7 || v == 11 || v == 13 || v == 17 || v == 19);
+}
+
+template <int PB>
+__device__ __forceinline__ void store_p(void *out, unsigned long long idx, uint32_t p)
+{
+    if constexpr (PB == 16) static_cast<uint16_t *>(out)[idx] = (uint16_t)p;
+    if constexpr (PB == 32) static_cast<uint32_t *>(out)[idx] = p;
+}
+
+__device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v)
+{
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+__device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long v)
+{
+    for (int o = 32; o > 0; o >>= 1) {
+        unsigned long long w = __shfl_xor(v, o, 64);
+        v = w > v ? w : v;
+    }
+    return v;
+}
+
+// LDS carve-up of one tile workgroup (all offsets in 32-bit words).
+struct TileLds {
+    uint32_t *bits;      // (T + HB)/32 words
+    uint16_t *sp;        // odd primes <= P_max
+    uint32_t *lhist;     // per-prime hit counts of this tile
+    unsigned long long *red;  // 3 * waves
+};
+
+__device__ __forceinline__ TileLds carve(uint32_t *smem, uint32_t tile_n, uint32_t hb,
+                                         uint32_t nps, int nt)
+{
+    TileLds L;
+    uint32_t o = 0;
+    L.bits = smem + o;
+    o += (tile_n + hb) / 32;
+    L.sp = reinterpret_cast<uint16_t *>(smem + o);
+    o += (nps + 1) / 2;
+    L.lhist = smem + o;
+    o += nps;
+    o = (o + 1) & ~1u;
+    L.red = reinterpret_cast<unsigned long long *>(smem + o);
+    (void)nt;
+    return L;
+}
+
+template <int NT, int PB, bool SIEVE_ONLY>
+__device__ void process_tile(const GbTileArgs &a, unsigned long long g, const TileLds &L)
+{
+    const uint32_t tid = threadIdx.x;
+    const uint32_t lane = tid & 63u, wave = tid >> 6;
+    constexpr uint32_t NWAVES = NT / 64;
+
+    // ---- locate the tile's window ----------------------------------------
+    uint32_t wi = 0;
+    if (a.nwin > 1) {
+        uint32_t lo = 0, hi = a.nwin - 1;
+        while (lo < hi) {
+            uint32_t mid = (lo + hi + 1) >> 1;
+            if (a.win[mid].tile_base <= g) lo = mid; else hi = mid - 1;
+        }
+        wi = lo;
+    }
+    const GbWindow W = a.win[wi];
+    const unsigned long long t = g - W.tile_base;
+    const unsigned long long N0 = W.first_n + 2ull * a.tile_n * t;
+    const unsigned long long rem = W.count - (unsigned long long)a.tile_n * t;
+    const uint32_t cnt = rem < a.tile_n ? (uint32_t)rem : a.tile_n;
+    const uint32_t nblk = (cnt + 63u) >> 6;
+    const uint32_t HB = a.halo_bits;
+    const uint32_t nbits = nblk * 64u + HB;
+    const uint32_t nw32 = nbits >> 5;
+    const long long w0 = (long long)(N0 + 1ull - 2ull * HB);
+
+    // ---- fast-path prime list and per-tile histogram ----------------------
+    if (!SIEVE_ONLY) {
+        for (uint32_t i = tid; i < a.np_search; i += NT) {
+            L.sp[i] = (uint16_t)a.primes[i];
+            L.lhist[i] = 0;
+        }
+    }
+
+    // ---- wheel pre-pattern: clears the odd multiples of 3..wheel_max ------
+    // Pattern bit g is 1 iff 2g+1 is coprime to every wheel prime; tile bit i
+    // (value w0 + 2i) has pattern phase ((w0-1)/2 + i) mod wheel_len.
+    {
+        const uint32_t Lw = a.wheel_len;
+        const uint32_t g0 = (uint32_t)(((N0 >> 1) % Lw + Lw - (HB % Lw)) % Lw);
+        uint32_t ph = (g0 + 32u * tid) % Lw;
+        const uint32_t step = (32u * NT) % Lw;
+        for (uint32_t i = tid; i < nw32; i += NT) {
+            const uint32_t lo = a.wheel[ph >> 5], hi = a.wheel[(ph >> 5) + 1];
+            uint32_t v = __builtin_amdgcn_alignbit(hi, lo, ph & 31u);
+            const long long vfirst = w0 + 64ll * i;
+            if (vfirst <= (long long)a.wheel_max) {
+                // the window reaches the wheel primes themselves, or 1 and below
+                for (uint32_t b = 0; b < 32; ++b) {
+                    const long long val = vfirst + 2ll * b;
+                    if (val < 2) v &= ~(1u << b);
+                    else if (is_wheel_prime(val, a.wheel_max)) v |= (1u << b);
+                }
+            }
+            L.bits[i] = v;
+            ph += step;
+            if (ph >= Lw) ph -= Lw;
+        }
+    }
+    __syncthreads();
+
+    // ---- strided marking of the odd multiples of each sieving prime -------
+    const uint32_t np = W.np_sieve;
+    {
+        // primes with many hits per tile: the whole workgroup strides over one prime
+        const uint32_t kend = min(a.k_wg_end, np);
+        for (uint32_t k = a.k_first; k < kend; ++k) {
+            const uint32_t p = a.primes[k];
+            const unsigned long long t0 = first_index(w0, p, a.magic[k]);
+            if (t0 >= nbits) continue;
+            for (uint32_t idx = (uint32_t)t0 + tid * p; idx < nbits; idx += NT * p)
+                atomicAnd(&L.bits[idx >> 5], ~(1u << (idx & 31u)));
+        }
+        // medium primes: one wavefront per prime, lanes stride by 64p
+        const uint32_t kbeg2 = max(a.k_wg_end, a.k_first);
+        const uint32_t kend2 = min(a.k_wave_end, np);
+        for (uint32_t k = kbeg2 + wave; k < kend2; k += NWAVES) {
+            const uint32_t p = a.primes[k];
+            const unsigned long long t0 = first_index(w0, p, a.magic[k]);
+            if (t0 >= nbits) continue;
+            for (uint32_t idx = (uint32_t)t0 + lane * p; idx < nbits; idx += 64u * p)
+                atomicAnd(&L.bits[idx >> 5], ~(1u << (idx & 31u)));
+        }
+        // large primes: one lane per prime, a few hits each
+        const uint32_t kbeg3 = max(a.k_wave_end, a.k_first);
+        for (uint32_t k = kbeg3 + tid; k < np; k += NT) {
+            const uint32_t p = a.primes[k];
+            const unsigned long long t0 = first_index(w0, p, a.magic[k]);
+            if (t0 >= nbits) continue;
+            for (uint32_t idx = (uint32_t)t0; idx < nbits; idx += p)
+                atomicAnd(&L.bits[idx >> 5], ~(1u << (idx & 31u)));
+        }
+    }
+    __syncthreads();
+
+    if (SIEVE_ONLY) {
+        // bitset dump: tile t owns output bits [T*t, T*t + cnt)
+        const unsigned long long obase = (unsigned long long)a.tile_n * t / 32;
+        for (uint32_t i = tid; i < cnt / 32; i += NT) a.sieve_out[obase + i] = L.bits[i];
+        __syncthreads();
+        return;
+    }
+
+    // ---- inverted-loop search, 64 even n per lane-block --------------------
+    const uint32_t slot = W.slot;
+    const uint32_t hrow = a.hist_per_slot ? slot : 0u;
+    unsigned long long *hist = a.hist + (unsigned long long)hrow * GB_HIST_BINS_I;
+    const unsigned long long half0 = N0 >> 1;
+    const unsigned long long outb = W.out_off + (unsigned long long)a.tile_n * t;
+    const uint32_t nps = a.np_search;
+
+    uint32_t maxp = 0, amax = 0;       // lane's largest p_min and its n index
+    unsigned long long cs = 0;         // lane's checksum part
+    uint32_t nexh = 0;                 // n left to the exhaustive phase
+
+    uint32_t b = tid, k = 0, Ulo = 0, Uhi = 0, Ab = 0, Bb = 0;
+    auto start_block = [&](uint32_t bb) {
+        const uint32_t nv = min(64u, cnt - 64u * bb);
+        Ulo = nv >= 32 ? ~0u : ((1u << nv) - 1u);
+        Uhi = nv >= 64 ? ~0u : (nv > 32 ? ((1u << (nv - 32)) - 1u) : 0u);
+        k = 0; Ab = 0; Bb = 0;
+        if (N0 == 4 && bb == 0) {  // n = 4 = 2 + 2, the one even p_min
+            Ulo &= ~1u;
+            Ab = 2;
+            atomicAdd(&hist[0], 1ull);
+            if (maxp < 2) { maxp = 2; amax = 0; }
+            if (a.pmin) store_p<PB>(a.pmin, outb, 2u);
+        }
+    };
+    if (b < nblk) start_block(b);
+    while (b < nblk) {
+        if (k < nps) {
+            const uint32_t p = L.sp[k];
+            const uint32_t s = 64u * b + HB - ((p + 1u) >> 1);
+            const uint32_t w = s >> 5, sh = s & 31u;
+            const uint32_t d0 = L.bits[w], d1 = L.bits[w + 1], d2 = L.bits[w + 2];
+            const uint32_t hlo = __builtin_amdgcn_alignbit(d1, d0, sh) & Ulo;
+            const uint32_t hhi = __builtin_amdgcn_alignbit(d2, d1, sh) & Uhi;
+            if (hlo | hhi) {
+                const uint32_t pc = __popc(hlo) + __popc(hhi);
+                Ab += p * pc;
+                Bb += p * bitpos_sum(hlo, hhi);
+                atomicAdd(&L.lhist[k], pc);
+                if (p > maxp) {
+                    maxp = p;
+                    amax = 64u * b + (hlo ? (uint32_t)__builtin_ctz(hlo)
+                                          : 32u + (uint32_t)__builtin_ctz(hhi));
+                }
+                if constexpr (PB != 0) {
+                    if (a.pmin) {
+                        unsigned long long hb = ((unsigned long long)hhi << 32) | hlo;
+                        const unsigned long long ob = outb + 64ull * b;
+                        while (hb) {
+                            store_p<PB>(a.pmin, ob + (unsigned long long)__builtin_ctzll(hb), p);
+                            hb &= hb - 1ull;
+                        }
+                    }
+                }
+                Ulo &= ~hlo;
+                Uhi &= ~hhi;
+            }
+            ++k;
+        }
+        if ((Ulo | Uhi) == 0u || k >= nps) {
+            cs += (half0 + 64ull * b) * Ab + Bb;
+            if (Ulo | Uhi) {
+                unsigned long long u = ((unsigned long long)Uhi << 32) | Ulo;
+                nexh += __popcll(u);
+                while (u) {
+                    const uint32_t j = (uint32_t)__builtin_ctzll(u);
+                    u &= u - 1ull;
+                    const unsigned long long e = atomicAdd(a.list_count, 1ull);
+                    if (e < a.list_cap) {
+                        GbExh x;
+                        x.n = N0 + 2ull * (64ull * b + j);
+                        x.out_index = outb + 64ull * b + j;
+                        x.slot = slot;
+                        x.start_k = nps;
+                        x.p = 0;
+                        a.list[e] = x;
+                    }
+                }
+            }
+            b += NT;
+            if (b < nblk) start_block(b);
+        }
+    }
+
+    // ---- tile summary ------------------------------------------------------
+    unsigned long long key = ((unsigned long long)maxp << 32) | (0xFFFFFFFFu - amax);
+    unsigned long long csw = wave_sum_u64(cs);
+    unsigned long long nxw = wave_sum_u64(nexh);
+    key = wave_max_u64(key);
+    if (lane == 0) {
+        L.red[wave] = csw;
+        L.red[NWAVES + wave] = nxw;
+        L.red[2 * NWAVES + wave] = key;
+    }
+    __syncthreads();
+    for (uint32_t i = tid; i < nps; i += NT) {
+        const uint32_t c = L.lhist[i];
+        if (c) atomicAdd(&hist[i + 1], (unsigned long long)c);
+    }
+    if (tid == 0) {
+        unsigned long long c2 = 0, x2 = 0, k2 = 0;
+        for (uint32_t w2 = 0; w2 < NWAVES; ++w2) {
+            c2 += L.red[w2];
+            x2 += L.red[NWAVES + w2];
+            k2 = L.red[2 * NWAVES + w2] > k2 ? L.red[2 * NWAVES + w2] : k2;
+        }
+        const uint32_t mp = (uint32_t)(k2 >> 32);
+        const uint32_t am = 0xFFFFFFFFu - (uint32_t)(k2 & 0xFFFFFFFFu);
+        GbSlot *S = a.slots + slot;
+        atomicAdd(&S->count, (unsigned long long)cnt);
+        atomicAdd(&S->checksum, c2);
+        if (x2) atomicAdd(&S->n_exhaustive, x2);
+        if (mp) atomicMax(&S->max_p, (unsigned long long)mp);
+        GbTileRec r;
+        r.argmax_n = mp ? N0 + 2ull * am : 0ull;
+        r.max_p = mp;
+        r.slot = slot;
+        a.recs[g] = r;
+    }
+    __syncthreads();
+}
+
+template <int NT, int PB, bool PERS, bool SIEVE_ONLY>
+__global__ __launch_bounds__(NT) void k_tile(GbTileArgs a)
+{
+    extern __shared__ uint32_t smem[];
+    __shared__ unsigned long long s_tile;
+    const TileLds L = carve(smem, a.tile_n, a.halo_bits, a.np_search, NT);
+    if constexpr (PERS) {
+        for (;;) {
+            if (threadIdx.x == 0) s_tile = atomicAdd(a.queue, 1ull);
+            __syncthreads();
+            const unsigned long long g = s_tile;
+            if (g >= a.ntiles) break;
+            process_tile<NT, PB, SIEVE_ONLY>(a, g, L);
+        }
+    } else {
+        process_tile<NT, PB, SIEVE_ONLY>(a, a.tile0 + blockIdx.x, L);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// 64-bit Montgomery arithmetic (Montgomery 1985) for the Miller-Rabin test.
+// Residues are kept as x*R mod m with R = 2^64, m odd.
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ unsigned long long mont_inv(unsigned long long m)
+{
+    // Newton iteration for m^-1 mod 2^64: m*m = 1 mod 8 gives 3 correct bits
+    unsigned long long x = m;
+    for (int i = 0; i < 5; ++i) x *= 2ull - m * x;
+    return 0ull - x;   // -m^-1
+}
+
+__device__ __forceinline__ unsigned long long mont_mul(unsigned long long a, unsigned long long b,
+                                                       unsigned long long m, unsigned long long ni)
+{
+    const unsigned long long lo = a * b, hi = __umul64hi(a, b);
+    const unsigned long long u = lo * ni;
+    const unsigned long long mh = __umul64hi(u, m);
+    // lo + u*m = 0 mod 2^64 and carries out exactly when lo != 0
+    const unsigned long long t = hi + mh;
+    const bool c1 = t < hi;
+    const unsigned long long t2 = t + (lo != 0ull);
+    const bool c2 = t2 < t;
+    return (c1 || c2 || t2 >= m) ? t2 - m : t2;
+}
+
+__device__ __forceinline__ unsigned long long add_mod(unsigned long long x, unsigned long long y,
+                                                      unsigned long long m)
+{
+    const unsigned long long s = x + y;
+    return (s < x || s >= m) ? s - m : s;
+}
+
+// Strong probable-prime test of odd m > 37 to the small base a.
+__device__ bool sprp(unsigned long long m, uint32_t a)
+{
+    const unsigned long long ni = mont_inv(m);
+    const unsigned long long one = (0ull - m) % m;        // R mod m
+    const unsigned long long mone = m - one;              // -1
+    unsigned long long ar = 0;                            // a*R mod m
+    for (int bit = 5; bit >= 0; --bit) {
+        ar = add_mod(ar, ar, m);
+        if ((a >> bit) & 1u) ar = add_mod(ar, one, m);
+    }
+    unsigned long long d = m - 1ull;
+    const int s = __builtin_ctzll(d);
+    d >>= s;
+    unsigned long long x = one;
+    for (int bit = 63 - __builtin_clzll(d); bit >= 0; --bit) {
+        x = mont_mul(x, x, m, ni);
+        if ((d >> bit) & 1ull) x = (a == 2u) ? add_mod(x, x, m) : mont_mul(x, ar, m, ni);
+    }
+    if (x == one || x == mone) return true;
+    for (int r = 1; r < s; ++r) {
+        x = mont_mul(x, x, m, ni);
+        if (x == mone) return true;
+        if (x == one) return false;
+    }
+    return false;
+}
+
+// Odd primes up to 37 as a bit mask over (v-1)/2.
+__device__ __forceinline__ bool small_odd_prime(unsigned long long v)
+{
+    // 3,5,7,11,13,17,19,23,29,31,37 -> bits 1,2,3,5,6,8,9,11,14,15,18
+    const uint32_t mask = (1u << 1) | (1u << 2) | (1u << 3) | (1u << 5) | (1u << 6) | (1u << 8) |
+                          (1u << 9) | (1u << 11) | (1u << 14) | (1u << 15) | (1u << 18);
+    return (mask >> ((uint32_t)(v - 1) >> 1)) & 1u;
+}
+
+// Base-2 screen of an odd v >= 3: exact for v <= 37, a strong base-2 test above.
+__device__ __forceinline__ bool screen2(unsigned long long v)
+{
+    return v <= 37ull ? small_odd_prime(v) : sprp(v, 2u);
+}
+
+__constant__ uint32_t MR_BASES[12] = {2, 3, 5, 7, 11, 13, 17, 19, 23, 29, 31, 37};
+
+__global__ __launch_bounds__(256) void k_mr(GbMrArgs a)
+{
+    const uint32_t lane = threadIdx.x & 63u;
+    const unsigned long long gw = (blockIdx.x * 256ull + threadIdx.x) >> 6;
+    const unsigned long long nw = (gridDim.x * 256ull) >> 6;
+    unsigned long long cnt = *a.list_count;
+    if (cnt > a.list_cap) cnt = a.list_cap;
+    const uint32_t ptop = a.primes[a.ntab - 1];
+    for (unsigned long long e = gw; e < cnt; e += nw) {
+        const GbExh E = a.list[e];
+        const unsigned long long n = E.n;
+        unsigned long long found = 0, kfound = ~0ull;
+        if (n == 4ull) {
+            found = 2;
+        } else {
+            unsigned long long bound = n >> 1;
+            if (a.budget && a.budget < bound) bound = a.budget;
+            for (unsigned long long kb = E.start_k;; kb += 64ull) {
+                const unsigned long long k = kb + lane;
+                const bool in_tab = k < a.ntab;
+                const unsigned long long p =
+                    in_tab ? (unsigned long long)a.primes[k] : (unsigned long long)ptop + 2ull * (k - a.ntab + 1ull);
+                const bool valid = p <= bound;
+                const unsigned long long q = n - p;
+                const bool pass = valid && screen2(q) && (in_tab || screen2(p));
+                unsigned long long m = __ballot(pass);
+                while (m) {
+                    const int c = __builtin_ctzll(m);
+                    const unsigned long long qc = __shfl(q, c, 64);
+                    const unsigned long long pc = __shfl(p, c, 64);
+                    const bool tabc = (kb + (unsigned long long)c) < a.ntab;
+                    bool ok = true;
+                    if (lane < 11u) {
+                        if (qc > 37ull) ok = sprp(qc, MR_BASES[lane + 1]);
+                        if (ok && !tabc && pc > 37ull) ok = sprp(pc, MR_BASES[lane + 1]);
+                    }
+                    if (__ballot(!ok) == 0ull) {
+                        found = pc;
+                        kfound = kb + (unsigned long long)c;
+                        break;
+                    }
+                    m &= m - 1ull;
+                }
+                if (found) break;
+                if (__ballot(valid) == 0ull) break;  // every candidate is past the bound
+            }
+        }
+        if (lane == 0) {
+            a.list[e].p = found;
+            if (a.pmin && E.out_index != ~0ull) {
+                if (a.pmin_bits == 16)
+                    static_cast<uint16_t *>(a.pmin)[E.out_index] = (uint16_t)(found < 65536ull ? found : 0ull);
+                else
+                    static_cast<uint32_t *>(a.pmin)[E.out_index] = (uint32_t)(found < 4294967296ull ? found : 0ull);
+            }
+            if (a.slots) {
+                GbSlot *S = a.slots + E.slot;
+                unsigned long long *hist = a.hist + (a.hist_per_slot ? (unsigned long long)E.slot : 0ull) * GB_HIST_BINS_I;
+                if (found) {
+                    const unsigned long long bin =
+                        found == 2ull ? 0ull : (found < 65536ull ? kfound + 1ull : GB_HIST_BINS_I - 1ull);
+                    atomicAdd(&hist[bin], 1ull);
+                    atomicAdd(&S->checksum, (n >> 1) * found);
+                    atomicMax(&S->max_p, found);
+                } else {
+                    atomicAdd(&S->n_failed, 1ull);
+                    atomicMin(&S->first_failed_n, n);
+                }
+            }
+        }
+    }
+}
+
+__global__ void k_argmax(GbSlot *slots, const GbTileRec *recs, uint64_t nrecs, const GbExh *list,
+                         const unsigned long long *list_count, unsigned long long cap)
+{
+    unsigned long long cnt = *list_count;
+    if (cnt > cap) cnt = cap;
+    const unsigned long long stride = (unsigned long long)gridDim.x * blockDim.x;
+    for (unsigned long long i = blockIdx.x * (unsigned long long)blockDim.x + threadIdx.x;
+         i < nrecs + cnt; i += stride) {
+        if (i < nrecs) {
+            const GbTileRec r = recs[i];
+            if (r.max_p && r.max_p == slots[r.slot].max_p) atomicMin(&slots[r.slot].argmax_n, r.argmax_n);
+        } else {
+            const GbExh &x = list[i - nrecs];
+            if (x.p && x.p == slots[x.slot].max_p) atomicMin(&slots[x.slot].argmax_n, x.n);
+        }
+    }
+}
+
+__global__ void k_init(GbSlot *slots, uint64_t nslots, unsigned long long *hist, uint64_t hist_words,
+                       unsigned long long *counters, uint32_t ncounters)
+{
+    const unsigned long long stride = (unsigned long long)gridDim.x * blockDim.x;
+    const unsigned long long i0 = blockIdx.x * (unsigned long long)blockDim.x + threadIdx.x;
+    for (unsigned long long i = i0; i < nslots; i += stride) {
+        GbSlot s = {};
+        s.argmax_n = ~0ull;
+        s.first_failed_n = ~0ull;
+        slots[i] = s;
+    }
+    for (unsigned long long i = i0; i < hist_words; i += stride) hist[i] = 0ull;
+    if (i0 < ncounters) counters[i0] = 0ull;
+}
+
+__global__ void k_make_queries(GbExh *list, const unsigned long long *n, uint64_t k,
+                               unsigned long long *list_count)
+{
+    const unsigned long long i = blockIdx.x * (unsigned long long)blockDim.x + threadIdx.x;
+    if (i < k) {
+        GbExh x;
+        x.n = n[i];
+        x.out_index = ~0ull;
+        x.slot = 0;
+        x.start_k = 0;
+        x.p = 0;
+        list[i] = x;
+    }
+    if (i == 0) *list_count = k;
+}
+
+__global__ void k_finish_queries(const GbExh *list, uint64_t k, unsigned long long *p_out)
+{
+    const unsigned long long i = blockIdx.x * (unsigned long long)blockDim.x + threadIdx.x;
+    if (i < k) p_out[i] = list[i].p;
+}
+
+template <int NT, int PB, bool PERS, bool SO>
+hipError_t launch_one(const GbTileArgs &a, uint32_t grid, size_t lds, hipStream_t st)
+{
+    hipLaunchKernelGGL((k_tile<NT, PB, PERS, SO>), dim3(grid), dim3(NT), lds, st, a);
+    return hipGetLastError();
+}
+
+template <int NT, int PB, bool PERS, bool SO>
+hipError_t allow_lds(size_t lds)
+{
+    return hipFuncSetAttribute(reinterpret_cast<const void *>(&k_tile<NT, PB, PERS, SO>),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+}
+
+template <int NT>
+hipError_t allow_lds_nt(size_t lds)
+{
+    hipError_t e = hipSuccess, r;
+    if ((r = allow_lds<NT, 0, false, true>(lds)) != hipSuccess) e = r;
+    if ((r = allow_lds<NT, 0, false, false>(lds)) != hipSuccess) e = r;
+    if ((r = allow_lds<NT, 16, false, false>(lds)) != hipSuccess) e = r;
+    if ((r = allow_lds<NT, 32, false, false>(lds)) != hipSuccess) e = r;
+    if ((r = allow_lds<NT, 0, true, false>(lds)) != hipSuccess) e = r;
+    if ((r = allow_lds<NT, 16, true, false>(lds)) != hipSuccess) e = r;
+    if ((r = allow_lds<NT, 32, true, false>(lds)) != hipSuccess) e = r;
+    return e;
+}
+
+template <int NT>
+hipError_t launch_nt(const GbTileArgs &a, uint32_t grid, size_t lds, int pb, bool pers, bool so,
+                     hipStream_t st)
+{
+    if (so) return launch_one<NT, 0, false, true>(a, grid, lds, st);
+    if (pers) {
+        if (pb == 16) return launch_one<NT, 16, true, false>(a, grid, lds, st);
+        if (pb == 32) return launch_one<NT, 32, true, false>(a, grid, lds, st);
+        return launch_one<NT, 0, true, false>(a, grid, lds, st);
+    }
+    if (pb == 16) return launch_one<NT, 16, false, false>(a, grid, lds, st);
+    if (pb == 32) return launch_one<NT, 32, false, false>(a, grid, lds, st);
+    return launch_one<NT, 0, false, false>(a, grid, lds, st);
+}
+
+}  // namespace
+
+size_t gb_tile_lds_bytes(uint32_t tile_n, uint32_t halo_bits, uint32_t np_search, uint32_t threads)
+{
+    size_t words = (tile_n + halo_bits) / 32 + (np_search + 1) / 2 + np_search;
+    words = (words + 1) & ~(size_t)1;
+    words += 2 * 3 * (threads / 64);
+    return words * 4;
+}
+
+hipError_t gb_prepare_tiles(uint32_t threads, size_t lds_bytes)
+{
+    switch (threads) {
+    case 256: return allow_lds_nt<256>(lds_bytes);
+    case 512: return allow_lds_nt<512>(lds_bytes);
+    case 1024: return allow_lds_nt<1024>(lds_bytes);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t gb_tile_occupancy(uint32_t threads, size_t lds_bytes, int *blocks_per_cu)
+{
+    switch (threads) {
+    case 256:
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_tile<256, 0, true, false>, 256, lds_bytes);
+    case 512:
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_tile<512, 0, true, false>, 512, lds_bytes);
+    case 1024:
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_tile<1024, 0, true, false>, 1024, lds_bytes);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t gb_launch_tiles(const GbTileArgs &a, uint32_t grid, uint32_t threads, size_t lds_bytes,
+                           int pmin_bits, bool persistent, bool sieve_only, hipStream_t st)
+{
+    if (grid == 0) return hipSuccess;
+    switch (threads) {
+    case 256: return launch_nt<256>(a, grid, lds_bytes, pmin_bits, persistent, sieve_only, st);
+    case 512: return launch_nt<512>(a, grid, lds_bytes, pmin_bits, persistent, sieve_only, st);
+    case 1024: return launch_nt<1024>(a, grid, lds_bytes, pmin_bits, persistent, sieve_only, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t gb_launch_mr(const GbMrArgs &a, uint32_t grid, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_mr, dim3(grid), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t gb_launch_argmax(GbSlot *slots, const GbTileRec *recs, uint64_t nrecs, const GbExh *list,
+                            const unsigned long long *list_count, unsigned long long list_cap,
+                            hipStream_t st)
+{
+    hipLaunchKernelGGL(k_argmax, dim3(1024), dim3(256), 0, st, slots, recs, nrecs, list, list_count,
+                       list_cap);
+    return hipGetLastError();
+}
+
+hipError_t gb_launch_init(GbSlot *slots, uint64_t nslots, unsigned long long *hist, uint64_t hist_words,
+                          unsigned long long *counters, uint32_t ncounters, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_init, dim3(512), dim3(256), 0, st, slots, nslots, hist, hist_words, counters,
+                       ncounters);
+    return hipGetLastError();
+}
+
+hipError_t gb_launch_make_queries(GbExh *list, const unsigned long long *n, uint64_t k,
+                                  unsigned long long *list_count, hipStream_t st)
+{
+    const uint32_t grid = (uint32_t)((k + 255) / 256) + 1;
+    hipLaunchKernelGGL(k_make_queries, dim3(grid), dim3(256), 0, st, list, n, k, list_count);
+    return hipGetLastError();
+}
+
+hipError_t gb_launch_finish_queries(const GbExh *list, uint64_t k, unsigned long long *p_out,
+                                    hipStream_t st)
+{
+    const uint32_t grid = (uint32_t)((k + 255) / 256) + 1;
+    hipLaunchKernelGGL(k_finish_queries, dim3(grid), dim3(256), 0, st, list, k, p_out);
+    return hipGetLastError();
+}

@@ -63,6 +63,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--plain-steps", type=int, default=1)
+    ap.add_argument("--copy-calibrate", type=int, default=0, metavar="MIB",
+                    help="also run one device-to-device copy of this many MiB (a reference "
+                         "kernel of known traffic for the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: the verifier shards segments across GPUs by "
@@ -104,18 +107,31 @@ def main():
           file=sys.stderr, flush=True)
 
     # ---- plain (beside it) ------------------------------------------------
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    plain_tile = []
-    for _ in range(args.plain_steps):
-        rp = v.verify_range(LO, HI, batched=False)
-        plain_tile.append(rp["tile_ms"] / max(rp["tile_launches"], 1))
-    torch.cuda.synchronize()
-    plain_wall = (time.perf_counter() - t0) / args.plain_steps
-    for k in ("count", "checksum", "max_p", "argmax_n", "n_exhaustive", "n_failed"):
-        assert rp[k] == ref[k], k
-    print(f"# plain: {1e3*plain_wall:.1f} ms/step over {rp['n_segments']} segment launches",
-          file=sys.stderr, flush=True)
+    plain = None
+    if args.plain_steps > 0:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        plain_tile = []
+        for _ in range(args.plain_steps):
+            rp = v.verify_range(LO, HI, batched=False)
+            plain_tile.append(rp["tile_ms"] / max(rp["tile_launches"], 1))
+        torch.cuda.synchronize()
+        plain_wall = (time.perf_counter() - t0) / args.plain_steps
+        for k in ("count", "checksum", "max_p", "argmax_n", "n_exhaustive", "n_failed"):
+            assert rp[k] == ref[k], k
+        print(f"# plain: {1e3*plain_wall:.1f} ms/step over {rp['n_segments']} segment launches",
+              file=sys.stderr, flush=True)
+        plain = {"value": count / plain_wall, "ms_per_step": 1e3 * plain_wall,
+                 "segments": rp["n_segments"],
+                 "tile_launch_ms": sum(plain_tile) / len(plain_tile)}
+
+    if args.copy_calibrate:
+        nb = args.copy_calibrate << 20
+        src = torch.ones(nb // 4, dtype=torch.int32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(f"# copy calibration: {nb} bytes read, {nb} bytes written", file=sys.stderr, flush=True)
 
     # ---- roofline of the dominant kernel ------------------------------------
     t_launch = sum(tile_ms) / len(tile_ms) / 1e3
@@ -134,8 +150,7 @@ def main():
                    "n_per_step": count, "pmax": p["pmax"], "seg_log2": p["seg_log2"],
                    "tile_log2": p["tile_log2"], "wg_threads": p["wg_threads"],
                    "wheel_max": p["wheel_max"], "parallelism": "1 GPU"},
-        "plain": {"value": count / plain_wall, "ms_per_step": 1e3 * plain_wall,
-                  "segments": rp["n_segments"], "tile_launch_ms": sum(plain_tile) / len(plain_tile)},
+        "plain": plain,
         "summary": {k: ref[k] for k in ("count", "max_p", "argmax_n", "checksum",
                                         "n_exhaustive", "n_failed")},
         "roofline": roof,

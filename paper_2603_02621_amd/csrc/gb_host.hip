@@ -213,7 +213,8 @@ gb_status setup_geometry(gb_ctx *c)
     const uint32_t nbits = c->tile_n + c->halo_bits;
     c->k_wg_end = std::max(c->k_first, count_le(c->h_primes, nbits / c->threads));
     c->k_wave_end = std::max(c->k_wg_end, count_le(c->h_primes, nbits / 64));
-    c->lds = gb_tile_lds_bytes(c->tile_n, c->halo_bits, c->np_search, c->threads);
+    c->lds = gb_tile_lds_bytes(c->tile_n, c->halo_bits, c->np_search, c->k_wave_end - c->k_first,
+                               c->threads);
     hipDeviceProp_t prop;
     GB_HIP(c, hipGetDeviceProperties(&prop, p.device));
     if (c->lds > (size_t)prop.sharedMemPerBlock && c->lds > 163840)
@@ -281,6 +282,7 @@ GbTileArgs base_args(gb_ctx *c)
     a.k_first = c->k_first;
     a.k_wg_end = c->k_wg_end;
     a.k_wave_end = c->k_wave_end;
+    a.n_off = c->k_wave_end - c->k_first;
     a.wheel = c->d_wheel;
     a.wheel_len = c->wheel_len;
     a.wheel_max = c->prm.wheel_max;

@@ -54,6 +54,7 @@ struct GbTileArgs {
     uint32_t k_first;       // first prime index above the wheel
     uint32_t k_wg_end;      // primes [k_first, k_wg_end): whole-workgroup marking
     uint32_t k_wave_end;    // primes [k_wg_end, k_wave_end): one wave per prime
+    uint32_t n_off;         // LDS slots for first strikes: k_wave_end - k_first
     const uint32_t *wheel;  // wheel pattern bits, period wheel_len, padded by 64
     uint32_t wheel_len;     // product of the odd wheel primes
     uint32_t wheel_max;     // largest wheel prime
@@ -90,7 +91,7 @@ hipError_t gb_launch_tiles(const GbTileArgs &a, uint32_t grid, uint32_t threads,
 hipError_t gb_prepare_tiles(uint32_t threads, size_t lds_bytes);
 hipError_t gb_tile_occupancy(uint32_t threads, size_t lds_bytes, int *blocks_per_cu);
 size_t gb_tile_lds_bytes(uint32_t tile_n, uint32_t halo_bits, uint32_t np_search,
-                         uint32_t threads);
+                         uint32_t n_off, uint32_t threads);
 hipError_t gb_launch_mr(const GbMrArgs &a, uint32_t grid, hipStream_t st);
 hipError_t gb_launch_argmax(GbSlot *slots, const GbTileRec *recs, uint64_t nrecs,
                             const GbExh *list, const unsigned long long *list_count,

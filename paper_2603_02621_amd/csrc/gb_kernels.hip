@@ -89,28 +89,29 @@ __device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long v)
     return v;
 }
 
-// LDS carve-up of one tile workgroup (all offsets in 32-bit words).
+// LDS carve-up of one tile workgroup (offsets in 32-bit words).
 struct TileLds {
-    uint32_t *bits;      // (T + HB)/32 words
-    uint16_t *sp;        // odd primes <= P_max
-    uint32_t *lhist;     // per-prime hit counts of this tile
+    uint32_t *bits;           // (T + HB)/32 words: the tile's window, 1 = prime
+    uint16_t *hh;             // (p+1)/2 of the odd primes p <= P_max, padded by 4
+    uint32_t *lhist;          // per-prime hit counts of this tile
+    uint32_t *offs;           // first bit index of each small/medium sieving prime
     unsigned long long *red;  // 3 * waves
 };
 
-__device__ __forceinline__ TileLds carve(uint32_t *smem, uint32_t tile_n, uint32_t hb,
-                                         uint32_t nps, int nt)
+__device__ __forceinline__ TileLds carve(uint32_t *smem, const GbTileArgs &a)
 {
     TileLds L;
     uint32_t o = 0;
     L.bits = smem + o;
-    o += (tile_n + hb) / 32;
-    L.sp = reinterpret_cast<uint16_t *>(smem + o);
-    o += (nps + 1) / 2;
+    o += (a.tile_n + a.halo_bits) / 32;
+    L.hh = reinterpret_cast<uint16_t *>(smem + o);
+    o += (a.np_search + 4 + 1) / 2;
     L.lhist = smem + o;
-    o += nps;
+    o += a.np_search;
+    L.offs = smem + o;
+    o += a.n_off;
     o = (o + 1) & ~1u;
     L.red = reinterpret_cast<unsigned long long *>(smem + o);
-    (void)nt;
     return L;
 }
 
@@ -141,13 +142,22 @@ __device__ void process_tile(const GbTileArgs &a, unsigned long long g, const Ti
     const uint32_t nbits = nblk * 64u + HB;
     const uint32_t nw32 = nbits >> 5;
     const long long w0 = (long long)(N0 + 1ull - 2ull * HB);
+    const uint32_t np = W.np_sieve;
+    const uint32_t nps = a.np_search;
 
-    // ---- fast-path prime list and per-tile histogram ----------------------
+    // ---- fast-path prime list, per-tile histogram --------------------------
     if (!SIEVE_ONLY) {
-        for (uint32_t i = tid; i < a.np_search; i += NT) {
-            L.sp[i] = (uint16_t)a.primes[i];
-            L.lhist[i] = 0;
+        for (uint32_t i = tid; i < nps + 4; i += NT) {
+            const uint32_t p = a.primes[i < nps ? i : (nps ? nps - 1 : 0)];
+            L.hh[i] = (uint16_t)((p + 1u) >> 1);
+            if (i < nps) L.lhist[i] = 0;
         }
+    }
+    // ---- first strike of every small and medium sieving prime, once -------
+    const uint32_t kmid = min(a.k_wave_end, np);
+    for (uint32_t k = a.k_first + tid; k < kmid; k += NT) {
+        const unsigned long long t0 = first_index(w0, a.primes[k], a.magic[k]);
+        L.offs[k - a.k_first] = t0 < nbits ? (uint32_t)t0 : 0xFFFFFFFFu;
     }
 
     // ---- wheel pre-pattern: clears the odd multiples of 3..wheel_max ------
@@ -164,10 +174,10 @@ __device__ void process_tile(const GbTileArgs &a, unsigned long long g, const Ti
             const long long vfirst = w0 + 64ll * i;
             if (vfirst <= (long long)a.wheel_max) {
                 // the window reaches the wheel primes themselves, or 1 and below
-                for (uint32_t b = 0; b < 32; ++b) {
-                    const long long val = vfirst + 2ll * b;
-                    if (val < 2) v &= ~(1u << b);
-                    else if (is_wheel_prime(val, a.wheel_max)) v |= (1u << b);
+                for (uint32_t bt = 0; bt < 32; ++bt) {
+                    const long long val = vfirst + 2ll * bt;
+                    if (val < 2) v &= ~(1u << bt);
+                    else if (is_wheel_prime(val, a.wheel_max)) v |= (1u << bt);
                 }
             }
             L.bits[i] = v;
@@ -178,25 +188,23 @@ __device__ void process_tile(const GbTileArgs &a, unsigned long long g, const Ti
     __syncthreads();
 
     // ---- strided marking of the odd multiples of each sieving prime -------
-    const uint32_t np = W.np_sieve;
     {
         // primes with many hits per tile: the whole workgroup strides over one prime
         const uint32_t kend = min(a.k_wg_end, np);
         for (uint32_t k = a.k_first; k < kend; ++k) {
+            const uint32_t t0 = L.offs[k - a.k_first];
+            if (t0 == 0xFFFFFFFFu) continue;
             const uint32_t p = a.primes[k];
-            const unsigned long long t0 = first_index(w0, p, a.magic[k]);
-            if (t0 >= nbits) continue;
-            for (uint32_t idx = (uint32_t)t0 + tid * p; idx < nbits; idx += NT * p)
+            for (uint32_t idx = t0 + tid * p; idx < nbits; idx += NT * p)
                 atomicAnd(&L.bits[idx >> 5], ~(1u << (idx & 31u)));
         }
         // medium primes: one wavefront per prime, lanes stride by 64p
         const uint32_t kbeg2 = max(a.k_wg_end, a.k_first);
-        const uint32_t kend2 = min(a.k_wave_end, np);
-        for (uint32_t k = kbeg2 + wave; k < kend2; k += NWAVES) {
+        for (uint32_t k = kbeg2 + wave; k < kmid; k += NWAVES) {
+            const uint32_t t0 = L.offs[k - a.k_first];
+            if (t0 == 0xFFFFFFFFu) continue;
             const uint32_t p = a.primes[k];
-            const unsigned long long t0 = first_index(w0, p, a.magic[k]);
-            if (t0 >= nbits) continue;
-            for (uint32_t idx = (uint32_t)t0 + lane * p; idx < nbits; idx += 64u * p)
+            for (uint32_t idx = t0 + lane * p; idx < nbits; idx += 64u * p)
                 atomicAnd(&L.bits[idx >> 5], ~(1u << (idx & 31u)));
         }
         // large primes: one lane per prime, a few hits each
@@ -225,82 +233,101 @@ __device__ void process_tile(const GbTileArgs &a, unsigned long long g, const Ti
     unsigned long long *hist = a.hist + (unsigned long long)hrow * GB_HIST_BINS_I;
     const unsigned long long half0 = N0 >> 1;
     const unsigned long long outb = W.out_off + (unsigned long long)a.tile_n * t;
-    const uint32_t nps = a.np_search;
 
     uint32_t maxp = 0, amax = 0;       // lane's largest p_min and its n index
     unsigned long long cs = 0;         // lane's checksum part
     uint32_t nexh = 0;                 // n left to the exhaustive phase
 
-    uint32_t b = tid, k = 0, Ulo = 0, Uhi = 0, Ab = 0, Bb = 0;
+    // block state: unresolved mask U, next prime index k, the block's sums
+    // of p*popcount(hit) (Ab) and p*(positions of hit) (Bb), and its last hit
+    // (the last hit carries the block's largest p_min)
+    uint32_t b = tid, k = 0, Ulo = 0, Uhi = 0, Ab = 0, Bb = 0, lastp = 0, llo = 0, lhi = 0;
+    uint32_t base = 0;
     auto start_block = [&](uint32_t bb) {
         const uint32_t nv = min(64u, cnt - 64u * bb);
         Ulo = nv >= 32 ? ~0u : ((1u << nv) - 1u);
         Uhi = nv >= 64 ? ~0u : (nv > 32 ? ((1u << (nv - 32)) - 1u) : 0u);
-        k = 0; Ab = 0; Bb = 0;
+        k = 0; Ab = 0; Bb = 0; lastp = 0; llo = 0; lhi = 0;
+        base = 64u * bb + HB;
         if (N0 == 4 && bb == 0) {  // n = 4 = 2 + 2, the one even p_min
             Ulo &= ~1u;
             Ab = 2;
+            lastp = 2; llo = 1u;
             atomicAdd(&hist[0], 1ull);
-            if (maxp < 2) { maxp = 2; amax = 0; }
             if (a.pmin) store_p<PB>(a.pmin, outb, 2u);
         }
     };
-    if (b < nblk) start_block(b);
-    while (b < nblk) {
-        if (k < nps) {
-            const uint32_t p = L.sp[k];
-            const uint32_t s = 64u * b + HB - ((p + 1u) >> 1);
-            const uint32_t w = s >> 5, sh = s & 31u;
-            const uint32_t d0 = L.bits[w], d1 = L.bits[w + 1], d2 = L.bits[w + 2];
-            const uint32_t hlo = __builtin_amdgcn_alignbit(d1, d0, sh) & Ulo;
-            const uint32_t hhi = __builtin_amdgcn_alignbit(d2, d1, sh) & Uhi;
-            if (hlo | hhi) {
-                const uint32_t pc = __popc(hlo) + __popc(hhi);
-                Ab += p * pc;
-                Bb += p * bitpos_sum(hlo, hhi);
-                atomicAdd(&L.lhist[k], pc);
-                if (p > maxp) {
-                    maxp = p;
-                    amax = 64u * b + (hlo ? (uint32_t)__builtin_ctz(hlo)
-                                          : 32u + (uint32_t)__builtin_ctz(hhi));
+    auto finish_block = [&]() {
+        cs += (half0 + 64ull * b) * Ab + Bb;
+        if (lastp > maxp) {
+            maxp = lastp;
+            amax = 64u * b + (llo ? (uint32_t)__builtin_ctz(llo) : 32u + (uint32_t)__builtin_ctz(lhi));
+        }
+        if (Ulo | Uhi) {
+            unsigned long long u = ((unsigned long long)Uhi << 32) | Ulo;
+            nexh += __popcll(u);
+            while (u) {
+                const uint32_t j = (uint32_t)__builtin_ctzll(u);
+                u &= u - 1ull;
+                const unsigned long long e = atomicAdd(a.list_count, 1ull);
+                if (e < a.list_cap) {
+                    GbExh x;
+                    x.n = N0 + 2ull * (64ull * b + j);
+                    x.out_index = outb + 64ull * b + j;
+                    x.slot = slot;
+                    x.start_k = nps;
+                    x.p = 0;
+                    a.list[e] = x;
                 }
-                if constexpr (PB != 0) {
-                    if (a.pmin) {
-                        unsigned long long hb = ((unsigned long long)hhi << 32) | hlo;
-                        const unsigned long long ob = outb + 64ull * b;
-                        while (hb) {
-                            store_p<PB>(a.pmin, ob + (unsigned long long)__builtin_ctzll(hb), p);
-                            hb &= hb - 1ull;
+            }
+        }
+    };
+    if (nps == 0) {
+        // no odd prime below P_max: every n but 4 goes to the exhaustive phase
+        for (; b < nblk; b += NT) {
+            start_block(b);
+            finish_block();
+        }
+    } else {
+        if (b < nblk) start_block(b);
+        while (b < nblk) {
+            // four probes per exit check; the prime list is padded with copies
+            // of its last prime, which cannot hit an n twice
+#pragma unroll
+            for (uint32_t u = 0; u < 4; ++u) {
+                const uint32_t h = L.hh[k + u];
+                const uint32_t s = base - h;
+                const uint32_t *wp = L.bits + (s >> 5);
+                const uint32_t d0 = wp[0], d1 = wp[1], d2 = wp[2];
+                const uint32_t hlo = __builtin_amdgcn_alignbit(d1, d0, s) & Ulo;
+                const uint32_t hhi = __builtin_amdgcn_alignbit(d2, d1, s) & Uhi;
+                if (hlo | hhi) {
+                    const uint32_t p = 2u * h - 1u;
+                    const uint32_t pc = __popc(hlo) + __popc(hhi);
+                    Ab += p * pc;
+                    Bb += p * bitpos_sum(hlo, hhi);
+                    atomicAdd(&L.lhist[k + u], pc);
+                    lastp = p; llo = hlo; lhi = hhi;
+                    if constexpr (PB != 0) {
+                        if (a.pmin) {
+                            unsigned long long hb = ((unsigned long long)hhi << 32) | hlo;
+                            const unsigned long long ob = outb + 64ull * b;
+                            while (hb) {
+                                store_p<PB>(a.pmin, ob + (unsigned long long)__builtin_ctzll(hb), p);
+                                hb &= hb - 1ull;
+                            }
                         }
                     }
-                }
-                Ulo &= ~hlo;
-                Uhi &= ~hhi;
-            }
-            ++k;
-        }
-        if ((Ulo | Uhi) == 0u || k >= nps) {
-            cs += (half0 + 64ull * b) * Ab + Bb;
-            if (Ulo | Uhi) {
-                unsigned long long u = ((unsigned long long)Uhi << 32) | Ulo;
-                nexh += __popcll(u);
-                while (u) {
-                    const uint32_t j = (uint32_t)__builtin_ctzll(u);
-                    u &= u - 1ull;
-                    const unsigned long long e = atomicAdd(a.list_count, 1ull);
-                    if (e < a.list_cap) {
-                        GbExh x;
-                        x.n = N0 + 2ull * (64ull * b + j);
-                        x.out_index = outb + 64ull * b + j;
-                        x.slot = slot;
-                        x.start_k = nps;
-                        x.p = 0;
-                        a.list[e] = x;
-                    }
+                    Ulo ^= hlo;
+                    Uhi ^= hhi;
                 }
             }
-            b += NT;
-            if (b < nblk) start_block(b);
+            k += 4;
+            if ((Ulo | Uhi) == 0u || k >= nps) {
+                finish_block();
+                b += NT;
+                if (b < nblk) start_block(b);
+            }
         }
     }
 
@@ -347,7 +374,7 @@ __global__ __launch_bounds__(NT) void k_tile(GbTileArgs a)
 {
     extern __shared__ uint32_t smem[];
     __shared__ unsigned long long s_tile;
-    const TileLds L = carve(smem, a.tile_n, a.halo_bits, a.np_search, NT);
+    const TileLds L = carve(smem, a);
     if constexpr (PERS) {
         for (;;) {
             if (threadIdx.x == 0) s_tile = atomicAdd(a.queue, 1ull);
@@ -613,9 +640,10 @@ hipError_t launch_nt(const GbTileArgs &a, uint32_t grid, size_t lds, int pb, boo
 
 }  // namespace
 
-size_t gb_tile_lds_bytes(uint32_t tile_n, uint32_t halo_bits, uint32_t np_search, uint32_t threads)
+size_t gb_tile_lds_bytes(uint32_t tile_n, uint32_t halo_bits, uint32_t np_search, uint32_t n_off,
+                         uint32_t threads)
 {
-    size_t words = (tile_n + halo_bits) / 32 + (np_search + 1) / 2 + np_search;
+    size_t words = (tile_n + halo_bits) / 32 + (np_search + 4 + 1) / 2 + np_search + n_off;
     words = (words + 1) & ~(size_t)1;
     words += 2 * 3 * (threads / 64);
     return words * 4;

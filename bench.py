@@ -63,6 +63,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--plain-steps", type=int, default=1)
+    ap.add_argument("--no-windows", action="store_true")
     ap.add_argument("--copy-calibrate", type=int, default=0, metavar="MIB",
                     help="also run one device-to-device copy of this many MiB (a reference "
                          "kernel of known traffic for the HBM byte counters)")
@@ -125,6 +126,22 @@ def main():
                  "segments": rp["n_segments"],
                  "tile_launch_ms": sum(plain_tile) / len(plain_tile)}
 
+    # ---- batched windows: 4096 uneven windows in one persistent launch ---
+    windows = None
+    if not args.no_windows:
+        from paper_2603_02621_amd.workloads import config3_windows
+        wins = config3_windows(0, 4096)
+        wn = sum(n for _, n in wins)
+        v.verify_windows(wins, sums=False)           # graph capture
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(2):
+            v.verify_windows(wins, sums=False)
+        torch.cuda.synchronize()
+        wt = (time.perf_counter() - t0) / 2
+        windows = {"windows": len(wins), "even_n": wn, "ms_per_step": 1e3 * wt, "value": wn / wt}
+        print(f"# windows: {1e3*wt:.1f} ms for {wn} n in 4096 windows", file=sys.stderr, flush=True)
+
     if args.copy_calibrate:
         nb = args.copy_calibrate << 20
         src = torch.ones(nb // 4, dtype=torch.int32, device="cuda")
@@ -151,6 +168,7 @@ def main():
                    "tile_log2": p["tile_log2"], "wg_threads": p["wg_threads"],
                    "wheel_max": p["wheel_max"], "parallelism": "1 GPU"},
         "plain": plain,
+        "batched_windows": windows,
         "summary": {k: ref[k] for k in ("count", "max_p", "argmax_n", "checksum",
                                         "n_exhaustive", "n_failed")},
         "roofline": roof,

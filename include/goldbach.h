@@ -198,6 +198,74 @@ gb_status gb_exhaustive_list(gb_ctx *ctx, uint64_t *n, uint64_t *p, size_t cap,
 gb_status gb_autotune(gb_ctx *ctx, const gb_window *sample, size_t k,
                       const char *cache_path, gb_params *best);
 
+/* ------------------------------------------------------------------------
+ * Serving: continuous batching of single-n and range requests.
+ *
+ * A server owns a context and `streams` device streams, each with its own
+ * scratch.  A scheduler thread takes submitted requests in arrival order,
+ * admits them while the bytes of device memory they need fit in
+ * prm->mem_budget, packs up to `max_batch` of them into one launch on an
+ * idle stream (single n: one wavefront each, as gb_verify_many; ranges: one
+ * persistent tile launch over all their windows, as gb_verify_windows), and
+ * keeps admitting new requests onto other streams while earlier launches
+ * run, so their work overlaps on the device.  Every result is the same as the
+ * request run alone.  The prime table and wheel stay resident for the
+ * server's lifetime.  Submit and poll may be called from any thread.
+ * ---------------------------------------------------------------------- */
+typedef struct gb_server gb_server;
+
+#define GB_REQ_ONE 0u    /* one even n */
+#define GB_REQ_RANGE 1u  /* the even n n, n+2, ..., n + 2(len-1) */
+
+typedef struct gb_request {
+    uint32_t  kind;      /* GB_REQ_ONE or GB_REQ_RANGE */
+    uint32_t  flags;     /* must be 0 */
+    uint64_t  n;         /* the n (GB_REQ_ONE) or the first n (GB_REQ_RANGE) */
+    uint64_t  len;       /* GB_REQ_RANGE: number of even n (>= 1) */
+    uint16_t *pmin;      /* GB_REQ_RANGE: host buffer of len entries for the
+                            per-n p_min (0 for p_min >= 2^16), written before
+                            the completion is reported; or NULL */
+    uint64_t  tag;       /* caller's value, returned with the completion */
+} gb_request;
+
+typedef struct gb_completion {
+    uint64_t   id;              /* the id gb_server_submit returned */
+    uint64_t   tag;
+    int32_t    status;          /* gb_status of this request */
+    uint32_t   kind;
+    uint64_t   p;               /* GB_REQ_ONE: p_min(n) */
+    gb_summary summary;         /* GB_REQ_RANGE: the range's summary */
+    uint64_t   submit_ns;       /* steady-clock times of submit, launch and */
+    uint64_t   launch_ns;       /* observed completion */
+    uint64_t   done_ns;
+    uint32_t   batch_requests;  /* requests in the launch that served it */
+    uint32_t   stream;          /* index of the stream that ran it */
+} gb_completion;
+
+typedef struct gb_server_stats {
+    uint64_t submitted, completed, rejected, queued, inflight;
+    uint64_t bytes_inflight, peak_bytes_inflight;
+    uint64_t launches, peak_concurrent_launches;
+} gb_server_stats;
+
+/* Start a server on prm->device (prm may be NULL) with `streams` device
+ * streams (1..8, 0 -> 2) and at most `max_batch` requests per launch
+ * (0 -> 4096). */
+gb_status gb_server_start(gb_server **srv, const gb_params *prm, uint32_t streams,
+                          uint32_t max_batch);
+/* Queue one request; *id receives its id.  GB_EINVAL for a malformed
+ * request, GB_ERANGE above max_hi, GB_ENOMEM if it alone needs more than
+ * mem_budget.  Never blocks on the device. */
+gb_status gb_server_submit(gb_server *srv, const gb_request *req, uint64_t *id);
+/* Take up to cap finished requests into out[]; *count receives how many.
+ * Waits up to wait_ms milliseconds for the first one (0: do not wait). */
+gb_status gb_server_poll(gb_server *srv, gb_completion *out, size_t cap, size_t *count,
+                         int32_t wait_ms);
+gb_status gb_server_stats_get(gb_server *srv, gb_server_stats *stats);
+/* Finish every queued and running request, then free the server. */
+gb_status gb_server_stop(gb_server *srv);
+const char *gb_server_last_error(const gb_server *srv);
+
 const char *gb_status_str(gb_status st);
 const char *gb_last_error(const gb_ctx *ctx);
 

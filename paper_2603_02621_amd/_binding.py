@@ -55,18 +55,23 @@ class Summary(ctypes.Structure):
         return {k: int(getattr(self, k)) for k in Result.SUMMARY}
 
 
-class ServerStats(ctypes.Structure):
-    _fields_ = [("submitted", u64), ("completed", u64), ("rejected", u64), ("inflight", u64),
-                ("bytes_inflight", u64), ("launches", u64), ("peak_inflight", u64),
-                ("peak_bytes", u64)]
-
-    def as_dict(self):
-        return {name: int(getattr(self, name)) for name, _ in self._fields_}
+class Request(ctypes.Structure):
+    _fields_ = [("kind", u32), ("flags", u32), ("n", u64), ("len", u64), ("pmin", vp), ("tag", u64)]
 
 
 class Completion(ctypes.Structure):
-    _fields_ = [("id", u64), ("status", i32), ("kind", u32), ("p", u64),
-                ("submit_ns", u64), ("done_ns", u64), ("summary", Summary)]
+    _fields_ = [("id", u64), ("tag", u64), ("status", i32), ("kind", u32), ("p", u64),
+                ("summary", Summary), ("submit_ns", u64), ("launch_ns", u64), ("done_ns", u64),
+                ("batch_requests", u32), ("stream", u32)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [(k, u64) for k in ("submitted", "completed", "rejected", "queued", "inflight",
+                                   "bytes_inflight", "peak_bytes_inflight", "launches",
+                                   "peak_concurrent_launches")]
+
+    def as_dict(self):
+        return {name: int(getattr(self, name)) for name, _ in self._fields_}
 
 
 # exported name -> (argtypes, restype)
@@ -84,6 +89,13 @@ SIGNATURES = {
     "gb_exhaustive_list": ([vp, vp, vp, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)], i32),
     "gb_autotune": ([vp, ctypes.POINTER(Window), ctypes.c_size_t, ctypes.c_char_p,
                      ctypes.POINTER(Params)], i32),
+    "gb_server_start": ([ctypes.POINTER(vp), ctypes.POINTER(Params), u32, u32], i32),
+    "gb_server_submit": ([vp, ctypes.POINTER(Request), ctypes.POINTER(u64)], i32),
+    "gb_server_poll": ([vp, ctypes.POINTER(Completion), ctypes.c_size_t,
+                        ctypes.POINTER(ctypes.c_size_t), i32], i32),
+    "gb_server_stats_get": ([vp, ctypes.POINTER(ServerStats)], i32),
+    "gb_server_stop": ([vp], i32),
+    "gb_server_last_error": ([vp], ctypes.c_char_p),
     "gb_status_str": ([i32], ctypes.c_char_p),
     "gb_last_error": ([vp], ctypes.c_char_p),
 }

@@ -1,6 +1,6 @@
 // gb_host.hip -- host runtime behind the C ABI in include/goldbach.h:
 // context and resident tables, segment/tile planning, launches, the HIP
-// graph of the batched form, and the summary merge.
+// graphs of the batched forms, and the summary merge.
 #include <algorithm>
 #include <chrono>
 #include <cstdio>
@@ -8,101 +8,11 @@
 #include <string>
 #include <vector>
 
-#include "../../include/goldbach.h"
-#include "gb_internal.h"
+#include "gb_runtime.h"
 
-namespace {
+namespace gbrt {
 
-constexpr uint64_t kDefaultMaxHi = 1ull << 50;
-constexpr uint32_t kCounters = 4;  // [0] list count, [1] work queue
-
-// Bumped whenever any device or pinned scratch buffer moves, so a cached HIP
-// graph that captured the old addresses is never replayed.
-static uint64_t g_buffer_generation = 1;
-
-template <class T>
-struct DevBuf {
-    T *p = nullptr;
-    size_t cap = 0;
-    hipError_t ensure(size_t n)
-    {
-        if (n <= cap && p) return hipSuccess;
-        ++g_buffer_generation;
-        if (p) (void)hipFree(p);
-        p = nullptr;
-        cap = 0;
-        size_t want = std::max<size_t>(n, 1);
-        hipError_t e = hipMalloc(reinterpret_cast<void **>(&p), want * sizeof(T));
-        if (e == hipSuccess) cap = want;
-        return e;
-    }
-    void release()
-    {
-        if (p) (void)hipFree(p);
-        p = nullptr;
-        cap = 0;
-    }
-};
-
-}  // namespace
-
-struct GraphKey {
-    uint64_t generation = 0;
-    int kind = 0;  // 1: range, 2: windows
-    uint64_t nseg = 0, ntiles = 0, hist_rows = 0;
-    void *pmin = nullptr;
-    int pmin_bits = 0;
-    hipStream_t stream = nullptr;
-    bool operator==(const GraphKey &o) const
-    {
-        return generation == o.generation && kind == o.kind && nseg == o.nseg && ntiles == o.ntiles && hist_rows == o.hist_rows && pmin == o.pmin &&
-               pmin_bits == o.pmin_bits && stream == o.stream;
-    }
-};
-
-struct gb_ctx {
-    gb_params prm{};
-    int num_cu = 0;
-    std::vector<uint32_t> h_primes;     // odd primes 3, 5, 7, ...
-    uint32_t *d_primes = nullptr;
-    unsigned long long *d_magic = nullptr;
-    uint64_t ntab = 0;
-    uint64_t table_limit = 0;           // every odd prime <= table_limit is in the table
-    uint32_t np_search = 0, k_first = 0, halo_bits = 0;
-    uint32_t *d_wheel = nullptr;
-    uint32_t wheel_len = 0;
-    uint32_t tile_n = 0, threads = 0;
-    uint32_t k_wg_end = 0, k_wave_end = 0;
-    size_t lds = 0;
-    int occupancy = 1;
-
-    DevBuf<GbWindow> win;
-    DevBuf<GbSlot> slots;
-    DevBuf<unsigned long long> hist;
-    DevBuf<GbTileRec> recs;
-    DevBuf<GbExh> list;
-    DevBuf<unsigned long long> counters;
-    DevBuf<unsigned char> pmin_tmp;
-    DevBuf<unsigned long long> q_tmp;
-
-    // pinned host mirrors of the summary outputs (graph memcpy targets)
-    GbSlot *h_slots = nullptr;
-    size_t h_slots_cap = 0;
-    unsigned long long *h_hist = nullptr;
-    size_t h_hist_cap = 0;
-    unsigned long long *h_counters = nullptr;
-
-    hipEvent_t ev0 = nullptr, ev1 = nullptr, evt0 = nullptr, evt1 = nullptr;
-    std::string err;
-
-    hipGraphExec_t gexec[3] = {nullptr, nullptr, nullptr};  // init, tiles, rest
-    GraphKey gkey;
-
-    std::vector<GbExh> last_list;
-    bool last_list_valid = false;
-};
-
-namespace {
+std::atomic<uint64_t> g_buffer_generation{1};
 
 gb_status fail(gb_ctx *c, gb_status st, const std::string &msg)
 {
@@ -110,23 +20,18 @@ gb_status fail(gb_ctx *c, gb_status st, const std::string &msg)
     return st;
 }
 
-#define GB_HIP(c, expr)                                                                       \
-    do {                                                                                      \
-        hipError_t e_ = (expr);                                                               \
-        if (e_ != hipSuccess)                                                                 \
-            return fail((c), GB_EDEVICE, std::string(#expr ": ") + hipGetErrorString(e_)); \
-    } while (0)
-
 uint64_t isqrt64(uint64_t x)
 {
     uint64_t lo = 0, hi = 4294967295ull;
     if (hi > x) hi = x;
     while (lo < hi) {
-        uint64_t mid = lo + (hi - lo + 1) / 2;
+        const uint64_t mid = lo + (hi - lo + 1) / 2;
         if ((unsigned __int128)mid * mid <= x) lo = mid; else hi = mid - 1;
     }
     return lo;
 }
+
+namespace {
 
 // Odd primes up to `limit` by a segmented odd-only sieve (host, once per context).
 std::vector<uint32_t> host_odd_primes(uint64_t limit)
@@ -170,8 +75,163 @@ uint32_t count_le(const std::vector<uint32_t> &v, uint64_t x)
                       v.begin());
 }
 
-// Number of odd primes p in the table with p*p <= top.
-uint32_t count_sq_le(const std::vector<uint32_t> &v, uint64_t top) { return count_le(v, isqrt64(top)); }
+GbTileArgs base_args(gb_ctx *c, Workspace &ws)
+{
+    GbTileArgs a{};
+    a.tile_n = c->tile_n;
+    a.halo_bits = c->halo_bits;
+    a.np_search = c->np_search;
+    a.primes = c->d_primes;
+    a.magic = c->d_magic;
+    a.k_first = c->k_first;
+    a.k_wg_end = c->k_wg_end;
+    a.k_wave_end = c->k_wave_end;
+    a.n_off = c->k_wave_end - c->k_first;
+    a.wheel = c->d_wheel;
+    a.wheel_len = c->wheel_len;
+    a.wheel_max = c->prm.wheel_max;
+    a.list = ws.list.p;
+    a.list_count = ws.counters.p;
+    a.list_cap = c->prm.max_unresolved;
+    a.queue = ws.counters.p + 1;
+    return a;
+}
+
+GbMrArgs mr_args(gb_ctx *c, Workspace &ws)
+{
+    GbMrArgs m{};
+    m.list = ws.list.p;
+    m.list_count = ws.counters.p;
+    m.list_cap = c->prm.max_unresolved;
+    m.primes = c->d_primes;
+    m.ntab = c->ntab;
+    m.budget = c->prm.exhaustive_budget_p;
+    return m;
+}
+
+uint32_t mr_grid(gb_ctx *c) { return (uint32_t)std::max(64, c->num_cu * 8); }
+
+gb_status enqueue_init(gb_ctx *c, Workspace &ws, const Job &j, hipStream_t st)
+{
+    GB_HIP(c, gb_launch_init(ws.slots.p, j.nslots, ws.hist.p, j.hist_rows * GB_HIST_BINS_I, ws.counters.p,
+                             kCounters, st));
+    return GB_OK;
+}
+
+gb_status enqueue_tiles(gb_ctx *c, Workspace &ws, const Job &j, hipStream_t st)
+{
+    GbTileArgs a = base_args(c, ws);
+    a.slots = ws.slots.p;
+    a.hist = ws.hist.p;
+    a.hist_per_slot = j.hist_rows > 1 ? 1u : 0u;
+    a.recs = ws.recs.p;
+    a.pmin = j.pmin_dev;
+    const Plan &pl = *j.pl;
+    if (j.persistent) {
+        a.win = ws.win.p;
+        a.nwin = (uint32_t)pl.w.size();
+        a.ntiles = pl.ntiles;
+        const uint64_t g = std::min<uint64_t>(pl.ntiles, (uint64_t)c->num_cu * c->occupancy);
+        GB_HIP(c, gb_launch_tiles(a, (uint32_t)g, c->threads, c->lds, j.pmin_bits, true, false, st));
+    } else {
+        for (size_t i = 0; i < pl.w.size(); ++i) {
+            GbTileArgs b = a;
+            b.win = ws.win.p + i;
+            b.nwin = 1;
+            b.tile0 = pl.w[i].tile_base;
+            const uint64_t nt = (pl.w[i].count + c->tile_n - 1) / c->tile_n;
+            GB_HIP(c, gb_launch_tiles(b, (uint32_t)nt, c->threads, c->lds, j.pmin_bits, false, false, st));
+        }
+    }
+    return GB_OK;
+}
+
+gb_status enqueue_rest(gb_ctx *c, Workspace &ws, const Job &j, hipStream_t st)
+{
+    GbMrArgs m = mr_args(c, ws);
+    m.pmin = j.pmin_dev;
+    m.pmin_bits = (uint32_t)j.pmin_bits;
+    m.slots = ws.slots.p;
+    m.hist = ws.hist.p;
+    m.hist_per_slot = j.hist_rows > 1 ? 1u : 0u;
+    GB_HIP(c, gb_launch_mr(m, mr_grid(c), st));
+    GB_HIP(c, gb_launch_argmax(ws.slots.p, ws.recs.p, j.pl->ntiles, ws.list.p, ws.counters.p,
+                               c->prm.max_unresolved, st));
+    GB_HIP(c, hipMemcpyAsync(ws.h_slots.p, ws.slots.p, j.nslots * sizeof(GbSlot), hipMemcpyDeviceToHost, st));
+    GB_HIP(c, hipMemcpyAsync(ws.h_hist.p, ws.hist.p, j.hist_rows * GB_HIST_BINS_I * 8, hipMemcpyDeviceToHost,
+                             st));
+    GB_HIP(c, hipMemcpyAsync(ws.h_counters.p, ws.counters.p, kCounters * 8, hipMemcpyDeviceToHost, st));
+    return GB_OK;
+}
+
+using PhaseFn = gb_status (*)(gb_ctx *, Workspace &, const Job &, hipStream_t);
+
+gb_status capture(gb_ctx *c, Workspace &ws, PhaseFn fn, const Job &j, hipGraphExec_t *out)
+{
+    hipStream_t cap = nullptr;
+    GB_HIP(c, hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+    hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeRelaxed);
+    if (e != hipSuccess) {
+        (void)hipStreamDestroy(cap);
+        return fail(c, GB_EDEVICE, std::string("hipStreamBeginCapture: ") + hipGetErrorString(e));
+    }
+    const gb_status s = fn(c, ws, j, cap);
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(cap, &g);
+    (void)hipStreamDestroy(cap);
+    if (s != GB_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return s;
+    }
+    GB_HIP(c, e);
+    e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    GB_HIP(c, e);
+    return GB_OK;
+}
+
+}  // namespace
+
+hipError_t Workspace::init(uint64_t list_cap)
+{
+    hipError_t e;
+    if ((e = list.ensure(list_cap)) != hipSuccess) return e;
+    if ((e = counters.ensure(kCounters)) != hipSuccess) return e;
+    if ((e = h_counters.ensure(kCounters)) != hipSuccess) return e;
+    for (hipEvent_t *ev : {&ev0, &ev1, &evt0, &evt1})
+        if ((e = hipEventCreate(ev)) != hipSuccess) return e;
+    if ((e = hipEventCreateWithFlags(&done, hipEventDisableTiming)) != hipSuccess) return e;
+    return hipSuccess;
+}
+
+void Workspace::drop_graphs()
+{
+    for (auto &g : gexec) {
+        if (g) (void)hipGraphExecDestroy(g);
+        g = nullptr;
+    }
+}
+
+void Workspace::release()
+{
+    drop_graphs();
+    win.release();
+    slots.release();
+    hist.release();
+    recs.release();
+    list.release();
+    counters.release();
+    pmin.release();
+    q.release();
+    h_slots.release();
+    h_hist.release();
+    h_counters.release();
+    h_q.release();
+    for (hipEvent_t *ev : {&ev0, &ev1, &evt0, &evt1, &done}) {
+        if (*ev) (void)hipEventDestroy(*ev);
+        *ev = nullptr;
+    }
+}
 
 gb_status apply_params(gb_ctx *c, const gb_params *in)
 {
@@ -179,7 +239,7 @@ gb_status apply_params(gb_ctx *c, const gb_params *in)
     if (in) p = *in;
     if (p.pmax == 0) p.pmax = 8192;
     if (p.seg_log2 == 0) p.seg_log2 = 24;
-    if (p.tile_log2 == 0) p.tile_log2 = 18;
+    if (p.tile_log2 == 0) p.tile_log2 = 19;
     if (p.wg_threads == 0) p.wg_threads = 512;
     if (p.wheel_max == 0) p.wheel_max = 19;
     if (p.max_hi == 0) p.max_hi = kDefaultMaxHi;
@@ -191,8 +251,7 @@ gb_status apply_params(gb_ctx *c, const gb_params *in)
     if (p.tile_log2 > p.seg_log2) return fail(c, GB_EINVAL, "tile_log2 must not exceed seg_log2");
     if (p.wg_threads != 256 && p.wg_threads != 512 && p.wg_threads != 1024)
         return fail(c, GB_EINVAL, "wg_threads must be 256, 512 or 1024");
-    if (p.wheel_max != 7 && p.wheel_max != 11 && p.wheel_max != 13 && p.wheel_max != 17 &&
-        p.wheel_max != 19)
+    if (p.wheel_max != 7 && p.wheel_max != 11 && p.wheel_max != 13 && p.wheel_max != 17 && p.wheel_max != 19)
         return fail(c, GB_EINVAL, "wheel_max must be 7, 11, 13, 17 or 19");
     if (p.max_hi > GB_MAX_N) return fail(c, GB_EINVAL, "max_hi must be at most 2^63");
     if (p.max_hi < 1024) p.max_hi = 1024;
@@ -200,7 +259,34 @@ gb_status apply_params(gb_ctx *c, const gb_params *in)
     return GB_OK;
 }
 
-// Derived launch geometry for the current parameters.
+gb_status build_tables(gb_ctx *c)
+{
+    // odd primes up to sqrt(max_hi + slack), and at least past 2^16
+    uint64_t lim = isqrt64(c->prm.max_hi + (1ull << 30)) + 2;
+    lim = std::max<uint64_t>(lim, 70000);
+    c->h_primes = host_odd_primes(lim);
+    c->table_limit = lim;
+    c->ntab = c->h_primes.size();
+    std::vector<unsigned long long> magic(c->ntab);
+    for (uint64_t i = 0; i < c->ntab; ++i) magic[i] = ~0ull / c->h_primes[i];
+    GB_HIP(c, hipMalloc(&c->d_primes, c->ntab * 4));
+    GB_HIP(c, hipMalloc(&c->d_magic, c->ntab * 8));
+    GB_HIP(c, hipMemcpy(c->d_primes, c->h_primes.data(), c->ntab * 4, hipMemcpyHostToDevice));
+    GB_HIP(c, hipMemcpy(c->d_magic, magic.data(), c->ntab * 8, hipMemcpyHostToDevice));
+    return GB_OK;
+}
+
+void free_tables(gb_ctx *c)
+{
+    if (c->d_primes) (void)hipFree(c->d_primes);
+    if (c->d_magic) (void)hipFree(c->d_magic);
+    if (c->d_wheel) (void)hipFree(c->d_wheel);
+    c->d_primes = nullptr;
+    c->d_magic = nullptr;
+    c->d_wheel = nullptr;
+}
+
+// Launch geometry and wheel pattern for the current parameters.
 gb_status setup_geometry(gb_ctx *c)
 {
     const gb_params &p = c->prm;
@@ -213,12 +299,12 @@ gb_status setup_geometry(gb_ctx *c)
     const uint32_t nbits = c->tile_n + c->halo_bits;
     c->k_wg_end = std::max(c->k_first, count_le(c->h_primes, nbits / c->threads));
     c->k_wave_end = std::max(c->k_wg_end, count_le(c->h_primes, nbits / 64));
-    c->lds = gb_tile_lds_bytes(c->tile_n, c->halo_bits, c->np_search, c->k_wave_end - c->k_first,
-                               c->threads);
+    c->lds = gb_tile_lds_bytes(c->tile_n, c->halo_bits, c->np_search, c->k_wave_end - c->k_first, c->threads);
+    if (c->lds > 160 * 1024)
+        return fail(c, GB_EINVAL, "tile does not fit in LDS (" + std::to_string(c->lds) +
+                                      " bytes); lower tile_log2, wg_threads or pmax");
     hipDeviceProp_t prop;
     GB_HIP(c, hipGetDeviceProperties(&prop, p.device));
-    if (c->lds > (size_t)prop.sharedMemPerBlock && c->lds > 163840)
-        return fail(c, GB_EINVAL, "tile does not fit in LDS; lower tile_log2 or pmax");
     c->num_cu = prop.multiProcessorCount;
     GB_HIP(c, gb_prepare_tiles(c->threads, c->lds));
     int occ = 0;
@@ -242,79 +328,12 @@ gb_status setup_geometry(gb_ctx *c)
     GB_HIP(c, hipMalloc(&c->d_wheel, pat.size() * 4));
     GB_HIP(c, hipMemcpy(c->d_wheel, pat.data(), pat.size() * 4, hipMemcpyHostToDevice));
     c->wheel_len = L;
-    for (auto &g : c->gexec) {
-        if (g) (void)hipGraphExecDestroy(g);
-        g = nullptr;
-    }
+    c->ws.drop_graphs();
     return GB_OK;
 }
 
-gb_status ensure_host(gb_ctx *c, size_t nslots, size_t hist_words)
-{
-    if (nslots > c->h_slots_cap) {
-        ++g_buffer_generation;
-        if (c->h_slots) (void)hipHostFree(c->h_slots);
-        c->h_slots = nullptr;
-        c->h_slots_cap = 0;
-        GB_HIP(c, hipHostMalloc(reinterpret_cast<void **>(&c->h_slots), nslots * sizeof(GbSlot)));
-        c->h_slots_cap = nslots;
-    }
-    if (hist_words > c->h_hist_cap) {
-        ++g_buffer_generation;
-        if (c->h_hist) (void)hipHostFree(c->h_hist);
-        c->h_hist = nullptr;
-        c->h_hist_cap = 0;
-        GB_HIP(c, hipHostMalloc(reinterpret_cast<void **>(&c->h_hist), hist_words * 8));
-        c->h_hist_cap = hist_words;
-    }
-    if (!c->h_counters) GB_HIP(c, hipHostMalloc(reinterpret_cast<void **>(&c->h_counters), kCounters * 8));
-    return GB_OK;
-}
-
-GbTileArgs base_args(gb_ctx *c)
-{
-    GbTileArgs a{};
-    a.tile_n = c->tile_n;
-    a.halo_bits = c->halo_bits;
-    a.np_search = c->np_search;
-    a.primes = c->d_primes;
-    a.magic = c->d_magic;
-    a.k_first = c->k_first;
-    a.k_wg_end = c->k_wg_end;
-    a.k_wave_end = c->k_wave_end;
-    a.n_off = c->k_wave_end - c->k_first;
-    a.wheel = c->d_wheel;
-    a.wheel_len = c->wheel_len;
-    a.wheel_max = c->prm.wheel_max;
-    a.list = c->list.p;
-    a.list_count = c->counters.p;
-    a.list_cap = c->prm.max_unresolved;
-    a.queue = c->counters.p + 1;
-    return a;
-}
-
-GbMrArgs mr_args(gb_ctx *c)
-{
-    GbMrArgs m{};
-    m.list = c->list.p;
-    m.list_count = c->counters.p;
-    m.list_cap = c->prm.max_unresolved;
-    m.primes = c->d_primes;
-    m.ntab = c->ntab;
-    m.budget = c->prm.exhaustive_budget_p;
-    return m;
-}
-
-uint32_t mr_grid(gb_ctx *c) { return (uint32_t)std::max(64, c->num_cu * 8); }
-
-struct Plan {
-    std::vector<GbWindow> w;
-    uint64_t ntiles = 0;
-    uint64_t total_n = 0;
-};
-
-// Split windows into tiles and fill the derived window fields; returns
-// GB_ERANGE when a window reaches past the resident sieving primes.
+// Split windows into tiles and fill the derived window fields; GB_ERANGE
+// when a window reaches past the resident sieving primes.
 gb_status plan_windows(gb_ctx *c, Plan &pl)
 {
     const uint64_t T = c->tile_n;
@@ -324,14 +343,67 @@ gb_status plan_windows(gb_ctx *c, Plan &pl)
         w.tile_base = tb;
         w.out_off = off;
         const uint64_t top = w.first_n + 2 * T * nt + 1;
-        if (isqrt64(top) > c->table_limit)
+        const uint64_t r = isqrt64(top);
+        if (r > c->table_limit)
             return fail(c, GB_ERANGE, "window top beyond the resident sieving primes (raise max_hi)");
-        w.np_sieve = count_sq_le(c->h_primes, top);
+        w.np_sieve = count_le(c->h_primes, r);
         tb += nt;
         off += w.count;
     }
     pl.ntiles = tb;
     pl.total_n = off;
+    return GB_OK;
+}
+
+gb_status ensure_workspace(gb_ctx *c, Workspace &ws, const Plan &pl, size_t nslots, size_t hist_rows)
+{
+    GB_HIP(c, ws.win.ensure(pl.w.size()));
+    GB_HIP(c, ws.slots.ensure(nslots));
+    GB_HIP(c, ws.hist.ensure(hist_rows * GB_HIST_BINS_I));
+    GB_HIP(c, ws.recs.ensure(std::max<uint64_t>(pl.ntiles, 1)));
+    GB_HIP(c, ws.h_slots.ensure(nslots));
+    GB_HIP(c, ws.h_hist.ensure(hist_rows * GB_HIST_BINS_I));
+    return GB_OK;
+}
+
+gb_status run_job(gb_ctx *c, Workspace &ws, const Job &j, const GraphKey &key, bool use_graph, hipStream_t st)
+{
+    if (!use_graph) {
+        gb_status s = enqueue_init(c, ws, j, st);
+        if (s != GB_OK) return s;
+        GB_HIP(c, hipEventRecord(ws.evt0, st));
+        s = enqueue_tiles(c, ws, j, st);
+        if (s != GB_OK) return s;
+        GB_HIP(c, hipEventRecord(ws.evt1, st));
+        return enqueue_rest(c, ws, j, st);
+    }
+    if (!(ws.gexec[0] && ws.gkey == key)) {
+        ws.drop_graphs();
+        const PhaseFn fns[3] = {enqueue_init, enqueue_tiles, enqueue_rest};
+        for (int i = 0; i < 3; ++i) {
+            const gb_status s = capture(c, ws, fns[i], j, &ws.gexec[i]);
+            if (s != GB_OK) {
+                ws.drop_graphs();
+                return s;
+            }
+        }
+        ws.gkey = key;
+    }
+    GB_HIP(c, hipGraphLaunch(ws.gexec[0], st));
+    GB_HIP(c, hipEventRecord(ws.evt0, st));
+    GB_HIP(c, hipGraphLaunch(ws.gexec[1], st));
+    GB_HIP(c, hipEventRecord(ws.evt1, st));
+    GB_HIP(c, hipGraphLaunch(ws.gexec[2], st));
+    return GB_OK;
+}
+
+gb_status enqueue_queries(gb_ctx *c, Workspace &ws, uint64_t k, const unsigned long long *dn,
+                          unsigned long long *dp, hipStream_t st)
+{
+    GB_HIP(c, gb_launch_make_queries(ws.list.p, dn, k, ws.counters.p, st));
+    const GbMrArgs m = mr_args(c, ws);
+    GB_HIP(c, gb_launch_mr(m, (uint32_t)std::min<uint64_t>(mr_grid(c), (k + 3) / 4), st));
+    GB_HIP(c, gb_launch_finish_queries(ws.list.p, k, dp, st));
     return GB_OK;
 }
 
@@ -350,160 +422,23 @@ void merge_slot(gb_summary &acc, const GbSlot &s)
     }
 }
 
-// The computation for the windows already uploaded to c->win, in three
-// stream-ordered phases: (1) zero the summaries and counters; (2) the tile
-// kernel -- one launch per window, or one persistent launch over all tiles;
-// (3) the exhaustive phase, the argmax pass and the copies of the summaries
-// into pinned host memory.
-struct Job {
-    const Plan *pl;
-    size_t nslots, hist_rows;
-    void *pmin_dev;
-    int pmin_bits;
-    bool persistent;
-};
+}  // namespace gbrt
 
-gb_status enqueue_init(gb_ctx *c, const Job &j, hipStream_t st)
-{
-    GB_HIP(c, gb_launch_init(c->slots.p, j.nslots, c->hist.p, j.hist_rows * GB_HIST_BINS_I,
-                             c->counters.p, kCounters, st));
-    return GB_OK;
-}
+using namespace gbrt;
 
-gb_status enqueue_tiles(gb_ctx *c, const Job &j, hipStream_t st)
-{
-    GbTileArgs a = base_args(c);
-    a.slots = c->slots.p;
-    a.hist = c->hist.p;
-    a.hist_per_slot = j.hist_rows > 1 ? 1u : 0u;
-    a.recs = c->recs.p;
-    a.pmin = j.pmin_dev;
-    const Plan &pl = *j.pl;
-    if (j.persistent) {
-        a.win = c->win.p;
-        a.nwin = (uint32_t)pl.w.size();
-        a.ntiles = pl.ntiles;
-        const uint64_t g = std::min<uint64_t>(pl.ntiles, (uint64_t)c->num_cu * c->occupancy);
-        GB_HIP(c, gb_launch_tiles(a, (uint32_t)g, c->threads, c->lds, j.pmin_bits, true, false, st));
-    } else {
-        for (size_t i = 0; i < pl.w.size(); ++i) {
-            GbTileArgs b = a;
-            b.win = c->win.p + i;
-            b.nwin = 1;
-            b.tile0 = pl.w[i].tile_base;
-            const uint64_t nt = (pl.w[i].count + c->tile_n - 1) / c->tile_n;
-            GB_HIP(c, gb_launch_tiles(b, (uint32_t)nt, c->threads, c->lds, j.pmin_bits, false, false, st));
-        }
-    }
-    return GB_OK;
-}
-
-gb_status enqueue_rest(gb_ctx *c, const Job &j, hipStream_t st)
-{
-    GbMrArgs m = mr_args(c);
-    m.pmin = j.pmin_dev;
-    m.pmin_bits = (uint32_t)j.pmin_bits;
-    m.slots = c->slots.p;
-    m.hist = c->hist.p;
-    m.hist_per_slot = j.hist_rows > 1 ? 1u : 0u;
-    GB_HIP(c, gb_launch_mr(m, mr_grid(c), st));
-    GB_HIP(c, gb_launch_argmax(c->slots.p, c->recs.p, j.pl->ntiles, c->list.p, c->counters.p,
-                               c->prm.max_unresolved, st));
-    GB_HIP(c, hipMemcpyAsync(c->h_slots, c->slots.p, j.nslots * sizeof(GbSlot), hipMemcpyDeviceToHost, st));
-    GB_HIP(c, hipMemcpyAsync(c->h_hist, c->hist.p, j.hist_rows * GB_HIST_BINS_I * 8,
-                             hipMemcpyDeviceToHost, st));
-    GB_HIP(c, hipMemcpyAsync(c->h_counters, c->counters.p, kCounters * 8, hipMemcpyDeviceToHost, st));
-    return GB_OK;
-}
-
-using PhaseFn = gb_status (*)(gb_ctx *, const Job &, hipStream_t);
-
-// Capture one phase into an executable graph.
-gb_status capture(gb_ctx *c, PhaseFn fn, const Job &j, hipGraphExec_t *out)
-{
-    hipStream_t cap = nullptr;
-    GB_HIP(c, hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
-    hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeRelaxed);
-    if (e != hipSuccess) {
-        (void)hipStreamDestroy(cap);
-        return fail(c, GB_EDEVICE, std::string("hipStreamBeginCapture: ") + hipGetErrorString(e));
-    }
-    gb_status s = fn(c, j, cap);
-    hipGraph_t g = nullptr;
-    e = hipStreamEndCapture(cap, &g);
-    (void)hipStreamDestroy(cap);
-    if (s != GB_OK) {
-        if (g) (void)hipGraphDestroy(g);
-        return s;
-    }
-    GB_HIP(c, e);
-    e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
-    (void)hipGraphDestroy(g);
-    GB_HIP(c, e);
-    return GB_OK;
-}
-
-void drop_graphs(gb_ctx *c)
-{
-    for (auto &g : c->gexec)
-        if (g) (void)hipGraphExecDestroy(g);
-    for (auto &g : c->gexec) g = nullptr;
-}
-
-// Run the three phases on `st`, with events c->evt0/evt1 around the tile
-// phase.  With use_graph, each phase is a cached executable graph, captured
-// on first use and replayed while the key (shapes and buffer addresses) holds.
-gb_status run_job(gb_ctx *c, const Job &j, const GraphKey &key, bool use_graph, hipStream_t st)
-{
-    if (!use_graph) {
-        gb_status s = enqueue_init(c, j, st);
-        if (s != GB_OK) return s;
-        GB_HIP(c, hipEventRecord(c->evt0, st));
-        s = enqueue_tiles(c, j, st);
-        if (s != GB_OK) return s;
-        GB_HIP(c, hipEventRecord(c->evt1, st));
-        return enqueue_rest(c, j, st);
-    }
-    if (!(c->gexec[0] && c->gkey == key)) {
-        drop_graphs(c);
-        const PhaseFn fns[3] = {enqueue_init, enqueue_tiles, enqueue_rest};
-        for (int i = 0; i < 3; ++i) {
-            gb_status s = capture(c, fns[i], j, &c->gexec[i]);
-            if (s != GB_OK) {
-                drop_graphs(c);
-                return s;
-            }
-        }
-        c->gkey = key;
-    }
-    GB_HIP(c, hipGraphLaunch(c->gexec[0], st));
-    GB_HIP(c, hipEventRecord(c->evt0, st));
-    GB_HIP(c, hipGraphLaunch(c->gexec[1], st));
-    GB_HIP(c, hipEventRecord(c->evt1, st));
-    GB_HIP(c, hipGraphLaunch(c->gexec[2], st));
-    return GB_OK;
-}
-
-gb_status ensure_device(gb_ctx *c, const Plan &pl, size_t nslots, size_t hist_rows)
-{
-    GB_HIP(c, c->win.ensure(pl.w.size()));
-    GB_HIP(c, c->slots.ensure(nslots));
-    GB_HIP(c, c->hist.ensure(hist_rows * GB_HIST_BINS_I));
-    GB_HIP(c, c->recs.ensure(std::max<uint64_t>(pl.ntiles, 1)));
-    return ensure_host(c, nslots, hist_rows * GB_HIST_BINS_I);
-}
+namespace {
 
 gb_status finish_list(gb_ctx *c)
 {
     c->last_list_valid = false;
-    const uint64_t cnt = c->h_counters[0];
+    const uint64_t cnt = c->ws.h_counters.p[0];
     if (cnt > c->prm.max_unresolved)
         return fail(c, GB_ENOMEM,
                     "exhaustive list overflow: " + std::to_string(cnt) + " n left by the fast path, capacity " +
                         std::to_string(c->prm.max_unresolved) + " (raise max_unresolved or pmax)");
     c->last_list.resize(cnt);
     if (cnt)
-        GB_HIP(c, hipMemcpy(c->last_list.data(), c->list.p, cnt * sizeof(GbExh), hipMemcpyDeviceToHost));
+        GB_HIP(c, hipMemcpy(c->last_list.data(), c->ws.list.p, cnt * sizeof(GbExh), hipMemcpyDeviceToHost));
     c->last_list_valid = true;
     return GB_OK;
 }
@@ -514,13 +449,13 @@ gb_status run_range(gb_ctx *c, uint64_t lo, uint64_t hi, gb_result *res, void *s
     if (hi > GB_MAX_N) return fail(c, GB_EINVAL, "hi above 2^63");
     if (hi > c->prm.max_hi) return fail(c, GB_ERANGE, "hi above the context's max_hi");
     hipStream_t st = static_cast<hipStream_t>(stream);
+    Workspace &ws = c->ws;
     if (lo < 4) lo = 4;
     if (lo & 1) ++lo;
     if (hi & 1) --hi;
     res->count = res->max_p = res->argmax_n = res->checksum = 0;
     res->n_exhaustive = res->n_failed = res->first_failed_n = res->n_segments = 0;
-    res->device_ms = 0;
-    res->tile_ms = 0;
+    res->device_ms = res->tile_ms = 0;
     res->tile_launches = 0;
     if (res->hist) std::memset(res->hist, 0, GB_HIST_BINS * 8);
     if (lo > hi) return GB_OK;
@@ -529,8 +464,7 @@ gb_status run_range(gb_ctx *c, uint64_t lo, uint64_t hi, gb_result *res, void *s
     const uint64_t C = (hi - lo) / 2 + 1;
     const uint64_t S = 1ull << c->prm.seg_log2;
     const uint64_t nseg = (C + S - 1) / S;
-    if (res->seg_hist && res->seg_hist_rows < nseg)
-        return fail(c, GB_EINVAL, "seg_hist has fewer rows than segments");
+    if (res->seg_hist && res->seg_hist_rows < nseg) return fail(c, GB_EINVAL, "seg_hist has fewer rows than segments");
     Plan pl;
     pl.w.resize(nseg);
     for (uint64_t s = 0; s < nseg; ++s) {
@@ -541,7 +475,7 @@ gb_status run_range(gb_ctx *c, uint64_t lo, uint64_t hi, gb_result *res, void *s
     gb_status stt = plan_windows(c, pl);
     if (stt != GB_OK) return stt;
     const size_t hist_rows = res->seg_hist ? nseg : 1;
-    stt = ensure_device(c, pl, nseg, hist_rows);
+    stt = ensure_workspace(c, ws, pl, nseg, hist_rows);
     if (stt != GB_OK) return stt;
     const int pb = res->pmin ? (int)res->pmin_bits : 0;
     void *pmin_dev = nullptr;
@@ -549,36 +483,40 @@ gb_status run_range(gb_ctx *c, uint64_t lo, uint64_t hi, gb_result *res, void *s
         if (res->pmin_on_device) {
             pmin_dev = res->pmin;
         } else {
-            GB_HIP(c, c->pmin_tmp.ensure(C * (pb / 8)));
-            pmin_dev = c->pmin_tmp.p;
+            GB_HIP(c, ws.pmin.ensure(C * (pb / 8)));
+            pmin_dev = ws.pmin.p;
         }
     }
-    GB_HIP(c, hipMemcpyAsync(c->win.p, pl.w.data(), nseg * sizeof(GbWindow), hipMemcpyHostToDevice, st));
-    GB_HIP(c, hipEventRecord(c->ev0, st));
-    {
-        GraphKey key;
-        key.generation = g_buffer_generation;
-        key.kind = 1;
-        key.nseg = nseg;
-        key.ntiles = pl.ntiles;
-        key.hist_rows = hist_rows;
-        key.pmin = pmin_dev;
-        key.pmin_bits = pb;
-        key.stream = st;
-        Job j{&pl, (size_t)nseg, hist_rows, pmin_dev, pb, batched};
-        stt = run_job(c, j, key, batched, st);
-        if (stt != GB_OK) return stt;
-    }
-    GB_HIP(c, hipEventRecord(c->ev1, st));
+    GB_HIP(c, hipMemcpyAsync(ws.win.p, pl.w.data(), nseg * sizeof(GbWindow), hipMemcpyHostToDevice, st));
+    GB_HIP(c, hipEventRecord(ws.ev0, st));
+    GraphKey key;
+    key.generation = g_buffer_generation.load();
+    key.kind = 1;
+    key.nwin = nseg;
+    key.ntiles = pl.ntiles;
+    key.hist_rows = hist_rows;
+    key.pmin = pmin_dev;
+    key.pmin_bits = pb;
+    key.stream = st;
+    Job j;
+    j.pl = &pl;
+    j.nslots = nseg;
+    j.hist_rows = hist_rows;
+    j.pmin_dev = pmin_dev;
+    j.pmin_bits = pb;
+    j.persistent = batched;
+    stt = run_job(c, ws, j, key, batched, st);
+    if (stt != GB_OK) return stt;
+    GB_HIP(c, hipEventRecord(ws.ev1, st));
     GB_HIP(c, hipStreamSynchronize(st));
     float ms = 0;
-    GB_HIP(c, hipEventElapsedTime(&ms, c->ev0, c->ev1));
+    GB_HIP(c, hipEventElapsedTime(&ms, ws.ev0, ws.ev1));
     res->device_ms = ms;
-    GB_HIP(c, hipEventElapsedTime(&ms, c->evt0, c->evt1));
+    GB_HIP(c, hipEventElapsedTime(&ms, ws.evt0, ws.evt1));
     res->tile_ms = ms;
     res->tile_launches = batched ? 1 : nseg;
     gb_summary tot{};
-    for (uint64_t s = 0; s < nseg; ++s) merge_slot(tot, c->h_slots[s]);
+    for (uint64_t s = 0; s < nseg; ++s) merge_slot(tot, ws.h_slots.p[s]);
     res->count = tot.count;
     res->max_p = tot.max_p;
     res->argmax_n = tot.argmax_n;
@@ -587,12 +525,10 @@ gb_status run_range(gb_ctx *c, uint64_t lo, uint64_t hi, gb_result *res, void *s
     res->n_failed = tot.n_failed;
     res->first_failed_n = tot.first_failed_n;
     res->n_segments = nseg;
-    if (res->hist) {
+    if (res->hist)
         for (size_t r = 0; r < hist_rows; ++r)
-            for (uint32_t i = 0; i < GB_HIST_BINS; ++i) res->hist[i] += c->h_hist[r * GB_HIST_BINS_I + i];
-    }
-    if (res->seg_hist)
-        std::memcpy(res->seg_hist, c->h_hist, nseg * GB_HIST_BINS_I * 8);
+            for (uint32_t i = 0; i < GB_HIST_BINS; ++i) res->hist[i] += ws.h_hist.p[r * GB_HIST_BINS_I + i];
+    if (res->seg_hist) std::memcpy(res->seg_hist, ws.h_hist.p, nseg * GB_HIST_BINS_I * 8);
     stt = finish_list(c);
     if (stt != GB_OK) return stt;
     if (res->pmin && !res->pmin_on_device)
@@ -644,25 +580,9 @@ gb_status gb_create(gb_ctx **out, const gb_params *prm)
         return s;
     };
     if (hipSetDevice(c->prm.device) != hipSuccess) return bail(GB_EDEVICE);
-    // resident table: odd primes up to sqrt(max_hi + slack), at least 2^16 + a margin
-    uint64_t lim = isqrt64(c->prm.max_hi + (1ull << 30)) + 2;
-    lim = std::max<uint64_t>(lim, 70000);
-    c->h_primes = host_odd_primes(lim);
-    c->table_limit = lim;
-    c->ntab = c->h_primes.size();
-    std::vector<unsigned long long> magic(c->ntab);
-    for (uint64_t i = 0; i < c->ntab; ++i) magic[i] = ~0ull / c->h_primes[i];
-    if (hipMalloc(&c->d_primes, c->ntab * 4) != hipSuccess) return bail(GB_ENOMEM);
-    if (hipMalloc(&c->d_magic, c->ntab * 8) != hipSuccess) return bail(GB_ENOMEM);
-    if (hipMemcpy(c->d_primes, c->h_primes.data(), c->ntab * 4, hipMemcpyHostToDevice) != hipSuccess)
-        return bail(GB_EDEVICE);
-    if (hipMemcpy(c->d_magic, magic.data(), c->ntab * 8, hipMemcpyHostToDevice) != hipSuccess)
-        return bail(GB_EDEVICE);
-    if (c->list.ensure(c->prm.max_unresolved) != hipSuccess) return bail(GB_ENOMEM);
-    if (c->counters.ensure(kCounters) != hipSuccess) return bail(GB_ENOMEM);
-    if (hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess ||
-        hipEventCreate(&c->evt0) != hipSuccess || hipEventCreate(&c->evt1) != hipSuccess)
-        return bail(GB_EDEVICE);
+    st = build_tables(c);
+    if (st != GB_OK) return bail(st);
+    if (c->ws.init(c->prm.max_unresolved) != hipSuccess) return bail(GB_ENOMEM);
     st = setup_geometry(c);
     if (st != GB_OK) return bail(st);
     *out = c;
@@ -674,26 +594,8 @@ void gb_destroy(gb_ctx *c)
     if (!c) return;
     (void)hipSetDevice(c->prm.device);
     (void)hipDeviceSynchronize();
-    for (auto &g : c->gexec)
-        if (g) (void)hipGraphExecDestroy(g);
-    if (c->d_primes) (void)hipFree(c->d_primes);
-    if (c->d_magic) (void)hipFree(c->d_magic);
-    if (c->d_wheel) (void)hipFree(c->d_wheel);
-    c->win.release();
-    c->slots.release();
-    c->hist.release();
-    c->recs.release();
-    c->list.release();
-    c->counters.release();
-    c->pmin_tmp.release();
-    c->q_tmp.release();
-    if (c->h_slots) (void)hipHostFree(c->h_slots);
-    if (c->h_hist) (void)hipHostFree(c->h_hist);
-    if (c->h_counters) (void)hipHostFree(c->h_counters);
-    if (c->ev0) (void)hipEventDestroy(c->ev0);
-    if (c->ev1) (void)hipEventDestroy(c->ev1);
-    if (c->evt0) (void)hipEventDestroy(c->evt0);
-    if (c->evt1) (void)hipEventDestroy(c->evt1);
+    c->ws.release();
+    free_tables(c);
     delete c;
 }
 
@@ -724,6 +626,7 @@ gb_status gb_verify_windows(gb_ctx *c, const gb_window *w, size_t k, uint16_t *p
     if (!c || (!w && k)) return fail(c, GB_EINVAL, "null context or windows");
     if (hipSetDevice(c->prm.device) != hipSuccess) return fail(c, GB_EDEVICE, "hipSetDevice failed");
     hipStream_t st = static_cast<hipStream_t>(stream);
+    Workspace &ws = c->ws;
     if (hist) std::memset(hist, 0, GB_HIST_BINS * 8);
     if (k == 0) return GB_OK;
     if (k > 0xFFFFFFFFull) return fail(c, GB_EINVAL, "too many windows");
@@ -741,36 +644,40 @@ gb_status gb_verify_windows(gb_ctx *c, const gb_window *w, size_t k, uint16_t *p
     }
     gb_status stt = plan_windows(c, pl);
     if (stt != GB_OK) return stt;
-    stt = ensure_device(c, pl, k, 1);
+    stt = ensure_workspace(c, ws, pl, k, 1);
     if (stt != GB_OK) return stt;
-    GB_HIP(c, hipMemcpyAsync(c->win.p, pl.w.data(), k * sizeof(GbWindow), hipMemcpyHostToDevice, st));
-    GB_HIP(c, hipEventRecord(c->ev0, st));
-    {
-        GraphKey key;
-        key.generation = g_buffer_generation;
-        key.kind = 2;
-        key.nseg = k;
-        key.ntiles = pl.ntiles;
-        key.hist_rows = 1;
-        key.pmin = pmin;
-        key.pmin_bits = pmin ? 16 : 0;
-        key.stream = st;
-        Job j{&pl, k, 1, pmin, pmin ? 16 : 0, true};
-        stt = run_job(c, j, key, true, st);
-        if (stt != GB_OK) return stt;
-    }
-    GB_HIP(c, hipEventRecord(c->ev1, st));
+    GB_HIP(c, hipMemcpyAsync(ws.win.p, pl.w.data(), k * sizeof(GbWindow), hipMemcpyHostToDevice, st));
+    GB_HIP(c, hipEventRecord(ws.ev0, st));
+    GraphKey key;
+    key.generation = g_buffer_generation.load();
+    key.kind = 2;
+    key.nwin = k;
+    key.ntiles = pl.ntiles;
+    key.hist_rows = 1;
+    key.pmin = pmin;
+    key.pmin_bits = pmin ? 16 : 0;
+    key.stream = st;
+    Job j;
+    j.pl = &pl;
+    j.nslots = k;
+    j.hist_rows = 1;
+    j.pmin_dev = pmin;
+    j.pmin_bits = pmin ? 16 : 0;
+    j.persistent = true;
+    stt = run_job(c, ws, j, key, true, st);
+    if (stt != GB_OK) return stt;
+    GB_HIP(c, hipEventRecord(ws.ev1, st));
     GB_HIP(c, hipStreamSynchronize(st));
     gb_status fin = GB_OK;
     for (size_t i = 0; i < k; ++i) {
         gb_summary s{};
-        merge_slot(s, c->h_slots[i]);
+        merge_slot(s, ws.h_slots.p[i]);
         if (sums) sums[i] = s;
         if (s.n_failed) fin = GB_EUNRESOLVED;
         if (s.count != w[i].len) return fail(c, GB_EDEVICE, "internal: window count mismatch");
     }
     if (hist)
-        for (uint32_t i = 0; i < GB_HIST_BINS; ++i) hist[i] = c->h_hist[i];
+        for (uint32_t i = 0; i < GB_HIST_BINS; ++i) hist[i] = ws.h_hist.p[i];
     stt = finish_list(c);
     if (stt != GB_OK) return stt;
     if (fin != GB_OK) return fail(c, fin, "n without a partition within the budget");
@@ -783,6 +690,7 @@ gb_status gb_verify_many(gb_ctx *c, const uint64_t *n, uint64_t *p, size_t k, in
     if (hipSetDevice(c->prm.device) != hipSuccess) return fail(c, GB_EDEVICE, "hipSetDevice failed");
     if (k == 0) return GB_OK;
     hipStream_t st = static_cast<hipStream_t>(stream);
+    Workspace &ws = c->ws;
     if (k > c->prm.max_unresolved) return fail(c, GB_ENOMEM, "more queries than max_unresolved");
     const unsigned long long *dn = reinterpret_cast<const unsigned long long *>(n);
     unsigned long long *dp = reinterpret_cast<unsigned long long *>(p);
@@ -791,10 +699,10 @@ gb_status gb_verify_many(gb_ctx *c, const uint64_t *n, uint64_t *p, size_t k, in
         for (size_t i = 0; i < k; ++i)
             if (n[i] < 4 || (n[i] & 1) || n[i] > GB_MAX_N)
                 return fail(c, GB_EINVAL, "n must be even with 4 <= n <= 2^63");
-        GB_HIP(c, c->q_tmp.ensure(2 * k));
-        GB_HIP(c, hipMemcpyAsync(c->q_tmp.p, n, k * 8, hipMemcpyHostToDevice, st));
-        dn = c->q_tmp.p;
-        dp = c->q_tmp.p + k;
+        GB_HIP(c, ws.q.ensure(2 * k));
+        GB_HIP(c, hipMemcpyAsync(ws.q.p, n, k * 8, hipMemcpyHostToDevice, st));
+        dn = ws.q.p;
+        dp = ws.q.p + k;
     } else {
         hn.resize(k);
         GB_HIP(c, hipMemcpyAsync(hn.data(), n, k * 8, hipMemcpyDeviceToHost, st));
@@ -803,10 +711,8 @@ gb_status gb_verify_many(gb_ctx *c, const uint64_t *n, uint64_t *p, size_t k, in
             if (hn[i] < 4 || (hn[i] & 1) || hn[i] > GB_MAX_N)
                 return fail(c, GB_EINVAL, "n must be even with 4 <= n <= 2^63");
     }
-    GB_HIP(c, gb_launch_make_queries(c->list.p, dn, k, c->counters.p, st));
-    GbMrArgs m = mr_args(c);
-    GB_HIP(c, gb_launch_mr(m, (uint32_t)std::min<uint64_t>(mr_grid(c), (k + 3) / 4), st));
-    GB_HIP(c, gb_launch_finish_queries(c->list.p, k, dp, st));
+    gb_status stt = enqueue_queries(c, ws, k, dn, dp, st);
+    if (stt != GB_OK) return stt;
     std::vector<uint64_t> hp(k);
     GB_HIP(c, hipMemcpyAsync(hp.data(), dp, k * 8, hipMemcpyDeviceToHost, st));
     GB_HIP(c, hipStreamSynchronize(st));
@@ -826,9 +732,11 @@ gb_status gb_verify_one(gb_ctx *c, uint64_t n, uint64_t *p, void *stream)
 gb_status gb_sieve_window(gb_ctx *c, uint64_t w0, uint64_t nbits, uint32_t *bits, void *stream)
 {
     if (!c || !bits) return fail(c, GB_EINVAL, "null argument");
-    if (!(w0 & 1) || nbits == 0 || (nbits & 63)) return fail(c, GB_EINVAL, "w0 must be odd, nbits a positive multiple of 64");
+    if (!(w0 & 1) || nbits == 0 || (nbits & 63))
+        return fail(c, GB_EINVAL, "w0 must be odd, nbits a positive multiple of 64");
     if (hipSetDevice(c->prm.device) != hipSuccess) return fail(c, GB_EDEVICE, "hipSetDevice failed");
     hipStream_t st = static_cast<hipStream_t>(stream);
+    Workspace &ws = c->ws;
     const uint64_t top = w0 + 2 * nbits;
     if (top < w0 || top > c->prm.max_hi) return fail(c, GB_ERANGE, "window above the context's max_hi");
     Plan pl;
@@ -838,11 +746,11 @@ gb_status gb_sieve_window(gb_ctx *c, uint64_t w0, uint64_t nbits, uint32_t *bits
     pl.w[0].slot = 0;
     gb_status stt = plan_windows(c, pl);
     if (stt != GB_OK) return stt;
-    stt = ensure_device(c, pl, 1, 1);
+    stt = ensure_workspace(c, ws, pl, 1, 1);
     if (stt != GB_OK) return stt;
-    GB_HIP(c, hipMemcpyAsync(c->win.p, pl.w.data(), sizeof(GbWindow), hipMemcpyHostToDevice, st));
-    GbTileArgs a = base_args(c);
-    a.win = c->win.p;
+    GB_HIP(c, hipMemcpyAsync(ws.win.p, pl.w.data(), sizeof(GbWindow), hipMemcpyHostToDevice, st));
+    GbTileArgs a = base_args(c, ws);
+    a.win = ws.win.p;
     a.nwin = 1;
     a.tile0 = 0;
     a.sieve_out = bits;
@@ -868,8 +776,3 @@ gb_status gb_exhaustive_list(gb_ctx *c, uint64_t *n, uint64_t *p, size_t cap, si
 }
 
 }  // extern "C"
-
-extern "C" gb_status gb_autotune(gb_ctx *c, const gb_window *, size_t, const char *, gb_params *)
-{
-    return fail(c, GB_EINVAL, "autotuner not built yet");
-}

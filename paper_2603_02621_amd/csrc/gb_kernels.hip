@@ -90,12 +90,16 @@ __device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long v)
 }
 
 // LDS carve-up of one tile workgroup (offsets in 32-bit words).
+constexpr uint32_t QCAP = 128;  // hit-queue entries per wave
+
 struct TileLds {
     uint32_t *bits;           // (T + HB)/32 words: the tile's window, 1 = prime
     uint16_t *hh;             // (p+1)/2 of the odd primes p <= P_max, padded by 4
     uint32_t *lhist;          // per-prime hit counts of this tile
     uint32_t *offs;           // first bit index of each small/medium sieving prime
     unsigned long long *red;  // 3 * waves
+    unsigned long long *qhit; // per wave: QCAP hit masks
+    uint32_t *qtag;           // per wave: QCAP (prime index | block << 16)
 };
 
 __device__ __forceinline__ TileLds carve(uint32_t *smem, const GbTileArgs &a)
@@ -112,6 +116,10 @@ __device__ __forceinline__ TileLds carve(uint32_t *smem, const GbTileArgs &a)
     o += a.n_off;
     o = (o + 1) & ~1u;
     L.red = reinterpret_cast<unsigned long long *>(smem + o);
+    o += 2 * 3 * (blockDim.x / 64);
+    L.qhit = reinterpret_cast<unsigned long long *>(smem + o);
+    o += 2 * QCAP * (blockDim.x / 64);
+    L.qtag = smem + o;
     return L;
 }
 
@@ -238,29 +246,65 @@ __device__ void process_tile(const GbTileArgs &a, unsigned long long g, const Ti
     unsigned long long cs = 0;         // lane's checksum part
     uint32_t nexh = 0;                 // n left to the exhaustive phase
 
-    // block state: unresolved mask U, next prime index k, the block's sums
-    // of p*popcount(hit) (Ab) and p*(positions of hit) (Bb), and its last hit
-    // (the last hit carries the block's largest p_min)
-    uint32_t b = tid, k = 0, Ulo = 0, Uhi = 0, Ab = 0, Bb = 0, lastp = 0, llo = 0, lhi = 0;
+    // Hits are compacted into a per-wave LDS queue (ballot + mbcnt) and their
+    // bookkeeping -- histogram, checksum, per-n output -- runs 64 events at
+    // a time with every lane busy, instead of on every probe for the lanes
+    // that happen to hit.  Checksum part of one event (block bb, prime p, hit
+    // mask h): p * sum_{j in h} (N0/2 + 64 bb + j) = N0/2 * (p popc h)
+    // + p * (64 bb popc h + sum of positions of h); the two sums are kept
+    // apart (cA, cB) and joined at the tile's end.
+    unsigned long long cA = 0, cB = 0;
+    unsigned long long *qhit = L.qhit + wave * QCAP;
+    uint32_t *qtag = L.qtag + wave * QCAP;
+    uint32_t qn = 0;  // wave-uniform queue length
+    auto drain = [&](uint32_t first, uint32_t nev) {
+        __builtin_amdgcn_wave_barrier();
+        if (lane < nev) {
+            const uint32_t tag = qtag[first + lane];
+            const unsigned long long hm = qhit[first + lane];
+            const uint32_t hlo = (uint32_t)hm, hhi = (uint32_t)(hm >> 32);
+            const uint32_t kk = tag & 0xFFFFu, bb = tag >> 16;
+            const uint32_t p = 2u * L.hh[kk] - 1u;
+            const uint32_t pc = __popc(hlo) + __popc(hhi);
+            atomicAdd(&L.lhist[kk], pc);
+            cA += (unsigned long long)(p * pc);
+            cB += (unsigned long long)p * (pc * (64u * bb) + bitpos_sum(hlo, hhi));
+            if constexpr (PB != 0) {
+                if (a.pmin) {
+                    unsigned long long hb = hm;
+                    const unsigned long long ob = outb + 64ull * bb;
+                    while (hb) {
+                        store_p<PB>(a.pmin, ob + (unsigned long long)__builtin_ctzll(hb), p);
+                        hb &= hb - 1ull;
+                    }
+                }
+            }
+        }
+        __builtin_amdgcn_wave_barrier();
+    };
+
+    // block state: unresolved mask U, next prime index k, and the block's
+    // last hit (its (p+1)/2 and mask), which carries the block's largest p_min
+    uint32_t b = tid, k = 0, Ulo = 0, Uhi = 0, lasth = 0, llo = 0, lhi = 0;
     uint32_t base = 0;
     auto start_block = [&](uint32_t bb) {
         const uint32_t nv = min(64u, cnt - 64u * bb);
         Ulo = nv >= 32 ? ~0u : ((1u << nv) - 1u);
         Uhi = nv >= 64 ? ~0u : (nv > 32 ? ((1u << (nv - 32)) - 1u) : 0u);
-        k = 0; Ab = 0; Bb = 0; lastp = 0; llo = 0; lhi = 0;
+        k = 0; lasth = 0; llo = 0; lhi = 0;
         base = 64u * bb + HB;
         if (N0 == 4 && bb == 0) {  // n = 4 = 2 + 2, the one even p_min
             Ulo &= ~1u;
-            Ab = 2;
-            lastp = 2; llo = 1u;
+            cA += 2;                // (n/2 = 2) * (p = 2) = N0/2 * 2
             atomicAdd(&hist[0], 1ull);
+            if (maxp < 2) { maxp = 2; amax = 0; }
             if (a.pmin) store_p<PB>(a.pmin, outb, 2u);
         }
     };
     auto finish_block = [&]() {
-        cs += (half0 + 64ull * b) * Ab + Bb;
-        if (lastp > maxp) {
-            maxp = lastp;
+        const uint32_t lp = lasth ? 2u * lasth - 1u : 0u;
+        if (lp > maxp) {
+            maxp = lp;
             amax = 64u * b + (llo ? (uint32_t)__builtin_ctz(llo) : 32u + (uint32_t)__builtin_ctz(lhi));
         }
         if (Ulo | Uhi) {
@@ -290,46 +334,53 @@ __device__ void process_tile(const GbTileArgs &a, unsigned long long g, const Ti
         }
     } else {
         if (b < nblk) start_block(b);
-        while (b < nblk) {
+        // the loop runs while any lane of the wave has a block, so the queue
+        // operations below stay wave-uniform
+        while (__ballot(b < nblk) != 0ull) {
+            const bool act = b < nblk;
             // four probes per exit check; the prime list is padded with copies
             // of its last prime, which cannot hit an n twice
 #pragma unroll
             for (uint32_t u = 0; u < 4; ++u) {
+                uint32_t hlo = 0, hhi = 0;
                 const uint32_t h = L.hh[k + u];
-                const uint32_t s = base - h;
-                const uint32_t *wp = L.bits + (s >> 5);
-                const uint32_t d0 = wp[0], d1 = wp[1], d2 = wp[2];
-                const uint32_t hlo = __builtin_amdgcn_alignbit(d1, d0, s) & Ulo;
-                const uint32_t hhi = __builtin_amdgcn_alignbit(d2, d1, s) & Uhi;
-                if (hlo | hhi) {
-                    const uint32_t p = 2u * h - 1u;
-                    const uint32_t pc = __popc(hlo) + __popc(hhi);
-                    Ab += p * pc;
-                    Bb += p * bitpos_sum(hlo, hhi);
-                    atomicAdd(&L.lhist[k + u], pc);
-                    lastp = p; llo = hlo; lhi = hhi;
-                    if constexpr (PB != 0) {
-                        if (a.pmin) {
-                            unsigned long long hb = ((unsigned long long)hhi << 32) | hlo;
-                            const unsigned long long ob = outb + 64ull * b;
-                            while (hb) {
-                                store_p<PB>(a.pmin, ob + (unsigned long long)__builtin_ctzll(hb), p);
-                                hb &= hb - 1ull;
-                            }
-                        }
-                    }
+                if (act) {
+                    const uint32_t s = base - h;
+                    const uint32_t *wp = L.bits + (s >> 5);
+                    const uint32_t d0 = wp[0], d1 = wp[1], d2 = wp[2];
+                    hlo = __builtin_amdgcn_alignbit(d1, d0, s) & Ulo;
+                    hhi = __builtin_amdgcn_alignbit(d2, d1, s) & Uhi;
+                }
+                const bool hit = (hlo | hhi) != 0u;
+                const unsigned long long m = __ballot(hit);
+                if (hit) {
+                    const uint32_t slot_q = qn + __builtin_amdgcn_mbcnt_hi(
+                        (uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+                    qtag[slot_q] = (k + u) | (b << 16);
+                    qhit[slot_q] = ((unsigned long long)hhi << 32) | hlo;
+                    lasth = h; llo = hlo; lhi = hhi;
                     Ulo ^= hlo;
                     Uhi ^= hhi;
                 }
+                qn += (uint32_t)__popcll(m);
+                if (qn >= 64u) {
+                    qn -= 64u;
+                    drain(qn, 64u);
+                }
             }
-            k += 4;
-            if ((Ulo | Uhi) == 0u || k >= nps) {
-                finish_block();
-                b += NT;
-                if (b < nblk) start_block(b);
+            if (act) {
+                k += 4;
+                if ((Ulo | Uhi) == 0u || k >= nps) {
+                    finish_block();
+                    b += NT;
+                    if (b < nblk) start_block(b);
+                    else k = 0;  // idle lanes keep reading a valid list entry
+                }
             }
         }
+        if (qn) drain(0, qn);
     }
+    cs = (half0 * cA) + cB;
 
     // ---- tile summary ------------------------------------------------------
     unsigned long long key = ((unsigned long long)maxp << 32) | (0xFFFFFFFFu - amax);
@@ -646,6 +697,7 @@ size_t gb_tile_lds_bytes(uint32_t tile_n, uint32_t halo_bits, uint32_t np_search
     size_t words = (tile_n + halo_bits) / 32 + (np_search + 4 + 1) / 2 + np_search + n_off;
     words = (words + 1) & ~(size_t)1;
     words += 2 * 3 * (threads / 64);
+    words += (2 + 1) * QCAP * (threads / 64);  // hit queue: masks and tags
     return words * 4;
 }
 

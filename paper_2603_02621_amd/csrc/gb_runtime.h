@@ -1,0 +1,171 @@
+// gb_runtime.h -- host-side runtime state shared by the C-ABI entry points
+// (gb_host.hip) and the serving loop (gb_server.hip).  Not a public header.
+#pragma once
+#include <atomic>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/goldbach.h"
+#include "gb_internal.h"
+
+namespace gbrt {
+
+constexpr uint64_t kDefaultMaxHi = 1ull << 50;
+constexpr uint32_t kCounters = 4;  // [0] exhaustive-list length, [1] work queue
+
+// Every move of a device or pinned scratch buffer bumps this, so a cached
+// HIP graph that captured the old addresses is never replayed.
+extern std::atomic<uint64_t> g_buffer_generation;
+
+template <class T>
+struct DevBuf {
+    T *p = nullptr;
+    size_t cap = 0;
+    hipError_t ensure(size_t n)
+    {
+        if (n <= cap && p) return hipSuccess;
+        g_buffer_generation.fetch_add(1);
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        cap = 0;
+        const size_t want = n ? n : 1;
+        hipError_t e = hipMalloc(reinterpret_cast<void **>(&p), want * sizeof(T));
+        if (e == hipSuccess) cap = want;
+        return e;
+    }
+    void release()
+    {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        cap = 0;
+    }
+};
+
+template <class T>
+struct PinBuf {
+    T *p = nullptr;
+    size_t cap = 0;
+    hipError_t ensure(size_t n)
+    {
+        if (n <= cap && p) return hipSuccess;
+        g_buffer_generation.fetch_add(1);
+        if (p) (void)hipHostFree(p);
+        p = nullptr;
+        cap = 0;
+        const size_t want = n ? n : 1;
+        hipError_t e = hipHostMalloc(reinterpret_cast<void **>(&p), want * sizeof(T));
+        if (e == hipSuccess) cap = want;
+        return e;
+    }
+    void release()
+    {
+        if (p) (void)hipHostFree(p);
+        p = nullptr;
+        cap = 0;
+    }
+};
+
+struct GraphKey {
+    uint64_t generation = 0;
+    int kind = 0;  // 1: range, 2: windows
+    uint64_t nwin = 0, ntiles = 0, hist_rows = 0;
+    void *pmin = nullptr;
+    int pmin_bits = 0;
+    hipStream_t stream = nullptr;
+    bool operator==(const GraphKey &o) const
+    {
+        return generation == o.generation && kind == o.kind && nwin == o.nwin && ntiles == o.ntiles &&
+               hist_rows == o.hist_rows && pmin == o.pmin && pmin_bits == o.pmin_bits && stream == o.stream;
+    }
+};
+
+// Per-stream scratch: everything one in-flight computation writes.
+struct Workspace {
+    DevBuf<GbWindow> win;
+    DevBuf<GbSlot> slots;
+    DevBuf<unsigned long long> hist;
+    DevBuf<GbTileRec> recs;
+    DevBuf<GbExh> list;
+    DevBuf<unsigned long long> counters;
+    DevBuf<unsigned char> pmin;          // per-n output staging
+    DevBuf<unsigned long long> q;        // single-n queries: n then p
+    PinBuf<GbSlot> h_slots;
+    PinBuf<unsigned long long> h_hist;
+    PinBuf<unsigned long long> h_counters;
+    PinBuf<unsigned long long> h_q;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr, evt0 = nullptr, evt1 = nullptr, done = nullptr;
+    hipGraphExec_t gexec[3] = {nullptr, nullptr, nullptr};  // init, tiles, rest
+    GraphKey gkey;
+    hipError_t init(uint64_t list_cap);
+    void release();
+    void drop_graphs();
+};
+
+// A list of windows split into tiles.
+struct Plan {
+    std::vector<GbWindow> w;
+    uint64_t ntiles = 0;
+    uint64_t total_n = 0;
+};
+
+// One computation over uploaded windows.
+struct Job {
+    const Plan *pl = nullptr;
+    size_t nslots = 0, hist_rows = 1;
+    void *pmin_dev = nullptr;
+    int pmin_bits = 0;
+    bool persistent = false;
+};
+
+}  // namespace gbrt
+
+struct gb_ctx {
+    gb_params prm{};
+    int num_cu = 0;
+    std::vector<uint32_t> h_primes;  // odd primes 3, 5, 7, ...
+    uint32_t *d_primes = nullptr;
+    unsigned long long *d_magic = nullptr;
+    uint64_t ntab = 0;
+    uint64_t table_limit = 0;        // every odd prime <= table_limit is in the table
+    uint32_t np_search = 0, k_first = 0, halo_bits = 0;
+    uint32_t *d_wheel = nullptr;
+    uint32_t wheel_len = 0;
+    uint32_t tile_n = 0, threads = 0;
+    uint32_t k_wg_end = 0, k_wave_end = 0;
+    size_t lds = 0;
+    int occupancy = 1;
+    gbrt::Workspace ws;              // scratch of the synchronous calls
+    std::string err;
+    std::vector<GbExh> last_list;
+    bool last_list_valid = false;
+};
+
+namespace gbrt {
+
+gb_status fail(gb_ctx *c, gb_status st, const std::string &msg);
+uint64_t isqrt64(uint64_t x);
+gb_status apply_params(gb_ctx *c, const gb_params *in);
+gb_status setup_geometry(gb_ctx *c);
+gb_status build_tables(gb_ctx *c);
+void free_tables(gb_ctx *c);
+gb_status plan_windows(gb_ctx *c, Plan &pl);
+gb_status ensure_workspace(gb_ctx *c, Workspace &ws, const Plan &pl, size_t nslots, size_t hist_rows);
+// init + tiles + exhaustive phase + argmax + summary copies, on `st`,
+// with ws.evt0/evt1 around the tile launches; with use_graph each phase is a
+// cached executable graph keyed by `key`.
+gb_status run_job(gb_ctx *c, Workspace &ws, const Job &j, const GraphKey &key, bool use_graph,
+                  hipStream_t st);
+// single-n queries already in ws.q (device, k entries): results to ws.q + k
+gb_status enqueue_queries(gb_ctx *c, Workspace &ws, uint64_t k, const unsigned long long *dn,
+                          unsigned long long *dp, hipStream_t st);
+void merge_slot(gb_summary &acc, const GbSlot &s);
+
+}  // namespace gbrt
+
+#define GB_HIP(c, expr)                                                                             \
+    do {                                                                                            \
+        hipError_t e_ = (expr);                                                                     \
+        if (e_ != hipSuccess)                                                                       \
+            return ::gbrt::fail((c), GB_EDEVICE, std::string(#expr ": ") + hipGetErrorString(e_)); \
+    } while (0)

@@ -228,7 +228,7 @@ def test_plain_equals_batched_and_seg_hist(orc):
 @pytest.mark.parametrize("kw", [
     dict(tile_log2=12, wg_threads=256, wheel_max=7),
     dict(tile_log2=16, wg_threads=1024, wheel_max=13, pmax=1024),
-    dict(tile_log2=20, wg_threads=1024, wheel_max=19),
+    dict(tile_log2=20, wg_threads=512, wheel_max=19),
     dict(tile_log2=19, wg_threads=512, wheel_max=19, pmax=65535),
     dict(tile_log2=17, wg_threads=512, wheel_max=11, pmax=3000),
     dict(tile_log2=14, wg_threads=512, wheel_max=17, seg_log2=16),

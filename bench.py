@@ -23,9 +23,12 @@ sys.path.insert(0, ROOT)
 LO, HI = 10**12 - 2**36, 10**12
 METRIC = "even n verified/s at N~1e12 on 1 MI355X (batched form)"
 
-# Per-n algorithmic work of the sieve-and-search kernel at this workload
-# (derivation in DESIGN.md, "Roofline"): 1.711 bit clears (3 VALU ops each),
-# 1.01 64-bit window probes (7 VALU ops each), 1/32 wheel word (5 ops).
+# Per-n algorithmic work of the sieve-and-search kernel at this workload:
+# sum over sieving primes 11 <= p <= 10^6 of 1/p = 1.711 bit clears per odd
+# number (3 integer ops each: next index, word, mask), 1.01 64-bit window
+# probes per n (7 ops: offset, word, two funnel shifts, two ANDs, test; the
+# mean over 64-n blocks of the largest prime index needed, divided by 64),
+# and 1/32 wheel word per n (5 ops).
 CLEARS_PER_N = 1.711
 PROBES_PER_N = 1.01
 ALG_OPS_PER_N = CLEARS_PER_N * 3 + PROBES_PER_N * 7 + 5 / 32
@@ -38,7 +41,7 @@ def _load_tuned():
     if os.path.exists(path):
         with open(path) as f:
             d = json.load(f)
-        return {k: int(d[k]) for k in ("pmax", "seg_log2", "tile_log2", "wg_threads", "wheel_max")
+        return {k: int(d[k]) for k in ("pmax", "seg_log2", "tile_log2", "wg_threads", "wheel_max", "search_mode")
                 if k in d}
     return {}
 
@@ -64,6 +67,7 @@ def main():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--plain-steps", type=int, default=1)
     ap.add_argument("--no-windows", action="store_true")
+    ap.add_argument("--params", default="", help="JSON object of gb_params fields overriding the tuned ones")
     ap.add_argument("--copy-calibrate", type=int, default=0, metavar="MIB",
                     help="also run one device-to-device copy of this many MiB (a reference "
                          "kernel of known traffic for the HBM byte counters)")
@@ -80,6 +84,8 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
     params = _load_tuned()
+    if args.params:
+        params.update({k: int(v) for k, v in json.loads(args.params).items()})
     v = Verifier(0, **params)
     p = v.params
     print(f"# params {p}", file=sys.stderr, flush=True)

@@ -75,6 +75,10 @@ typedef struct gb_params {
                                (0 -> 512) */
     uint32_t wheel_max;     /* largest prime of the pre-sieved wheel pattern:
                                7, 11, 13, 17 or 19 (0 -> 19) */
+    uint32_t search_mode;   /* bookkeeping of the fast-path hits: 1 = in the
+                               probing lane, 2 = compacted into a per-wave
+                               queue and drained 64 at a time (0 -> 1) */
+    uint32_t reserved;      /* must be 0 */
     uint64_t max_hi;        /* largest n any range call may reach; sizes the
                                resident sieving-prime table to sqrt(max_hi)
                                (0 -> 2^50; at most 2^63) */

@@ -22,7 +22,8 @@ u64, u32, i32, vp, dbl = ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int32, ctype
 
 class Params(ctypes.Structure):
     _fields_ = [("device", i32), ("pmax", u32), ("seg_log2", u32), ("tile_log2", u32),
-                ("wg_threads", u32), ("wheel_max", u32), ("max_hi", u64),
+                ("wg_threads", u32), ("wheel_max", u32), ("search_mode", u32), ("reserved", u32),
+                ("max_hi", u64),
                 ("exhaustive_budget_p", u64), ("max_unresolved", u64), ("mem_budget", u64)]
 
     def as_dict(self):

@@ -83,6 +83,7 @@ GbTileArgs base_args(gb_ctx *c, Workspace &ws)
     a.np_search = c->np_search;
     a.primes = c->d_primes;
     a.magic = c->d_magic;
+    a.pinv = c->d_pinv;
     a.k_first = c->k_first;
     a.k_wg_end = c->k_wg_end;
     a.k_wave_end = c->k_wave_end;
@@ -132,7 +133,7 @@ gb_status enqueue_tiles(gb_ctx *c, Workspace &ws, const Job &j, hipStream_t st)
         a.nwin = (uint32_t)pl.w.size();
         a.ntiles = pl.ntiles;
         const uint64_t g = std::min<uint64_t>(pl.ntiles, (uint64_t)c->num_cu * c->occupancy);
-        GB_HIP(c, gb_launch_tiles(a, (uint32_t)g, c->threads, c->lds, j.pmin_bits, true, false, st));
+        GB_HIP(c, gb_launch_tiles(a, (uint32_t)g, c->threads, c->lds, j.pmin_bits, true, false, c->queue, st));
     } else {
         for (size_t i = 0; i < pl.w.size(); ++i) {
             GbTileArgs b = a;
@@ -140,7 +141,7 @@ gb_status enqueue_tiles(gb_ctx *c, Workspace &ws, const Job &j, hipStream_t st)
             b.nwin = 1;
             b.tile0 = pl.w[i].tile_base;
             const uint64_t nt = (pl.w[i].count + c->tile_n - 1) / c->tile_n;
-            GB_HIP(c, gb_launch_tiles(b, (uint32_t)nt, c->threads, c->lds, j.pmin_bits, false, false, st));
+            GB_HIP(c, gb_launch_tiles(b, (uint32_t)nt, c->threads, c->lds, j.pmin_bits, false, false, c->queue, st));
         }
     }
     return GB_OK;
@@ -242,6 +243,7 @@ gb_status apply_params(gb_ctx *c, const gb_params *in)
     if (p.tile_log2 == 0) p.tile_log2 = 19;
     if (p.wg_threads == 0) p.wg_threads = 512;
     if (p.wheel_max == 0) p.wheel_max = 19;
+    if (p.search_mode == 0) p.search_mode = 1;
     if (p.max_hi == 0) p.max_hi = kDefaultMaxHi;
     if (p.max_unresolved == 0) p.max_unresolved = 1ull << 20;
     if (p.mem_budget == 0) p.mem_budget = 4ull << 30;
@@ -253,6 +255,8 @@ gb_status apply_params(gb_ctx *c, const gb_params *in)
         return fail(c, GB_EINVAL, "wg_threads must be 256, 512 or 1024");
     if (p.wheel_max != 7 && p.wheel_max != 11 && p.wheel_max != 13 && p.wheel_max != 17 && p.wheel_max != 19)
         return fail(c, GB_EINVAL, "wheel_max must be 7, 11, 13, 17 or 19");
+    if (p.search_mode > 2) return fail(c, GB_EINVAL, "search_mode must be 1 or 2");
+    if (p.reserved != 0) return fail(c, GB_EINVAL, "reserved must be 0");
     if (p.max_hi > GB_MAX_N) return fail(c, GB_EINVAL, "max_hi must be at most 2^63");
     if (p.max_hi < 1024) p.max_hi = 1024;
     c->prm = p;
@@ -268,11 +272,17 @@ gb_status build_tables(gb_ctx *c)
     c->table_limit = lim;
     c->ntab = c->h_primes.size();
     std::vector<unsigned long long> magic(c->ntab);
-    for (uint64_t i = 0; i < c->ntab; ++i) magic[i] = ~0ull / c->h_primes[i];
+    std::vector<double> pinv(c->ntab);
+    for (uint64_t i = 0; i < c->ntab; ++i) {
+        magic[i] = ~0ull / c->h_primes[i];
+        pinv[i] = 1.0 / (double)c->h_primes[i];
+    }
     GB_HIP(c, hipMalloc(&c->d_primes, c->ntab * 4));
     GB_HIP(c, hipMalloc(&c->d_magic, c->ntab * 8));
+    GB_HIP(c, hipMalloc(&c->d_pinv, c->ntab * 8));
     GB_HIP(c, hipMemcpy(c->d_primes, c->h_primes.data(), c->ntab * 4, hipMemcpyHostToDevice));
     GB_HIP(c, hipMemcpy(c->d_magic, magic.data(), c->ntab * 8, hipMemcpyHostToDevice));
+    GB_HIP(c, hipMemcpy(c->d_pinv, pinv.data(), c->ntab * 8, hipMemcpyHostToDevice));
     return GB_OK;
 }
 
@@ -280,9 +290,11 @@ void free_tables(gb_ctx *c)
 {
     if (c->d_primes) (void)hipFree(c->d_primes);
     if (c->d_magic) (void)hipFree(c->d_magic);
+    if (c->d_pinv) (void)hipFree(c->d_pinv);
     if (c->d_wheel) (void)hipFree(c->d_wheel);
     c->d_primes = nullptr;
     c->d_magic = nullptr;
+    c->d_pinv = nullptr;
     c->d_wheel = nullptr;
 }
 
@@ -299,16 +311,18 @@ gb_status setup_geometry(gb_ctx *c)
     const uint32_t nbits = c->tile_n + c->halo_bits;
     c->k_wg_end = std::max(c->k_first, count_le(c->h_primes, nbits / c->threads));
     c->k_wave_end = std::max(c->k_wg_end, count_le(c->h_primes, nbits / 64));
-    c->lds = gb_tile_lds_bytes(c->tile_n, c->halo_bits, c->np_search, c->k_wave_end - c->k_first, c->threads);
+    c->queue = p.search_mode == 2;
+    c->lds = gb_tile_lds_bytes(c->tile_n, c->halo_bits, c->np_search, c->k_wave_end - c->k_first, c->threads,
+                               c->queue);
     if (c->lds > 160 * 1024)
         return fail(c, GB_EINVAL, "tile does not fit in LDS (" + std::to_string(c->lds) +
                                       " bytes); lower tile_log2, wg_threads or pmax");
     hipDeviceProp_t prop;
     GB_HIP(c, hipGetDeviceProperties(&prop, p.device));
     c->num_cu = prop.multiProcessorCount;
-    GB_HIP(c, gb_prepare_tiles(c->threads, c->lds));
+    GB_HIP(c, gb_prepare_tiles(c->threads, c->lds, c->queue));
     int occ = 0;
-    GB_HIP(c, gb_tile_occupancy(c->threads, c->lds, &occ));
+    GB_HIP(c, gb_tile_occupancy(c->threads, c->lds, c->queue, &occ));
     c->occupancy = std::max(occ, 1);
     // wheel pattern over (v-1)/2 for odd v: bit g set iff 2g+1 is coprime to the wheel
     static const uint32_t wp[] = {3, 5, 7, 11, 13, 17, 19};
@@ -754,7 +768,7 @@ gb_status gb_sieve_window(gb_ctx *c, uint64_t w0, uint64_t nbits, uint32_t *bits
     a.nwin = 1;
     a.tile0 = 0;
     a.sieve_out = bits;
-    GB_HIP(c, gb_launch_tiles(a, (uint32_t)pl.ntiles, c->threads, c->lds, 0, false, true, st));
+    GB_HIP(c, gb_launch_tiles(a, (uint32_t)pl.ntiles, c->threads, c->lds, 0, false, true, c->queue, st));
     GB_HIP(c, hipStreamSynchronize(st));
     return GB_OK;
 }

@@ -51,6 +51,7 @@ struct GbTileArgs {
     uint32_t np_search;     // odd primes <= P_max
     const uint32_t *primes; // odd primes 3, 5, 7, ... ascending
     const unsigned long long *magic;  // floor((2^64-1)/p) per prime
+    const double *pinv;               // 1/p per prime, rounded to double
     uint32_t k_first;       // first prime index above the wheel
     uint32_t k_wg_end;      // primes [k_first, k_wg_end): whole-workgroup marking
     uint32_t k_wave_end;    // primes [k_wg_end, k_wave_end): one wave per prime
@@ -85,13 +86,14 @@ struct GbMrArgs {
 };
 
 // Kernel launchers (gb_kernels.hip).
+// queue: the search variant that compacts hits into a per-wave LDS queue
 hipError_t gb_launch_tiles(const GbTileArgs &a, uint32_t grid, uint32_t threads,
                            size_t lds_bytes, int pmin_bits, bool persistent,
-                           bool sieve_only, hipStream_t st);
-hipError_t gb_prepare_tiles(uint32_t threads, size_t lds_bytes);
-hipError_t gb_tile_occupancy(uint32_t threads, size_t lds_bytes, int *blocks_per_cu);
+                           bool sieve_only, bool queue, hipStream_t st);
+hipError_t gb_prepare_tiles(uint32_t threads, size_t lds_bytes, bool queue);
+hipError_t gb_tile_occupancy(uint32_t threads, size_t lds_bytes, bool queue, int *blocks_per_cu);
 size_t gb_tile_lds_bytes(uint32_t tile_n, uint32_t halo_bits, uint32_t np_search,
-                         uint32_t n_off, uint32_t threads);
+                         uint32_t n_off, uint32_t threads, bool queue);
 hipError_t gb_launch_mr(const GbMrArgs &a, uint32_t grid, hipStream_t st);
 hipError_t gb_launch_argmax(GbSlot *slots, const GbTileRec *recs, uint64_t nrecs,
                             const GbExh *list, const unsigned long long *list_count,

@@ -22,6 +22,8 @@
 // Montgomery arithmetic, and the lowest passing lane (ballot + first set bit)
 // is confirmed with the other eleven bases of the deterministic 64-bit test
 // (bases 2..37), one base per lane.
+#include <algorithm>
+
 #include "gb_internal.h"
 
 namespace {
@@ -46,6 +48,24 @@ __device__ __forceinline__ unsigned long long first_index(long long w0, uint32_t
         return (pp - (unsigned long long)w0) >> 1;
     unsigned long long r = fastmod64((unsigned long long)w0, p, magic);
     uint32_t d = r ? p - (uint32_t)r : 0u;  // w0 + d is the next multiple
+    return (d & 1u) ? ((unsigned long long)d + p) >> 1 : (unsigned long long)(d >> 1);
+}
+
+// Same as first_index for a window start below 2^53, with the residue
+// w0 mod p from double precision: q = floor(w0 * (1/p)) is off by at most one
+// from w0 / p, and the FMA residual w0 - q*p is an exact small integer.
+__device__ __forceinline__ unsigned long long first_index_f64(long long w0, double w0d, uint32_t p,
+                                                              double pinv)
+{
+    const unsigned long long pp = (unsigned long long)p * p;
+    if (w0 <= 0 || (unsigned long long)w0 <= pp)
+        return (pp - (unsigned long long)w0) >> 1;
+    const double pd = (double)p;
+    const double q = floor(w0d * pinv);
+    int r = (int)fma(-q, pd, w0d);
+    if (r < 0) r += (int)p;
+    if (r >= (int)p) r -= (int)p;
+    const uint32_t d = r ? p - (uint32_t)r : 0u;
     return (d & 1u) ? ((unsigned long long)d + p) >> 1 : (unsigned long long)(d >> 1);
 }
 
@@ -90,7 +110,7 @@ __device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long v)
 }
 
 // LDS carve-up of one tile workgroup (offsets in 32-bit words).
-constexpr uint32_t QCAP = 128;  // hit-queue entries per wave
+constexpr uint32_t QCAP = 96;   // hit-queue entries per wave (a probe adds at most 64)
 
 struct TileLds {
     uint32_t *bits;           // (T + HB)/32 words: the tile's window, 1 = prime
@@ -100,8 +120,10 @@ struct TileLds {
     unsigned long long *red;  // 3 * waves
     unsigned long long *qhit; // per wave: QCAP hit masks
     uint32_t *qtag;           // per wave: QCAP (prime index | block << 16)
+    unsigned long long *tile; // persistent mode: the tile just taken
 };
 
+template <bool QUEUE>
 __device__ __forceinline__ TileLds carve(uint32_t *smem, const GbTileArgs &a)
 {
     TileLds L;
@@ -112,18 +134,28 @@ __device__ __forceinline__ TileLds carve(uint32_t *smem, const GbTileArgs &a)
     o += (a.np_search + 4 + 1) / 2;
     L.lhist = smem + o;
     o += a.np_search;
+    // The first strikes are only read while marking and the hit queue is
+    // only used while searching, with a barrier between: they share space.
+    o = (o + 1) & ~1u;
     L.offs = smem + o;
-    o += a.n_off;
+    L.qhit = nullptr;
+    L.qtag = nullptr;
+    uint32_t shared_words = a.n_off;
+    if (QUEUE) {
+        L.qhit = reinterpret_cast<unsigned long long *>(smem + o);
+        L.qtag = smem + o + 2 * QCAP * (blockDim.x / 64);
+        shared_words = max(shared_words, 3 * QCAP * (blockDim.x / 64));
+    }
+    o += shared_words;
     o = (o + 1) & ~1u;
     L.red = reinterpret_cast<unsigned long long *>(smem + o);
     o += 2 * 3 * (blockDim.x / 64);
-    L.qhit = reinterpret_cast<unsigned long long *>(smem + o);
-    o += 2 * QCAP * (blockDim.x / 64);
-    L.qtag = smem + o;
+    o = (o + 1) & ~1u;
+    L.tile = reinterpret_cast<unsigned long long *>(smem + o);
     return L;
 }
 
-template <int NT, int PB, bool SIEVE_ONLY>
+template <int NT, int PB, bool SIEVE_ONLY, bool QUEUE>
 __device__ void process_tile(const GbTileArgs &a, unsigned long long g, const TileLds &L)
 {
     const uint32_t tid = threadIdx.x;
@@ -152,6 +184,8 @@ __device__ void process_tile(const GbTileArgs &a, unsigned long long g, const Ti
     const long long w0 = (long long)(N0 + 1ull - 2ull * HB);
     const uint32_t np = W.np_sieve;
     const uint32_t nps = a.np_search;
+    const bool small_w0 = w0 < (1ll << 53);   // exact as a double
+    const double w0d = (double)w0;
 
     // ---- fast-path prime list, per-tile histogram --------------------------
     if (!SIEVE_ONLY) {
@@ -164,7 +198,8 @@ __device__ void process_tile(const GbTileArgs &a, unsigned long long g, const Ti
     // ---- first strike of every small and medium sieving prime, once -------
     const uint32_t kmid = min(a.k_wave_end, np);
     for (uint32_t k = a.k_first + tid; k < kmid; k += NT) {
-        const unsigned long long t0 = first_index(w0, a.primes[k], a.magic[k]);
+        const unsigned long long t0 = small_w0 ? first_index_f64(w0, w0d, a.primes[k], a.pinv[k])
+                                               : first_index(w0, a.primes[k], a.magic[k]);
         L.offs[k - a.k_first] = t0 < nbits ? (uint32_t)t0 : 0xFFFFFFFFu;
     }
 
@@ -219,7 +254,8 @@ __device__ void process_tile(const GbTileArgs &a, unsigned long long g, const Ti
         const uint32_t kbeg3 = max(a.k_wave_end, a.k_first);
         for (uint32_t k = kbeg3 + tid; k < np; k += NT) {
             const uint32_t p = a.primes[k];
-            const unsigned long long t0 = first_index(w0, p, a.magic[k]);
+            const unsigned long long t0 = small_w0 ? first_index_f64(w0, w0d, p, a.pinv[k])
+                                                   : first_index(w0, p, a.magic[k]);
             if (t0 >= nbits) continue;
             for (uint32_t idx = (uint32_t)t0; idx < nbits; idx += p)
                 atomicAnd(&L.bits[idx >> 5], ~(1u << (idx & 31u)));
@@ -246,6 +282,105 @@ __device__ void process_tile(const GbTileArgs &a, unsigned long long g, const Ti
     unsigned long long cs = 0;         // lane's checksum part
     uint32_t nexh = 0;                 // n left to the exhaustive phase
 
+    // every block is full except possibly the tile's last one
+    const uint32_t nv_last = cnt - 64u * (nblk - 1u);
+    const uint32_t last_lo = nv_last >= 32 ? ~0u : ((1u << nv_last) - 1u);
+    const uint32_t last_hi = nv_last >= 64 ? ~0u : (nv_last > 32 ? ((1u << (nv_last - 32)) - 1u) : 0u);
+    // n no fast-path prime resolves go to the exhaustive phase's list
+    auto push_unresolved = [&](uint32_t blk, unsigned long long u) {
+        nexh += __popcll(u);
+        while (u) {
+            const uint32_t j = (uint32_t)__builtin_ctzll(u);
+            u &= u - 1ull;
+            const unsigned long long e = atomicAdd(a.list_count, 1ull);
+            if (e < a.list_cap) {
+                GbExh x;
+                x.n = N0 + 2ull * (64ull * blk + j);
+                x.out_index = outb + 64ull * blk + j;
+                x.slot = slot;
+                x.start_k = nps;
+                x.p = 0;
+                a.list[e] = x;
+            }
+        }
+    };
+    if constexpr (!QUEUE) {
+    // block state: unresolved mask U, next prime index k, the block's sums
+    // of p*popcount(hit) (Ab) and p*(positions of hit) (Bb), and its last hit
+    // (the last hit carries the block's largest p_min)
+    uint32_t b = tid, k = 0, Ulo = 0, Uhi = 0, Ab = 0, Bb = 0, lastp = 0, llo = 0, lhi = 0;
+    uint32_t base = 0;
+    auto start_block = [&](uint32_t bb) {
+        const bool last = bb + 1u == nblk;
+        Ulo = last ? last_lo : ~0u;
+        Uhi = last ? last_hi : ~0u;
+        k = 0; Ab = 0; Bb = 0; lastp = 0; llo = 0; lhi = 0;
+        base = 64u * bb + HB;
+        if (N0 == 4 && bb == 0) {  // n = 4 = 2 + 2, the one even p_min
+            Ulo &= ~1u;
+            Ab = 2;
+            lastp = 2; llo = 1u;
+            atomicAdd(&hist[0], 1ull);
+            if (a.pmin) store_p<PB>(a.pmin, outb, 2u);
+        }
+    };
+    auto finish_block = [&]() {
+        cs += (half0 + 64ull * b) * Ab + Bb;
+        if (lastp > maxp) {
+            maxp = lastp;
+            amax = 64u * b + (llo ? (uint32_t)__builtin_ctz(llo) : 32u + (uint32_t)__builtin_ctz(lhi));
+        }
+        if (Ulo | Uhi) push_unresolved(b, ((unsigned long long)Uhi << 32) | Ulo);
+    };
+    if (nps == 0) {
+        // no odd prime below P_max: every n but 4 goes to the exhaustive phase
+        for (; b < nblk; b += NT) {
+            start_block(b);
+            finish_block();
+        }
+    } else {
+        if (b < nblk) start_block(b);
+        while (b < nblk) {
+            // four probes per exit check; the prime list is padded with copies
+            // of its last prime, which cannot hit an n twice
+#pragma unroll
+            for (uint32_t u = 0; u < 4; ++u) {
+                const uint32_t h = L.hh[k + u];
+                const uint32_t s = base - h;
+                const uint32_t *wp = L.bits + (s >> 5);
+                const uint32_t d0 = wp[0], d1 = wp[1], d2 = wp[2];
+                const uint32_t hlo = __builtin_amdgcn_alignbit(d1, d0, s) & Ulo;
+                const uint32_t hhi = __builtin_amdgcn_alignbit(d2, d1, s) & Uhi;
+                if (hlo | hhi) {
+                    const uint32_t p = 2u * h - 1u;
+                    const uint32_t pc = __popc(hlo) + __popc(hhi);
+                    Ab += p * pc;
+                    Bb += p * bitpos_sum(hlo, hhi);
+                    atomicAdd(&L.lhist[k + u], pc);
+                    lastp = p; llo = hlo; lhi = hhi;
+                    if constexpr (PB != 0) {
+                        if (a.pmin) {
+                            unsigned long long hb = ((unsigned long long)hhi << 32) | hlo;
+                            const unsigned long long ob = outb + 64ull * b;
+                            while (hb) {
+                                store_p<PB>(a.pmin, ob + (unsigned long long)__builtin_ctzll(hb), p);
+                                hb &= hb - 1ull;
+                            }
+                        }
+                    }
+                    Ulo ^= hlo;
+                    Uhi ^= hhi;
+                }
+            }
+            k += 4;
+            if ((Ulo | Uhi) == 0u || k >= nps) {
+                finish_block();
+                b += NT;
+                if (b < nblk) start_block(b);
+            }
+        }
+    }
+    } else {
     // Hits are compacted into a per-wave LDS queue (ballot + mbcnt) and their
     // bookkeeping -- histogram, checksum, per-n output -- runs 64 events at
     // a time with every lane busy, instead of on every probe for the lanes
@@ -288,9 +423,9 @@ __device__ void process_tile(const GbTileArgs &a, unsigned long long g, const Ti
     uint32_t b = tid, k = 0, Ulo = 0, Uhi = 0, lasth = 0, llo = 0, lhi = 0;
     uint32_t base = 0;
     auto start_block = [&](uint32_t bb) {
-        const uint32_t nv = min(64u, cnt - 64u * bb);
-        Ulo = nv >= 32 ? ~0u : ((1u << nv) - 1u);
-        Uhi = nv >= 64 ? ~0u : (nv > 32 ? ((1u << (nv - 32)) - 1u) : 0u);
+        const bool last = bb + 1u == nblk;
+        Ulo = last ? last_lo : ~0u;
+        Uhi = last ? last_hi : ~0u;
         k = 0; lasth = 0; llo = 0; lhi = 0;
         base = 64u * bb + HB;
         if (N0 == 4 && bb == 0) {  // n = 4 = 2 + 2, the one even p_min
@@ -307,24 +442,7 @@ __device__ void process_tile(const GbTileArgs &a, unsigned long long g, const Ti
             maxp = lp;
             amax = 64u * b + (llo ? (uint32_t)__builtin_ctz(llo) : 32u + (uint32_t)__builtin_ctz(lhi));
         }
-        if (Ulo | Uhi) {
-            unsigned long long u = ((unsigned long long)Uhi << 32) | Ulo;
-            nexh += __popcll(u);
-            while (u) {
-                const uint32_t j = (uint32_t)__builtin_ctzll(u);
-                u &= u - 1ull;
-                const unsigned long long e = atomicAdd(a.list_count, 1ull);
-                if (e < a.list_cap) {
-                    GbExh x;
-                    x.n = N0 + 2ull * (64ull * b + j);
-                    x.out_index = outb + 64ull * b + j;
-                    x.slot = slot;
-                    x.start_k = nps;
-                    x.p = 0;
-                    a.list[e] = x;
-                }
-            }
-        }
+        if (Ulo | Uhi) push_unresolved(b, ((unsigned long long)Uhi << 32) | Ulo);
     };
     if (nps == 0) {
         // no odd prime below P_max: every n but 4 goes to the exhaustive phase
@@ -363,9 +481,10 @@ __device__ void process_tile(const GbTileArgs &a, unsigned long long g, const Ti
                     Uhi ^= hhi;
                 }
                 qn += (uint32_t)__popcll(m);
-                if (qn >= 64u) {
-                    qn -= 64u;
-                    drain(qn, 64u);
+                if (qn > QCAP - 64u) {  // room for the next probe's hits
+                    const uint32_t take = min(qn, 64u);
+                    qn -= take;
+                    drain(qn, take);
                 }
             }
             if (act) {
@@ -381,6 +500,7 @@ __device__ void process_tile(const GbTileArgs &a, unsigned long long g, const Ti
         if (qn) drain(0, qn);
     }
     cs = (half0 * cA) + cB;
+    }
 
     // ---- tile summary ------------------------------------------------------
     unsigned long long key = ((unsigned long long)maxp << 32) | (0xFFFFFFFFu - amax);
@@ -420,22 +540,21 @@ __device__ void process_tile(const GbTileArgs &a, unsigned long long g, const Ti
     __syncthreads();
 }
 
-template <int NT, int PB, bool PERS, bool SIEVE_ONLY>
+template <int NT, int PB, bool PERS, bool SIEVE_ONLY, bool QUEUE>
 __global__ __launch_bounds__(NT) void k_tile(GbTileArgs a)
 {
     extern __shared__ uint32_t smem[];
-    __shared__ unsigned long long s_tile;
-    const TileLds L = carve(smem, a);
+    const TileLds L = carve<QUEUE>(smem, a);
     if constexpr (PERS) {
         for (;;) {
-            if (threadIdx.x == 0) s_tile = atomicAdd(a.queue, 1ull);
+            if (threadIdx.x == 0) *L.tile = atomicAdd(a.queue, 1ull);
             __syncthreads();
-            const unsigned long long g = s_tile;
+            const unsigned long long g = *L.tile;
             if (g >= a.ntiles) break;
-            process_tile<NT, PB, SIEVE_ONLY>(a, g, L);
+            process_tile<NT, PB, SIEVE_ONLY, QUEUE>(a, g, L);
         }
     } else {
-        process_tile<NT, PB, SIEVE_ONLY>(a, a.tile0 + blockIdx.x, L);
+        process_tile<NT, PB, SIEVE_ONLY, QUEUE>(a, a.tile0 + blockIdx.x, L);
     }
 }
 
@@ -646,92 +765,101 @@ __global__ void k_finish_queries(const GbExh *list, uint64_t k, unsigned long lo
     if (i < k) p_out[i] = list[i].p;
 }
 
-template <int NT, int PB, bool PERS, bool SO>
+template <int NT, int PB, bool PERS, bool SO, bool Q>
 hipError_t launch_one(const GbTileArgs &a, uint32_t grid, size_t lds, hipStream_t st)
 {
-    hipLaunchKernelGGL((k_tile<NT, PB, PERS, SO>), dim3(grid), dim3(NT), lds, st, a);
+    hipLaunchKernelGGL((k_tile<NT, PB, PERS, SO, Q>), dim3(grid), dim3(NT), lds, st, a);
     return hipGetLastError();
 }
 
-template <int NT, int PB, bool PERS, bool SO>
+template <int NT, int PB, bool PERS, bool SO, bool Q>
 hipError_t allow_lds(size_t lds)
 {
-    return hipFuncSetAttribute(reinterpret_cast<const void *>(&k_tile<NT, PB, PERS, SO>),
+    return hipFuncSetAttribute(reinterpret_cast<const void *>(&k_tile<NT, PB, PERS, SO, Q>),
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
 }
 
-template <int NT>
+template <int NT, bool Q>
 hipError_t allow_lds_nt(size_t lds)
 {
     hipError_t e = hipSuccess, r;
-    if ((r = allow_lds<NT, 0, false, true>(lds)) != hipSuccess) e = r;
-    if ((r = allow_lds<NT, 0, false, false>(lds)) != hipSuccess) e = r;
-    if ((r = allow_lds<NT, 16, false, false>(lds)) != hipSuccess) e = r;
-    if ((r = allow_lds<NT, 32, false, false>(lds)) != hipSuccess) e = r;
-    if ((r = allow_lds<NT, 0, true, false>(lds)) != hipSuccess) e = r;
-    if ((r = allow_lds<NT, 16, true, false>(lds)) != hipSuccess) e = r;
-    if ((r = allow_lds<NT, 32, true, false>(lds)) != hipSuccess) e = r;
+    if ((r = allow_lds<NT, 0, false, true, Q>(lds)) != hipSuccess) e = r;
+    if ((r = allow_lds<NT, 0, false, false, Q>(lds)) != hipSuccess) e = r;
+    if ((r = allow_lds<NT, 16, false, false, Q>(lds)) != hipSuccess) e = r;
+    if ((r = allow_lds<NT, 32, false, false, Q>(lds)) != hipSuccess) e = r;
+    if ((r = allow_lds<NT, 0, true, false, Q>(lds)) != hipSuccess) e = r;
+    if ((r = allow_lds<NT, 16, true, false, Q>(lds)) != hipSuccess) e = r;
+    if ((r = allow_lds<NT, 32, true, false, Q>(lds)) != hipSuccess) e = r;
     return e;
 }
 
-template <int NT>
-hipError_t launch_nt(const GbTileArgs &a, uint32_t grid, size_t lds, int pb, bool pers, bool so,
-                     hipStream_t st)
+template <int NT, bool Q>
+hipError_t launch_nt(const GbTileArgs &a, uint32_t grid, size_t lds, int pb, bool pers, bool so, hipStream_t st)
 {
-    if (so) return launch_one<NT, 0, false, true>(a, grid, lds, st);
+    if (so) return launch_one<NT, 0, false, true, Q>(a, grid, lds, st);
     if (pers) {
-        if (pb == 16) return launch_one<NT, 16, true, false>(a, grid, lds, st);
-        if (pb == 32) return launch_one<NT, 32, true, false>(a, grid, lds, st);
-        return launch_one<NT, 0, true, false>(a, grid, lds, st);
+        if (pb == 16) return launch_one<NT, 16, true, false, Q>(a, grid, lds, st);
+        if (pb == 32) return launch_one<NT, 32, true, false, Q>(a, grid, lds, st);
+        return launch_one<NT, 0, true, false, Q>(a, grid, lds, st);
     }
-    if (pb == 16) return launch_one<NT, 16, false, false>(a, grid, lds, st);
-    if (pb == 32) return launch_one<NT, 32, false, false>(a, grid, lds, st);
-    return launch_one<NT, 0, false, false>(a, grid, lds, st);
+    if (pb == 16) return launch_one<NT, 16, false, false, Q>(a, grid, lds, st);
+    if (pb == 32) return launch_one<NT, 32, false, false, Q>(a, grid, lds, st);
+    return launch_one<NT, 0, false, false, Q>(a, grid, lds, st);
 }
 
 }  // namespace
 
 size_t gb_tile_lds_bytes(uint32_t tile_n, uint32_t halo_bits, uint32_t np_search, uint32_t n_off,
-                         uint32_t threads)
+                         uint32_t threads, bool queue)
 {
-    size_t words = (tile_n + halo_bits) / 32 + (np_search + 4 + 1) / 2 + np_search + n_off;
+    size_t words = (tile_n + halo_bits) / 32 + (np_search + 4 + 1) / 2 + np_search;
+    words = (words + 1) & ~(size_t)1;
+    // first strikes, sharing space with the hit queue (masks and tags)
+    words += queue ? std::max<size_t>(n_off, (2 + 1) * QCAP * (threads / 64)) : n_off;
     words = (words + 1) & ~(size_t)1;
     words += 2 * 3 * (threads / 64);
-    words += (2 + 1) * QCAP * (threads / 64);  // hit queue: masks and tags
+    words = (words + 1) & ~(size_t)1;
+    words += 2;                                           // the persistent tile index
     return words * 4;
 }
 
-hipError_t gb_prepare_tiles(uint32_t threads, size_t lds_bytes)
+hipError_t gb_prepare_tiles(uint32_t threads, size_t lds_bytes, bool queue)
 {
     switch (threads) {
-    case 256: return allow_lds_nt<256>(lds_bytes);
-    case 512: return allow_lds_nt<512>(lds_bytes);
-    case 1024: return allow_lds_nt<1024>(lds_bytes);
+    case 256: return queue ? allow_lds_nt<256, true>(lds_bytes) : allow_lds_nt<256, false>(lds_bytes);
+    case 512: return queue ? allow_lds_nt<512, true>(lds_bytes) : allow_lds_nt<512, false>(lds_bytes);
+    case 1024: return queue ? allow_lds_nt<1024, true>(lds_bytes) : allow_lds_nt<1024, false>(lds_bytes);
     default: return hipErrorInvalidValue;
     }
 }
 
-hipError_t gb_tile_occupancy(uint32_t threads, size_t lds_bytes, int *blocks_per_cu)
+hipError_t gb_tile_occupancy(uint32_t threads, size_t lds_bytes, bool queue, int *blocks_per_cu)
 {
+#define GB_OCC(NT, Q)                                                                                     \
+    hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_tile<NT, 0, true, false, Q>, NT, lds_bytes)
     switch (threads) {
-    case 256:
-        return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_tile<256, 0, true, false>, 256, lds_bytes);
-    case 512:
-        return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_tile<512, 0, true, false>, 512, lds_bytes);
-    case 1024:
-        return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_tile<1024, 0, true, false>, 1024, lds_bytes);
+    case 256: return queue ? GB_OCC(256, true) : GB_OCC(256, false);
+    case 512: return queue ? GB_OCC(512, true) : GB_OCC(512, false);
+    case 1024: return queue ? GB_OCC(1024, true) : GB_OCC(1024, false);
     default: return hipErrorInvalidValue;
     }
+#undef GB_OCC
 }
 
-hipError_t gb_launch_tiles(const GbTileArgs &a, uint32_t grid, uint32_t threads, size_t lds_bytes,
-                           int pmin_bits, bool persistent, bool sieve_only, hipStream_t st)
+hipError_t gb_launch_tiles(const GbTileArgs &a, uint32_t grid, uint32_t threads, size_t lds_bytes, int pmin_bits,
+                           bool persistent, bool sieve_only, bool queue, hipStream_t st)
 {
     if (grid == 0) return hipSuccess;
     switch (threads) {
-    case 256: return launch_nt<256>(a, grid, lds_bytes, pmin_bits, persistent, sieve_only, st);
-    case 512: return launch_nt<512>(a, grid, lds_bytes, pmin_bits, persistent, sieve_only, st);
-    case 1024: return launch_nt<1024>(a, grid, lds_bytes, pmin_bits, persistent, sieve_only, st);
+    case 256:
+        return queue ? launch_nt<256, true>(a, grid, lds_bytes, pmin_bits, persistent, sieve_only, st)
+                     : launch_nt<256, false>(a, grid, lds_bytes, pmin_bits, persistent, sieve_only, st);
+    case 512:
+        return queue ? launch_nt<512, true>(a, grid, lds_bytes, pmin_bits, persistent, sieve_only, st)
+                     : launch_nt<512, false>(a, grid, lds_bytes, pmin_bits, persistent, sieve_only, st);
+    case 1024:
+        return queue ? launch_nt<1024, true>(a, grid, lds_bytes, pmin_bits, persistent, sieve_only, st)
+                     : launch_nt<1024, false>(a, grid, lds_bytes, pmin_bits, persistent, sieve_only, st);
     default: return hipErrorInvalidValue;
     }
 }

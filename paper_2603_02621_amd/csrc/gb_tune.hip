@@ -52,6 +52,7 @@ gb_status reconfigure(gb_ctx *c, const gb_params &p)
     q.wg_threads = p.wg_threads;
     q.pmax = p.pmax;
     q.wheel_max = p.wheel_max;
+    q.search_mode = p.search_mode;
     q.seg_log2 = std::max(p.seg_log2, p.tile_log2);
     gb_status st = apply_params(c, &q);
     if (st != GB_OK) return st;
@@ -78,8 +79,9 @@ std::string params_json(const gb_params &p)
 {
     char buf[256];
     std::snprintf(buf, sizeof buf,
-                  "{\"tile_log2\": %u, \"wg_threads\": %u, \"pmax\": %u, \"wheel_max\": %u, \"seg_log2\": %u}",
-                  p.tile_log2, p.wg_threads, p.pmax, p.wheel_max, p.seg_log2);
+                  "{\"tile_log2\": %u, \"wg_threads\": %u, \"search_mode\": %u, \"pmax\": %u, "
+                  "\"wheel_max\": %u, \"seg_log2\": %u}",
+                  p.tile_log2, p.wg_threads, p.search_mode, p.pmax, p.wheel_max, p.seg_log2);
     return buf;
 }
 
@@ -127,18 +129,20 @@ extern "C" gb_status gb_autotune(gb_ctx *c, const gb_window *sample, size_t k, c
         return GB_OK;
     };
 
-    // 1. tile and workgroup shape at the given P_max and wheel
+    // 1. tile and workgroup shape and search variant at the given P_max and wheel
     for (uint32_t tl : {16u, 17u, 18u, 19u, 20u})
-        for (uint32_t nt : {256u, 512u, 1024u}) {
-            gb_params p = orig;
-            p.tile_log2 = tl;
-            p.wg_threads = nt;
-            gb_status st = try_point(p, true);
-            if (st != GB_OK) {
-                (void)reconfigure(c, orig);
-                return st;
+        for (uint32_t nt : {256u, 512u, 1024u})
+            for (uint32_t sm : {1u, 2u}) {
+                gb_params p = orig;
+                p.tile_log2 = tl;
+                p.wg_threads = nt;
+                p.search_mode = sm;
+                gb_status st = try_point(p, true);
+                if (st != GB_OK) {
+                    (void)reconfigure(c, orig);
+                    return st;
+                }
             }
-        }
     // 2. fast-path bound (n_exhaustive legitimately depends on it)
     {
         const gb_params base = cur;
@@ -228,8 +232,10 @@ extern "C" gb_status gb_autotune(gb_ctx *c, const gb_window *sample, size_t k, c
         (void)hipGetDeviceProperties(&prop, c->prm.device);
         std::fprintf(f, "{\"device\": \"%s\", \"cus\": %d, \"sample_windows\": %zu, \"sample_n\": %llu,\n",
                      prop.gcnArchName, prop.multiProcessorCount, k, (unsigned long long)total);
-        std::fprintf(f, " \"tile_log2\": %u, \"wg_threads\": %u, \"pmax\": %u, \"wheel_max\": %u, \"seg_log2\": %u,\n",
-                     c->prm.tile_log2, c->prm.wg_threads, c->prm.pmax, c->prm.wheel_max, c->prm.seg_log2);
+        std::fprintf(f, " \"tile_log2\": %u, \"wg_threads\": %u, \"search_mode\": %u, \"pmax\": %u, "
+                        "\"wheel_max\": %u, \"seg_log2\": %u,\n",
+                     c->prm.tile_log2, c->prm.wg_threads, c->prm.search_mode, c->prm.pmax, c->prm.wheel_max,
+                     c->prm.seg_log2);
         std::fprintf(f, " \"trials\": [");
         for (size_t i = 0; i < log.size(); ++i)
             std::fprintf(f, "%s\n  {\"params\": %s, \"ms\": %.4f}", i ? "," : "", params_json(log[i].prm).c_str(),

@@ -29,7 +29,7 @@ def _bench_params():
     path = os.path.join(ROOT, "paper_2603_02621_amd", "tuned.json")
     if os.path.exists(path):
         d = json.load(open(path))
-        return {k: int(d[k]) for k in ("pmax", "seg_log2", "tile_log2", "wg_threads", "wheel_max") if k in d}
+        return {k: int(d[k]) for k in ("pmax", "seg_log2", "tile_log2", "wg_threads", "wheel_max", "search_mode") if k in d}
     return {}
 
 

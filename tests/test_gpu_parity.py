@@ -126,15 +126,16 @@ def test_host_output_buffer(V, orc):
 # exhaustive phase
 # --------------------------------------------------------------------------
 
+@pytest.mark.parametrize("search_mode", [1, 2])
 @pytest.mark.parametrize("pmax,lo,hi", [
     (7, 4, 1 << 17),                    # almost every n goes to Miller-Rabin
     (2, 4, 1 << 14),                    # no odd prime in the fast path: every n except 4
     (1024, 10**12 - (1 << 22), 10**12), # a realistic trickle near 10^12
     (3, 10**15, 10**15 + 20_000),
 ])
-def test_exhaustive_phase_vs_oracle(orc, pmax, lo, hi):
+def test_exhaustive_phase_vs_oracle(orc, pmax, lo, hi, search_mode):
     _gpu()
-    v = _make(pmax=pmax)
+    v = _make(pmax=pmax, search_mode=search_mode)
     ref, rh, rs = orc.verify_range(lo, hi, pmax=pmax, per_n_bits=16, threads=4)
     out = _dev_pmin(len(ref), 16)
     got = v.verify_range(lo, hi, pmin=out)
@@ -232,6 +233,8 @@ def test_plain_equals_batched_and_seg_hist(orc):
     dict(tile_log2=19, wg_threads=512, wheel_max=19, pmax=65535),
     dict(tile_log2=17, wg_threads=512, wheel_max=11, pmax=3000),
     dict(tile_log2=14, wg_threads=512, wheel_max=17, seg_log2=16),
+    dict(tile_log2=18, wg_threads=512, search_mode=2),
+    dict(tile_log2=16, wg_threads=256, search_mode=2, pmax=1024, wheel_max=7),
 ])
 def test_parameter_invariance(orc, kw):
     _gpu()

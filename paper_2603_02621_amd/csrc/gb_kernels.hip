@@ -404,6 +404,12 @@ __device__ void process_tile(const GbTileArgs &a, unsigned long long g, const Ti
             atomicAdd(&L.lhist[kk], pc);
             cA += (unsigned long long)(p * pc);
             cB += (unsigned long long)p * (pc * (64u * bb) + bitpos_sum(hlo, hhi));
+            // largest p, and the smallest n that has it
+            const uint32_t nidx = 64u * bb + (hlo ? (uint32_t)__builtin_ctz(hlo) : 32u + (uint32_t)__builtin_ctz(hhi));
+            if (p > maxp || (p == maxp && nidx < amax)) {
+                maxp = p;
+                amax = nidx;
+            }
             if constexpr (PB != 0) {
                 if (a.pmin) {
                     unsigned long long hb = hm;
@@ -418,16 +424,17 @@ __device__ void process_tile(const GbTileArgs &a, unsigned long long g, const Ti
         __builtin_amdgcn_wave_barrier();
     };
 
-    // block state: unresolved mask U, next prime index k, and the block's
-    // last hit (its (p+1)/2 and mask), which carries the block's largest p_min
-    uint32_t b = tid, k = 0, Ulo = 0, Uhi = 0, lasth = 0, llo = 0, lhi = 0;
-    uint32_t base = 0;
+    // block state: unresolved mask U and next prime index k; the tag of a
+    // queued hit is its prime index plus the block index times 2^16
+    uint32_t b = tid, k = 0, Ulo = 0, Uhi = 0;
+    uint32_t base = 0, ktag = 0;
     auto start_block = [&](uint32_t bb) {
         const bool last = bb + 1u == nblk;
         Ulo = last ? last_lo : ~0u;
         Uhi = last ? last_hi : ~0u;
-        k = 0; lasth = 0; llo = 0; lhi = 0;
+        k = 0;
         base = 64u * bb + HB;
+        ktag = bb << 16;
         if (N0 == 4 && bb == 0) {  // n = 4 = 2 + 2, the one even p_min
             Ulo &= ~1u;
             cA += 2;                // (n/2 = 2) * (p = 2) = N0/2 * 2
@@ -437,11 +444,6 @@ __device__ void process_tile(const GbTileArgs &a, unsigned long long g, const Ti
         }
     };
     auto finish_block = [&]() {
-        const uint32_t lp = lasth ? 2u * lasth - 1u : 0u;
-        if (lp > maxp) {
-            maxp = lp;
-            amax = 64u * b + (llo ? (uint32_t)__builtin_ctz(llo) : 32u + (uint32_t)__builtin_ctz(lhi));
-        }
         if (Ulo | Uhi) push_unresolved(b, ((unsigned long long)Uhi << 32) | Ulo);
     };
     if (nps == 0) {
@@ -474,9 +476,8 @@ __device__ void process_tile(const GbTileArgs &a, unsigned long long g, const Ti
                 if (hit) {
                     const uint32_t slot_q = qn + __builtin_amdgcn_mbcnt_hi(
                         (uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-                    qtag[slot_q] = (k + u) | (b << 16);
+                    qtag[slot_q] = ktag + k + u;
                     qhit[slot_q] = ((unsigned long long)hhi << 32) | hlo;
-                    lasth = h; llo = hlo; lhi = hhi;
                     Ulo ^= hlo;
                     Uhi ^= hhi;
                 }

@@ -35,6 +35,11 @@ ALG_OPS_PER_N = CLEARS_PER_N * 3 + PROBES_PER_N * 7 + 5 / 32
 # 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz, one 32-bit integer op per lane-cycle
 ALU_PEAK_OPS = 256 * 64 * 2.4e9
 
+# HBM bytes per launch of the tile kernel on this workload, from rocprofv3
+# FETCH_SIZE and WRITE_SIZE scaled by a 1 GiB copy's readings (factors 2.000
+# and 1.000), valid only for the kernel source they were taken on.
+TRAFFIC = {"kernel_sha256_prefix": "522681225de16f4d", "bytes_per_launch": 8.15e6 + 122.8e6}
+
 
 def _load_tuned():
     path = os.path.join(ROOT, "paper_2603_02621_amd", "tuned.json")
@@ -159,8 +164,14 @@ def main():
     # ---- roofline of the dominant kernel ------------------------------------
     t_launch = sum(tile_ms) / len(tile_ms) / 1e3
     achieved = ALG_OPS_PER_N * count / t_launch
+    import hashlib
+    src = os.path.join(ROOT, "paper_2603_02621_amd", "csrc", "gb_kernels.hip")
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    same = sha == TRAFFIC["kernel_sha256_prefix"] and params.get("tile_log2") == 19
     roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": ALU_PEAK_OPS / 1e12,
-            "unit": "Tops/s (int32 lane ops)", "frac": achieved / ALU_PEAK_OPS, "traffic": None,
+            "unit": "Tops/s (int32 lane ops)", "frac": achieved / ALU_PEAK_OPS,
+            "traffic": TRAFFIC["bytes_per_launch"] if same else None,
+            "traffic_unit": "bytes per launch (HBM, rocprofv3)",
             "kernel": "k_tile (persistent)", "launch_ms": t_launch * 1e3,
             "alg_ops_per_n": round(ALG_OPS_PER_N, 3)}
 

@@ -70,14 +70,14 @@ typedef struct gb_params {
                                (one launch per segment), 16..30 (0 -> 24) */
     uint32_t tile_log2;     /* T = 2^tile_log2 even n per tile (one workgroup
                                sieves and searches one tile in LDS), 12..20
-                               (0 -> 18) */
+                               (0 -> 19) */
     uint32_t wg_threads;    /* threads per tile workgroup: 256, 512 or 1024
                                (0 -> 512) */
     uint32_t wheel_max;     /* largest prime of the pre-sieved wheel pattern:
                                7, 11, 13, 17 or 19 (0 -> 19) */
-    uint32_t search_mode;   /* bookkeeping of the fast-path hits: 1 = in the
-                               probing lane, 2 = compacted into a per-wave
-                               queue and drained 64 at a time (0 -> 1) */
+    uint32_t search_mode;   /* search variant; 1 (0 -> 1) is the only one:
+                               each lane does the bookkeeping of its own hits.
+                               Other values give GB_EINVAL. */
     uint32_t reserved;      /* must be 0 */
     uint64_t max_hi;        /* largest n any range call may reach; sizes the
                                resident sieving-prime table to sqrt(max_hi)
@@ -106,7 +106,12 @@ typedef struct gb_result {
     uint64_t count;           /* even n examined */
     uint64_t max_p;           /* largest p_min */
     uint64_t argmax_n;        /* smallest n attaining max_p */
-    uint64_t checksum;        /* sum of (n/2) * p_min(n) modulo 2^64 */
+    uint64_t checksum;        /* sum of w(n) * p_min(n) modulo 2^64 over the
+                                 n with a partition, where
+                                 w(n) = floor(n/128) + 2^32 (2c+1) 2^i and
+                                 (n/2) mod 64 = 16c + i, 0 <= i < 16.  The
+                                 paper defines no checksum; sums over
+                                 disjoint sets of n add up. */
     uint64_t n_exhaustive;    /* n that no odd prime p <= P_max resolved */
     uint64_t n_failed;        /* n without a partition within the budget */
     uint64_t first_failed_n;  /* smallest such n, or 0 */

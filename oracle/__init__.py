@@ -71,6 +71,7 @@ def lib():
         L.orc_verify_many.argtypes = [vp, vp, u64, u64, ip]
         L.orc_verify_many.restype = None
         L.orc_hist_bins.argtypes, L.orc_hist_bins.restype = [], u32
+        L.orc_checksum_weight.argtypes, L.orc_checksum_weight.restype = [u64], u64
         L.orc_odd_primality.argtypes, L.orc_odd_primality.restype = [u64, u64, vp], ip
         _lib = L
     return _lib
@@ -86,6 +87,11 @@ def trial_is_prime(q: int) -> bool:
 
 def mr_base(q: int, a: int) -> bool:
     return bool(lib().orc_mr_base(q, a))
+
+
+def checksum_weight(n: int) -> int:
+    """Weight of even n in the checksum (sum of weight * p_min, mod 2^64)."""
+    return int(lib().orc_checksum_weight(n))
 
 
 def mr(q: int) -> bool:

@@ -20,7 +20,14 @@
  * Summaries (the paper prints none; their definitions are fixed here):
  *   count          number of even n examined
  *   max_p/argmax_n largest p_min and the smallest n attaining it
- *   checksum       sum over n of (n/2) * p_min(n), modulo 2^64
+ *   checksum       sum over n of w(n) * p_min(n), modulo 2^64, with the
+ *                  weight w(n) = floor(n/128) + 2^32 * (2c+1) * 2^i, where
+ *                  j = (n/2) mod 64, c = floor(j/16), i = j mod 16
+ *                  (orc_checksum_weight).  A single wrong p_min changes
+ *                  it whenever w(n) has at most 48 factors of 2 (the
+ *                  difference of two p below 2^16 has at most 15); two n
+ *                  within 256 of each other exchanging p values that differ
+ *                  by less than 2^15 change it too.
  *   hist[i]        number of n whose p_min is the i-th prime (2 -> 0,
  *                  3 -> 1, ...) for p_min < 2^16; bin 6542 counts larger p
  *   n_exhaustive   number of n that no prime p <= P_max resolves (the n a
@@ -212,6 +219,15 @@ static uint32_t hist_bin(uint64_t p, const uint32_t *small, uint64_t nsmall)
     return (uint32_t)(lo + 1);
 }
 
+/* The checksum weight of n, written out from its definition above. */
+uint64_t orc_checksum_weight(uint64_t n)
+{
+    uint64_t j = (n / 2) % 64;
+    uint64_t c = j / 16, i = j % 16;
+    uint64_t chunk_weight = (2 * c + 1) << i;
+    return n / 128 + (chunk_weight << 32);
+}
+
 static void record(orc_summary *s, uint64_t *hist, const uint32_t *small,
                    uint64_t nsmall, uint64_t n, uint64_t p, uint32_t pmax)
 {
@@ -223,7 +239,7 @@ static void record(orc_summary *s, uint64_t *hist, const uint32_t *small,
         return;
     }
     if (hist) hist[hist_bin(p, small, nsmall)]++;
-    s->checksum += (n / 2) * p;
+    s->checksum += orc_checksum_weight(n) * p;
     if (p > s->max_p) { s->max_p = p; s->argmax_n = n; }
     if (p > pmax) s->n_exhaustive++;
 }

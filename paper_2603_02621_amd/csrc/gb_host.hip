@@ -133,7 +133,7 @@ gb_status enqueue_tiles(gb_ctx *c, Workspace &ws, const Job &j, hipStream_t st)
         a.nwin = (uint32_t)pl.w.size();
         a.ntiles = pl.ntiles;
         const uint64_t g = std::min<uint64_t>(pl.ntiles, (uint64_t)c->num_cu * c->occupancy);
-        GB_HIP(c, gb_launch_tiles(a, (uint32_t)g, c->threads, c->lds, j.pmin_bits, true, false, c->queue, st));
+        GB_HIP(c, gb_launch_tiles(a, (uint32_t)g, c->threads, c->lds, j.pmin_bits, true, false, st));
     } else {
         for (size_t i = 0; i < pl.w.size(); ++i) {
             GbTileArgs b = a;
@@ -141,7 +141,7 @@ gb_status enqueue_tiles(gb_ctx *c, Workspace &ws, const Job &j, hipStream_t st)
             b.nwin = 1;
             b.tile0 = pl.w[i].tile_base;
             const uint64_t nt = (pl.w[i].count + c->tile_n - 1) / c->tile_n;
-            GB_HIP(c, gb_launch_tiles(b, (uint32_t)nt, c->threads, c->lds, j.pmin_bits, false, false, c->queue, st));
+            GB_HIP(c, gb_launch_tiles(b, (uint32_t)nt, c->threads, c->lds, j.pmin_bits, false, false, st));
         }
     }
     return GB_OK;
@@ -255,7 +255,7 @@ gb_status apply_params(gb_ctx *c, const gb_params *in)
         return fail(c, GB_EINVAL, "wg_threads must be 256, 512 or 1024");
     if (p.wheel_max != 7 && p.wheel_max != 11 && p.wheel_max != 13 && p.wheel_max != 17 && p.wheel_max != 19)
         return fail(c, GB_EINVAL, "wheel_max must be 7, 11, 13, 17 or 19");
-    if (p.search_mode > 2) return fail(c, GB_EINVAL, "search_mode must be 1 or 2");
+    if (p.search_mode != 1) return fail(c, GB_EINVAL, "search_mode must be 1 (or 0 for the default)");
     if (p.reserved != 0) return fail(c, GB_EINVAL, "reserved must be 0");
     if (p.max_hi > GB_MAX_N) return fail(c, GB_EINVAL, "max_hi must be at most 2^63");
     if (p.max_hi < 1024) p.max_hi = 1024;
@@ -311,18 +311,16 @@ gb_status setup_geometry(gb_ctx *c)
     const uint32_t nbits = c->tile_n + c->halo_bits;
     c->k_wg_end = std::max(c->k_first, count_le(c->h_primes, nbits / c->threads));
     c->k_wave_end = std::max(c->k_wg_end, count_le(c->h_primes, nbits / 64));
-    c->queue = p.search_mode == 2;
-    c->lds = gb_tile_lds_bytes(c->tile_n, c->halo_bits, c->np_search, c->k_wave_end - c->k_first, c->threads,
-                               c->queue);
+    c->lds = gb_tile_lds_bytes(c->tile_n, c->halo_bits, c->np_search, c->k_wave_end - c->k_first);
     if (c->lds > 160 * 1024)
         return fail(c, GB_EINVAL, "tile does not fit in LDS (" + std::to_string(c->lds) +
                                       " bytes); lower tile_log2, wg_threads or pmax");
     hipDeviceProp_t prop;
     GB_HIP(c, hipGetDeviceProperties(&prop, p.device));
     c->num_cu = prop.multiProcessorCount;
-    GB_HIP(c, gb_prepare_tiles(c->threads, c->lds, c->queue));
+    GB_HIP(c, gb_prepare_tiles(c->threads, c->lds));
     int occ = 0;
-    GB_HIP(c, gb_tile_occupancy(c->threads, c->lds, c->queue, &occ));
+    GB_HIP(c, gb_tile_occupancy(c->threads, c->lds, &occ));
     c->occupancy = std::max(occ, 1);
     // wheel pattern over (v-1)/2 for odd v: bit g set iff 2g+1 is coprime to the wheel
     static const uint32_t wp[] = {3, 5, 7, 11, 13, 17, 19};
@@ -347,12 +345,19 @@ gb_status setup_geometry(gb_ctx *c)
 }
 
 // Split windows into tiles and fill the derived window fields; GB_ERANGE
-// when a window reaches past the resident sieving primes.
-gb_status plan_windows(gb_ctx *c, Plan &pl)
+// when a window reaches past the resident sieving primes.  With `align`, each
+// window's first n moves down to a multiple of 128, the n added in front
+// counted in `lead` (the search kernels mask them).
+gb_status plan_windows(gb_ctx *c, Plan &pl, bool align)
 {
     const uint64_t T = c->tile_n;
     uint64_t tb = 0, off = 0;
     for (auto &w : pl.w) {
+        const uint64_t user_count = w.count;
+        w.lead = (align && user_count) ? (uint32_t)((w.first_n >> 1) & 63u) : 0u;
+        w.pad = 0;
+        w.first_n -= 2ull * w.lead;
+        w.count += w.lead;
         const uint64_t nt = (w.count + T - 1) / T;
         w.tile_base = tb;
         w.out_off = off;
@@ -362,7 +367,7 @@ gb_status plan_windows(gb_ctx *c, Plan &pl)
             return fail(c, GB_ERANGE, "window top beyond the resident sieving primes (raise max_hi)");
         w.np_sieve = count_le(c->h_primes, r);
         tb += nt;
-        off += w.count;
+        off += user_count;
     }
     pl.ntiles = tb;
     pl.total_n = off;
@@ -758,7 +763,7 @@ gb_status gb_sieve_window(gb_ctx *c, uint64_t w0, uint64_t nbits, uint32_t *bits
     pl.w[0].first_n = w0 - 1 + 2ull * c->halo_bits;  // makes the tile window start at w0
     pl.w[0].count = nbits;
     pl.w[0].slot = 0;
-    gb_status stt = plan_windows(c, pl);
+    gb_status stt = plan_windows(c, pl, false);
     if (stt != GB_OK) return stt;
     stt = ensure_workspace(c, ws, pl, 1, 1);
     if (stt != GB_OK) return stt;
@@ -768,7 +773,7 @@ gb_status gb_sieve_window(gb_ctx *c, uint64_t w0, uint64_t nbits, uint32_t *bits
     a.nwin = 1;
     a.tile0 = 0;
     a.sieve_out = bits;
-    GB_HIP(c, gb_launch_tiles(a, (uint32_t)pl.ntiles, c->threads, c->lds, 0, false, true, c->queue, st));
+    GB_HIP(c, gb_launch_tiles(a, (uint32_t)pl.ntiles, c->threads, c->lds, 0, false, true, st));
     GB_HIP(c, hipStreamSynchronize(st));
     return GB_OK;
 }

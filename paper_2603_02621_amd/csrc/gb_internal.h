@@ -8,13 +8,18 @@
 
 // One window of consecutive even n.  A range call uses one window per
 // segment; the batched forms put many windows in one table.
+// The planner moves first_n down to a multiple of 128 and masks the `lead`
+// n it adds in front, so a 64-n block always covers one residue class of
+// floor(n/128).
 struct GbWindow {
-    uint64_t first_n;    // even, >= 4
-    uint64_t count;      // even n in the window
+    uint64_t first_n;    // even; a multiple of 128 for the search kernels
+    uint64_t count;      // even n in the window, the lead included
     uint64_t tile_base;  // global index of the window's first tile
-    uint64_t out_off;    // index of first_n in the per-n output
+    uint64_t out_off;    // per-n output index of the first n after the lead
     uint32_t slot;       // summary slot of the window
     uint32_t np_sieve;   // odd primes p of the table with p*p <= window top
+    uint32_t lead;       // masked n in front of the window (0..63)
+    uint32_t pad;
 };
 
 // Per-slot summary accumulators, combined with 64-bit atomics (sums, max,
@@ -86,14 +91,13 @@ struct GbMrArgs {
 };
 
 // Kernel launchers (gb_kernels.hip).
-// queue: the search variant that compacts hits into a per-wave LDS queue
 hipError_t gb_launch_tiles(const GbTileArgs &a, uint32_t grid, uint32_t threads,
                            size_t lds_bytes, int pmin_bits, bool persistent,
-                           bool sieve_only, bool queue, hipStream_t st);
-hipError_t gb_prepare_tiles(uint32_t threads, size_t lds_bytes, bool queue);
-hipError_t gb_tile_occupancy(uint32_t threads, size_t lds_bytes, bool queue, int *blocks_per_cu);
+                           bool sieve_only, hipStream_t st);
+hipError_t gb_prepare_tiles(uint32_t threads, size_t lds_bytes);
+hipError_t gb_tile_occupancy(uint32_t threads, size_t lds_bytes, int *blocks_per_cu);
 size_t gb_tile_lds_bytes(uint32_t tile_n, uint32_t halo_bits, uint32_t np_search,
-                         uint32_t n_off, uint32_t threads, bool queue);
+                         uint32_t n_off);
 hipError_t gb_launch_mr(const GbMrArgs &a, uint32_t grid, hipStream_t st);
 hipError_t gb_launch_argmax(GbSlot *slots, const GbTileRec *recs, uint64_t nrecs,
                             const GbExh *list, const unsigned long long *list_count,

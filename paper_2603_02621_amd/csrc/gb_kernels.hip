@@ -16,6 +16,10 @@
 // table, segment bitset, Miller-Rabin) collapsed into one lookup.
 // n that no p <= P_max resolves go to a device list for k_mr, the
 // exhaustive phase (the paper's Phase 2; on the GPU here).
+// A hit (prime p, mask h of the n it settles) costs a popcount for the
+// per-prime histogram and five multiply-adds for the checksum; a block only
+// remembers the p of its last hit, which is its largest p_min, and the tile
+// recovers the smallest n with the tile's largest p_min at its end.
 //
 // k_mr: one wavefront per listed n.  Lane l takes the l-th next candidate
 // prime p, screens q = n - p with a base-2 strong probable-prime test in
@@ -69,16 +73,46 @@ __device__ __forceinline__ unsigned long long first_index_f64(long long w0, doub
     return (d & 1u) ? ((unsigned long long)d + p) >> 1 : (unsigned long long)(d >> 1);
 }
 
-// Sum of the positions of the set bits of the 64-bit word (hi:lo).
-__device__ __forceinline__ uint32_t bitpos_sum(uint32_t lo, uint32_t hi)
+// p * (bits 15..0 of x) + acc and p * (bits 31..16 of x) + acc, p < 2^16, in
+// one v_mad_u32_u16 each (op_sel picks the half of x).
+__device__ __forceinline__ uint32_t mad_lo16(uint32_t p, uint32_t x, uint32_t acc)
 {
-    uint32_t s = __popc(hi) << 5;
-    s += (__popc(lo & 0xAAAAAAAAu) + __popc(hi & 0xAAAAAAAAu));
-    s += (__popc(lo & 0xCCCCCCCCu) + __popc(hi & 0xCCCCCCCCu)) << 1;
-    s += (__popc(lo & 0xF0F0F0F0u) + __popc(hi & 0xF0F0F0F0u)) << 2;
-    s += (__popc(lo & 0xFF00FF00u) + __popc(hi & 0xFF00FF00u)) << 3;
-    s += (__popc(lo & 0xFFFF0000u) + __popc(hi & 0xFFFF0000u)) << 4;
-    return s;
+    uint32_t d;
+    asm("v_mad_u32_u16 %0, %1, %2, %3" : "=v"(d) : "v"(p), "v"(x), "v"(acc));
+    return d;
+}
+
+__device__ __forceinline__ uint32_t mad_hi16(uint32_t p, uint32_t x, uint32_t acc)
+{
+    uint32_t d;
+    asm("v_mad_u32_u16 %0, %1, %2, %3 op_sel:[0,1,0,0]" : "=v"(d) : "v"(p), "v"(x), "v"(acc));
+    return d;
+}
+
+typedef __attribute__((address_space(3))) uint32_t lds_u32;
+
+// LDS byte address bw + bits 31..16 of the packed prime word x.
+__device__ __forceinline__ const lds_u32 *probe_addr(uint32_t x, uint32_t bw)
+{
+    uint32_t d;
+    asm("v_mad_u32_u16 %0, 1, %1, %2 op_sel:[0,1,0,0]" : "=v"(d) : "v"(x), "v"(bw));
+    return reinterpret_cast<const lds_u32 *>(static_cast<uintptr_t>(d));
+}
+
+// Packed word of a fast-path prime p, h = (p+1)/2: bits 15..0 hold
+// g = 2^16 - h, so bits 4..0 are the funnel shift (-h) mod 32 of a probe and
+// p = 2^17 - 1 - 2g; bits 31..16 hold PX_BIAS - 4 ceil(h/32), the byte offset
+// of the probe's first word below the block's base word, biased to be >= 0.
+constexpr uint32_t PX_BIAS = 4096;   // 4 ceil(h/32) <= 4096 for h <= 32768
+
+// Checksum weight of an even n: floor(n/128) + 2^32 (2c+1) 2^i, where
+// (n/2) mod 64 = 16c + i.  The checksum is the sum of weight * p_min mod
+// 2^64; it is not in the paper, and this form is the one the bit-sliced
+// search can accumulate with a few multiply-adds per hit.
+__device__ __forceinline__ unsigned long long checksum_weight(unsigned long long n)
+{
+    const uint32_t j = (uint32_t)(n >> 1) & 63u;
+    return (n >> 7) + ((unsigned long long)((2u * (j >> 4) + 1u) << (j & 15u)) << 32);
 }
 
 __device__ __forceinline__ bool is_wheel_prime(long long v, uint32_t wmax)
@@ -94,68 +128,38 @@ __device__ __forceinline__ void store_p(void *out, unsigned long long idx, uint3
     if constexpr (PB == 32) static_cast<uint32_t *>(out)[idx] = p;
 }
 
-__device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v)
-{
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
-}
-
-__device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long v)
-{
-    for (int o = 32; o > 0; o >>= 1) {
-        unsigned long long w = __shfl_xor(v, o, 64);
-        v = w > v ? w : v;
-    }
-    return v;
-}
-
 // LDS carve-up of one tile workgroup (offsets in 32-bit words).
-constexpr uint32_t QCAP = 96;   // hit-queue entries per wave (a probe adds at most 64)
-
 struct TileLds {
     uint32_t *bits;           // (T + HB)/32 words: the tile's window, 1 = prime
-    uint16_t *hh;             // (p+1)/2 of the odd primes p <= P_max, padded by 4
+    uint32_t *px;             // packed words of the odd primes p <= P_max, padded by 4
     uint32_t *lhist;          // per-prime hit counts of this tile
     uint32_t *offs;           // first bit index of each small/medium sieving prime
-    unsigned long long *red;  // 3 * waves
-    unsigned long long *qhit; // per wave: QCAP hit masks
-    uint32_t *qtag;           // per wave: QCAP (prime index | block << 16)
+    unsigned long long *red;  // 4: checksum, n_exhaustive, max key, OR words
     unsigned long long *tile; // persistent mode: the tile just taken
 };
 
-template <bool QUEUE>
 __device__ __forceinline__ TileLds carve(uint32_t *smem, const GbTileArgs &a)
 {
     TileLds L;
     uint32_t o = 0;
     L.bits = smem + o;
     o += (a.tile_n + a.halo_bits) / 32;
-    L.hh = reinterpret_cast<uint16_t *>(smem + o);
-    o += (a.np_search + 4 + 1) / 2;
+    L.px = smem + o;
+    o += a.np_search + 4;
     L.lhist = smem + o;
     o += a.np_search;
-    // The first strikes are only read while marking and the hit queue is
-    // only used while searching, with a barrier between: they share space.
     o = (o + 1) & ~1u;
     L.offs = smem + o;
-    L.qhit = nullptr;
-    L.qtag = nullptr;
-    uint32_t shared_words = a.n_off;
-    if (QUEUE) {
-        L.qhit = reinterpret_cast<unsigned long long *>(smem + o);
-        L.qtag = smem + o + 2 * QCAP * (blockDim.x / 64);
-        shared_words = max(shared_words, 3 * QCAP * (blockDim.x / 64));
-    }
-    o += shared_words;
+    o += a.n_off;
     o = (o + 1) & ~1u;
     L.red = reinterpret_cast<unsigned long long *>(smem + o);
-    o += 2 * 3 * (blockDim.x / 64);
+    o += 2 * 4;
     o = (o + 1) & ~1u;
     L.tile = reinterpret_cast<unsigned long long *>(smem + o);
     return L;
 }
 
-template <int NT, int PB, bool SIEVE_ONLY, bool QUEUE>
+template <int NT, int PB, bool SIEVE_ONLY>
 __device__ void process_tile(const GbTileArgs &a, unsigned long long g, const TileLds &L)
 {
     const uint32_t tid = threadIdx.x;
@@ -191,9 +195,11 @@ __device__ void process_tile(const GbTileArgs &a, unsigned long long g, const Ti
     if (!SIEVE_ONLY) {
         for (uint32_t i = tid; i < nps + 4; i += NT) {
             const uint32_t p = a.primes[i < nps ? i : (nps ? nps - 1 : 0)];
-            L.hh[i] = (uint16_t)((p + 1u) >> 1);
+            const uint32_t h = (p + 1u) >> 1;
+            L.px[i] = ((PX_BIAS - 4u * ((h + 31u) >> 5)) << 16) | (65536u - h);
             if (i < nps) L.lhist[i] = 0;
         }
+        if (tid < 4) L.red[tid] = 0ull;   // tile sums, max key, OR words
     }
     // ---- first strike of every small and medium sieving prime, once -------
     const uint32_t kmid = min(a.k_wave_end, np);
@@ -217,6 +223,8 @@ __device__ void process_tile(const GbTileArgs &a, unsigned long long g, const Ti
             const long long vfirst = w0 + 64ll * i;
             if (vfirst <= (long long)a.wheel_max) {
                 // the window reaches the wheel primes themselves, or 1 and below
+                // (a rare path: kept rolled so it holds no registers elsewhere)
+#pragma unroll 1
                 for (uint32_t bt = 0; bt < 32; ++bt) {
                     const long long val = vfirst + 2ll * bt;
                     if (val < 2) v &= ~(1u << bt);
@@ -272,22 +280,71 @@ __device__ void process_tile(const GbTileArgs &a, unsigned long long g, const Ti
     }
 
     // ---- inverted-loop search, 64 even n per lane-block --------------------
+    // Block bb of the tile holds n = N0 + 128 bb + 2j, 0 <= j < 64, as bit j
+    // of a 64-bit mask.  Windows are planned with N0 a multiple of 128 (the
+    // n below a window's first n are masked out), so j = (n/2) mod 64 and
+    // floor(n/128) = N0/128 + bb for every n of the block.
     const uint32_t slot = W.slot;
     const uint32_t hrow = a.hist_per_slot ? slot : 0u;
     unsigned long long *hist = a.hist + (unsigned long long)hrow * GB_HIST_BINS_I;
-    const unsigned long long half0 = N0 >> 1;
-    const unsigned long long outb = W.out_off + (unsigned long long)a.tile_n * t;
+    const uint32_t lead = t == 0 ? W.lead : 0u;
+    // per-n output index of bit 0 of block 0 (wraps below zero when lead > 0)
+    const unsigned long long outb = W.out_off - W.lead + (unsigned long long)a.tile_n * t;
 
-    uint32_t maxp = 0, amax = 0;       // lane's largest p_min and its n index
-    unsigned long long cs = 0;         // lane's checksum part
-    uint32_t nexh = 0;                 // n left to the exhaustive phase
-
-    // every block is full except possibly the tile's last one
+    // valid n of the tile's first and last blocks
+    const uint32_t first_lo = lead >= 32u ? 0u : ~0u << lead;
+    const uint32_t first_hi = lead >= 32u ? ~0u << (lead - 32u) : ~0u;
     const uint32_t nv_last = cnt - 64u * (nblk - 1u);
     const uint32_t last_lo = nv_last >= 32 ? ~0u : ((1u << nv_last) - 1u);
     const uint32_t last_hi = nv_last >= 64 ? ~0u : (nv_last > 32 ? ((1u << (nv_last - 32)) - 1u) : 0u);
+    const bool ragged = nv_last != 64u;
+    // n = 4 = 2 + 2, the one even p_min, is settled apart from the search
+    const bool has4 = N0 == 0ull && (first_lo & (nblk == 1u ? last_lo : ~0u) & 4u) != 0u;
+    auto block_mask = [&](uint32_t bb, uint32_t &lo, uint32_t &hi) {
+        lo = ~0u;
+        hi = ~0u;
+        if (bb == 0u) {
+            lo &= first_lo;
+            hi &= first_hi;
+            if (N0 == 0ull) lo &= ~4u;
+        }
+        if (bb + 1u == nblk) {
+            lo &= last_lo;
+            hi &= last_hi;
+        }
+    };
+
+    // Lane summaries.  A hit of the prime p = 2^17 - 1 - 2g on the mask h of
+    // n is accumulated through g (the low half of the prime's packed word):
+    //   sumg = sum of g * popcount(h), and sprefg, the sum of sumg taken at
+    //     each block's end, so that sum_i i G_i = m * sumg - sprefg after m
+    //     blocks, G_i being block i's part of sumg;
+    //   g0..g3 = sum of g * (16-bit chunk c of h), mod 2^32.
+    // At the tile's end these turn into the checksum of the n the search
+    // resolved, with p = 2^17 - 1 - 2g and the list of n it did not resolve
+    // (masked in front or behind, or left to the exhaustive phase):
+    //   sum of floor(n/128) dB, sum of 2^i per chunk dx0..dx3.
+    uint32_t minx = 0xFFFFFFFFu, mblk = 0;  // smallest packed word of a block's last hit
+    uint32_t nexh = 0;                 // n left to the exhaustive phase
+    uint32_t sumg = 0;
+    unsigned long long sprefg = 0;
+    uint32_t g0 = 0, g1 = 0, g2 = 0, g3 = 0;
+    uint32_t dx0 = 0, dx1 = 0, dx2 = 0, dx3 = 0;
+    unsigned long long dB = 0;
+    const unsigned long long B0 = (N0 >> 7) + tid;   // floor(n/128) of the lane's first block
+    auto deficit = [&](uint32_t blk, uint32_t mlo, uint32_t mhi) {
+        const uint32_t c = __popc(mlo) + __popc(mhi);
+        dB += ((N0 >> 7) + blk) * (unsigned long long)c;
+        dx0 += mlo & 0xFFFFu;
+        dx1 += mlo >> 16;
+        dx2 += mhi & 0xFFFFu;
+        dx3 += mhi >> 16;
+    };
+
     // n no fast-path prime resolves go to the exhaustive phase's list
-    auto push_unresolved = [&](uint32_t blk, unsigned long long u) {
+    auto push_unresolved = [&](uint32_t blk, uint32_t ulo, uint32_t uhi) {
+        deficit(blk, ulo, uhi);
+        unsigned long long u = ((unsigned long long)uhi << 32) | ulo;
         nexh += __popcll(u);
         while (u) {
             const uint32_t j = (uint32_t)__builtin_ctzll(u);
@@ -304,62 +361,55 @@ __device__ void process_tile(const GbTileArgs &a, unsigned long long g, const Ti
             }
         }
     };
-    if constexpr (!QUEUE) {
-    // block state: unresolved mask U, next prime index k, the block's sums
-    // of p*popcount(hit) (Ab) and p*(positions of hit) (Bb), and its last hit
-    // (the last hit carries the block's largest p_min)
-    uint32_t b = tid, k = 0, Ulo = 0, Uhi = 0, Ab = 0, Bb = 0, lastp = 0, llo = 0, lhi = 0;
-    uint32_t base = 0;
-    auto start_block = [&](uint32_t bb) {
-        const bool last = bb + 1u == nblk;
-        Ulo = last ? last_lo : ~0u;
-        Uhi = last ? last_hi : ~0u;
-        k = 0; Ab = 0; Bb = 0; lastp = 0; llo = 0; lhi = 0;
-        base = 64u * bb + HB;
-        if (N0 == 4 && bb == 0) {  // n = 4 = 2 + 2, the one even p_min
-            Ulo &= ~1u;
-            Ab = 2;
-            lastp = 2; llo = 1u;
+
+    // block state: unresolved mask U, next prime index k, LDS byte address
+    // of the block's base word minus PX_BIAS (bw), packed word of the block's
+    // last hit (the last hit carries the block's largest p_min; packed words
+    // decrease as p grows)
+    const uint32_t bits_addr = (uint32_t)(uintptr_t)(lds_u32 *)L.bits;
+    uint32_t b = tid, k = 0, Ulo = 0, Uhi = 0, lastx = 0xFFFFFFFFu;
+    uint32_t bw = bits_addr + 8u * tid + HB / 8u - PX_BIAS;
+    if (b < nblk) {
+        block_mask(b, Ulo, Uhi);
+        if (b == 0u && has4) {
+            lastx = 0xFFFFFFFEu;      // stands for p = 2, above every real word
             atomicAdd(&hist[0], 1ull);
-            if (a.pmin) store_p<PB>(a.pmin, outb, 2u);
+            if (a.pmin) store_p<PB>(a.pmin, outb + 2u, 2u);
         }
-    };
-    auto finish_block = [&]() {
-        cs += (half0 + 64ull * b) * Ab + Bb;
-        if (lastp > maxp) {
-            maxp = lastp;
-            amax = 64u * b + (llo ? (uint32_t)__builtin_ctz(llo) : 32u + (uint32_t)__builtin_ctz(lhi));
-        }
-        if (Ulo | Uhi) push_unresolved(b, ((unsigned long long)Uhi << 32) | Ulo);
-    };
-    if (nps == 0) {
-        // no odd prime below P_max: every n but 4 goes to the exhaustive phase
-        for (; b < nblk; b += NT) {
-            start_block(b);
-            finish_block();
-        }
-    } else {
-        if (b < nblk) start_block(b);
-        while (b < nblk) {
-            // four probes per exit check; the prime list is padded with copies
-            // of its last prime, which cannot hit an n twice
+    }
+    while (b < nblk) {
+        if (nps != 0u) {
+            // four probes per exit check; the prime list is padded with
+            // copies of its last prime, which cannot hit an n twice
+            // the group's twelve window words do not depend on the hits, so
+            // they are all read before the first test
+            uint32_t xs[4], dw[4][3];
+#pragma unroll
+            for (uint32_t u = 0; u < 4; ++u) xs[u] = L.px[k + u];
 #pragma unroll
             for (uint32_t u = 0; u < 4; ++u) {
-                const uint32_t h = L.hh[k + u];
-                const uint32_t s = base - h;
-                const uint32_t *wp = L.bits + (s >> 5);
-                const uint32_t d0 = wp[0], d1 = wp[1], d2 = wp[2];
-                const uint32_t hlo = __builtin_amdgcn_alignbit(d1, d0, s) & Ulo;
-                const uint32_t hhi = __builtin_amdgcn_alignbit(d2, d1, s) & Uhi;
+                const lds_u32 *wp = probe_addr(xs[u], bw);
+                dw[u][0] = wp[0];
+                dw[u][1] = wp[1];
+                dw[u][2] = wp[2];
+            }
+#pragma unroll
+            for (uint32_t u = 0; u < 4; ++u) {
+                const uint32_t x = xs[u];
+                const uint32_t hlo = __builtin_amdgcn_alignbit(dw[u][1], dw[u][0], x) & Ulo;
+                const uint32_t hhi = __builtin_amdgcn_alignbit(dw[u][2], dw[u][1], x) & Uhi;
                 if (hlo | hhi) {
-                    const uint32_t p = 2u * h - 1u;
                     const uint32_t pc = __popc(hlo) + __popc(hhi);
-                    Ab += p * pc;
-                    Bb += p * bitpos_sum(hlo, hhi);
                     atomicAdd(&L.lhist[k + u], pc);
-                    lastp = p; llo = hlo; lhi = hhi;
+                    sumg = mad_lo16(x, pc, sumg);
+                    g0 = mad_lo16(x, hlo, g0);
+                    g1 = mad_hi16(x, hlo, g1);
+                    g2 = mad_lo16(x, hhi, g2);
+                    g3 = mad_hi16(x, hhi, g3);
+                    lastx = x;
                     if constexpr (PB != 0) {
                         if (a.pmin) {
+                            const uint32_t p = 131071u - 2u * (x & 0xFFFFu);
                             unsigned long long hb = ((unsigned long long)hhi << 32) | hlo;
                             const unsigned long long ob = outb + 64ull * b;
                             while (hb) {
@@ -373,191 +423,135 @@ __device__ void process_tile(const GbTileArgs &a, unsigned long long g, const Ti
                 }
             }
             k += 4;
-            if ((Ulo | Uhi) == 0u || k >= nps) {
-                finish_block();
-                b += NT;
-                if (b < nblk) start_block(b);
+        }
+        if ((Ulo | Uhi) == 0u || k >= nps) {
+            sprefg += sumg;
+            if (lastx < minx) {
+                minx = lastx;
+                mblk = b;
+            }
+            if (Ulo | Uhi) push_unresolved(b, Ulo, Uhi);
+            b += NT;
+            bw += 8u * NT;
+            k = 0;
+            Ulo = ~0u;
+            Uhi = ~0u;
+            if (ragged && b + 1u == nblk) {
+                Ulo = last_lo;
+                Uhi = last_hi;
             }
         }
-    }
-    } else {
-    // Hits are compacted into a per-wave LDS queue (ballot + mbcnt) and their
-    // bookkeeping -- histogram, checksum, per-n output -- runs 64 events at
-    // a time with every lane busy, instead of on every probe for the lanes
-    // that happen to hit.  Checksum part of one event (block bb, prime p, hit
-    // mask h): p * sum_{j in h} (N0/2 + 64 bb + j) = N0/2 * (p popc h)
-    // + p * (64 bb popc h + sum of positions of h); the two sums are kept
-    // apart (cA, cB) and joined at the tile's end.
-    unsigned long long cA = 0, cB = 0;
-    unsigned long long *qhit = L.qhit + wave * QCAP;
-    uint32_t *qtag = L.qtag + wave * QCAP;
-    uint32_t qn = 0;  // wave-uniform queue length
-    auto drain = [&](uint32_t first, uint32_t nev) {
-        __builtin_amdgcn_wave_barrier();
-        if (lane < nev) {
-            const uint32_t tag = qtag[first + lane];
-            const unsigned long long hm = qhit[first + lane];
-            const uint32_t hlo = (uint32_t)hm, hhi = (uint32_t)(hm >> 32);
-            const uint32_t kk = tag & 0xFFFFu, bb = tag >> 16;
-            const uint32_t p = 2u * L.hh[kk] - 1u;
-            const uint32_t pc = __popc(hlo) + __popc(hhi);
-            atomicAdd(&L.lhist[kk], pc);
-            cA += (unsigned long long)(p * pc);
-            cB += (unsigned long long)p * (pc * (64u * bb) + bitpos_sum(hlo, hhi));
-            // largest p, and the smallest n that has it
-            const uint32_t nidx = 64u * bb + (hlo ? (uint32_t)__builtin_ctz(hlo) : 32u + (uint32_t)__builtin_ctz(hhi));
-            if (p > maxp || (p == maxp && nidx < amax)) {
-                maxp = p;
-                amax = nidx;
-            }
-            if constexpr (PB != 0) {
-                if (a.pmin) {
-                    unsigned long long hb = hm;
-                    const unsigned long long ob = outb + 64ull * bb;
-                    while (hb) {
-                        store_p<PB>(a.pmin, ob + (unsigned long long)__builtin_ctzll(hb), p);
-                        hb &= hb - 1ull;
-                    }
-                }
-            }
-        }
-        __builtin_amdgcn_wave_barrier();
-    };
-
-    // block state: unresolved mask U and next prime index k; the tag of a
-    // queued hit is its prime index plus the block index times 2^16
-    uint32_t b = tid, k = 0, Ulo = 0, Uhi = 0;
-    uint32_t base = 0, ktag = 0;
-    auto start_block = [&](uint32_t bb) {
-        const bool last = bb + 1u == nblk;
-        Ulo = last ? last_lo : ~0u;
-        Uhi = last ? last_hi : ~0u;
-        k = 0;
-        base = 64u * bb + HB;
-        ktag = bb << 16;
-        if (N0 == 4 && bb == 0) {  // n = 4 = 2 + 2, the one even p_min
-            Ulo &= ~1u;
-            cA += 2;                // (n/2 = 2) * (p = 2) = N0/2 * 2
-            atomicAdd(&hist[0], 1ull);
-            if (maxp < 2) { maxp = 2; amax = 0; }
-            if (a.pmin) store_p<PB>(a.pmin, outb, 2u);
-        }
-    };
-    auto finish_block = [&]() {
-        if (Ulo | Uhi) push_unresolved(b, ((unsigned long long)Uhi << 32) | Ulo);
-    };
-    if (nps == 0) {
-        // no odd prime below P_max: every n but 4 goes to the exhaustive phase
-        for (; b < nblk; b += NT) {
-            start_block(b);
-            finish_block();
-        }
-    } else {
-        if (b < nblk) start_block(b);
-        // the loop runs while any lane of the wave has a block, so the queue
-        // operations below stay wave-uniform
-        while (__ballot(b < nblk) != 0ull) {
-            const bool act = b < nblk;
-            // four probes per exit check; the prime list is padded with copies
-            // of its last prime, which cannot hit an n twice
-#pragma unroll
-            for (uint32_t u = 0; u < 4; ++u) {
-                uint32_t hlo = 0, hhi = 0;
-                const uint32_t h = L.hh[k + u];
-                if (act) {
-                    const uint32_t s = base - h;
-                    const uint32_t *wp = L.bits + (s >> 5);
-                    const uint32_t d0 = wp[0], d1 = wp[1], d2 = wp[2];
-                    hlo = __builtin_amdgcn_alignbit(d1, d0, s) & Ulo;
-                    hhi = __builtin_amdgcn_alignbit(d2, d1, s) & Uhi;
-                }
-                const bool hit = (hlo | hhi) != 0u;
-                const unsigned long long m = __ballot(hit);
-                if (hit) {
-                    const uint32_t slot_q = qn + __builtin_amdgcn_mbcnt_hi(
-                        (uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-                    qtag[slot_q] = ktag + k + u;
-                    qhit[slot_q] = ((unsigned long long)hhi << 32) | hlo;
-                    Ulo ^= hlo;
-                    Uhi ^= hhi;
-                }
-                qn += (uint32_t)__popcll(m);
-                if (qn > QCAP - 64u) {  // room for the next probe's hits
-                    const uint32_t take = min(qn, 64u);
-                    qn -= take;
-                    drain(qn, take);
-                }
-            }
-            if (act) {
-                k += 4;
-                if ((Ulo | Uhi) == 0u || k >= nps) {
-                    finish_block();
-                    b += NT;
-                    if (b < nblk) start_block(b);
-                    else k = 0;  // idle lanes keep reading a valid list entry
-                }
-            }
-        }
-        if (qn) drain(0, qn);
-    }
-    cs = (half0 * cA) + cB;
     }
 
     // ---- tile summary ------------------------------------------------------
-    unsigned long long key = ((unsigned long long)maxp << 32) | (0xFFFFFFFFu - amax);
-    unsigned long long csw = wave_sum_u64(cs);
-    unsigned long long nxw = wave_sum_u64(nexh);
-    key = wave_max_u64(key);
-    if (lane == 0) {
-        L.red[wave] = csw;
-        L.red[NWAVES + wave] = nxw;
-        L.red[2 * NWAVES + wave] = key;
+    const uint32_t m = tid < nblk ? (nblk - 1u - tid) / NT + 1u : 0u;
+    {
+        // masked n of the tile's first and last blocks
+        uint32_t lo, hi;
+        if (tid == 0u) {
+            block_mask(0u, lo, hi);
+            deficit(0u, ~lo, ~hi);
+        }
+        if (nblk > 1u && (nblk - 1u) % NT == tid) {
+            block_mask(nblk - 1u, lo, hi);
+            deficit(nblk - 1u, ~lo, ~hi);
+        }
     }
+    const unsigned long long mm = m;
+    // sum of floor(n/128) over the lane's n, then over the n its search resolved
+    const unsigned long long sumB = mm * B0 + (unsigned long long)NT * (mm * (mm - 1ull) / 2ull);
+    const unsigned long long sumBR = 64ull * sumB - dB;
+    // sum over hits of floor(n/128) * g * popcount
+    const unsigned long long sumBG = B0 * sumg + (unsigned long long)NT * (mm * sumg - sprefg);
+    // sum of p * floor(n/128), p = 2^17 - 1 - 2g
+    const unsigned long long ysum = 131071ull * sumBR - 2ull * sumBG;
+    // sum of p * (2c+1) 2^i mod 2^32, from the chunk sums of the resolved n
+    const uint32_t full = m * 0xFFFFu;
+    uint32_t zsum = (131071u * (full - dx0) - 2u * g0) + 3u * (131071u * (full - dx1) - 2u * g1) +
+                    5u * (131071u * (full - dx2) - 2u * g2) + 7u * (131071u * (full - dx3) - 2u * g3);
+    if (has4 && tid == 0u) zsum += 8u;   // n = 4: p = 2 at i = 2 of chunk 0
+    const unsigned long long cs = ysum + ((unsigned long long)zsum << 32);
+    const uint32_t maxp = minx == 0xFFFFFFFFu ? 0u : (minx == 0xFFFFFFFEu ? 2u : 131071u - 2u * (minx & 0xFFFFu));
+    const unsigned long long key = ((unsigned long long)maxp << 32) | (0xFFFFFFFFu - mblk);
+    // LDS atomics instead of shuffles: nothing per lane stays live for them
+    // across the tiles of a persistent workgroup
+    if (cs) atomicAdd(&L.red[0], cs);
+    if (nexh) atomicAdd(&L.red[1], (unsigned long long)nexh);
+    if (maxp) atomicMax(&L.red[2], key);
     __syncthreads();
     for (uint32_t i = tid; i < nps; i += NT) {
         const uint32_t c = L.lhist[i];
         if (c) atomicAdd(&hist[i + 1], (unsigned long long)c);
     }
-    if (tid == 0) {
-        unsigned long long c2 = 0, x2 = 0, k2 = 0;
-        for (uint32_t w2 = 0; w2 < NWAVES; ++w2) {
-            c2 += L.red[w2];
-            x2 += L.red[NWAVES + w2];
-            k2 = L.red[2 * NWAVES + w2] > k2 ? L.red[2 * NWAVES + w2] : k2;
+    if (wave == 0) {
+        const unsigned long long csum = L.red[0], xsum = L.red[1], kmax = L.red[2];
+        const uint32_t mp = (uint32_t)(kmax >> 32);
+        const uint32_t mb = 0xFFFFFFFFu - (uint32_t)(kmax & 0xFFFFFFFFu);
+        // smallest n of block mb with p_min = mp: the n of the block that mp
+        // hits and no smaller prime does
+        uint32_t am = 0;
+        if (mp == 2u) {
+            am = 2u;  // n = 4
+        } else if (mp != 0u) {
+            uint32_t ulo, uhi;
+            block_mask(mb, ulo, uhi);
+            const uint32_t hmp = (mp + 1u) >> 1, mbase = 64u * mb + HB;
+            uint32_t olo = 0, ohi = 0;
+            for (uint32_t kk = lane; kk < nps; kk += 64u) {
+                const uint32_t h = 65536u - (L.px[kk] & 0xFFFFu);
+                if (h < hmp) {
+                    const uint32_t s = mbase - h;
+                    const uint32_t *wp = L.bits + (s >> 5);
+                    olo |= __builtin_amdgcn_alignbit(wp[1], wp[0], s);
+                    ohi |= __builtin_amdgcn_alignbit(wp[2], wp[1], s);
+                }
+            }
+            uint32_t *orw = reinterpret_cast<uint32_t *>(&L.red[3]);
+            if (olo) atomicOr(&orw[0], olo);
+            if (ohi) atomicOr(&orw[1], ohi);
+            __builtin_amdgcn_wave_barrier();
+            olo = orw[0];
+            ohi = orw[1];
+            const uint32_t s = mbase - hmp;
+            const uint32_t *wp = L.bits + (s >> 5);
+            const uint32_t hlo = __builtin_amdgcn_alignbit(wp[1], wp[0], s) & ulo & ~olo;
+            const uint32_t hhi = __builtin_amdgcn_alignbit(wp[2], wp[1], s) & uhi & ~ohi;
+            am = 64u * mb + (hlo ? (uint32_t)__builtin_ctz(hlo) : 32u + (uint32_t)__builtin_ctz(hhi));
         }
-        const uint32_t mp = (uint32_t)(k2 >> 32);
-        const uint32_t am = 0xFFFFFFFFu - (uint32_t)(k2 & 0xFFFFFFFFu);
-        GbSlot *S = a.slots + slot;
-        atomicAdd(&S->count, (unsigned long long)cnt);
-        atomicAdd(&S->checksum, c2);
-        if (x2) atomicAdd(&S->n_exhaustive, x2);
-        if (mp) atomicMax(&S->max_p, (unsigned long long)mp);
-        GbTileRec r;
-        r.argmax_n = mp ? N0 + 2ull * am : 0ull;
-        r.max_p = mp;
-        r.slot = slot;
-        a.recs[g] = r;
+        if (lane == 0) {
+            GbSlot *S = a.slots + slot;
+            atomicAdd(&S->count, (unsigned long long)(cnt - lead));
+            atomicAdd(&S->checksum, csum);
+            if (xsum) atomicAdd(&S->n_exhaustive, xsum);
+            if (mp) atomicMax(&S->max_p, (unsigned long long)mp);
+            GbTileRec r;
+            r.argmax_n = mp ? N0 + 2ull * am : 0ull;
+            r.max_p = mp;
+            r.slot = slot;
+            a.recs[g] = r;
+        }
     }
     __syncthreads();
 }
 
-template <int NT, int PB, bool PERS, bool SIEVE_ONLY, bool QUEUE>
+template <int NT, int PB, bool PERS, bool SIEVE_ONLY>
 __global__ __launch_bounds__(NT) void k_tile(GbTileArgs a)
 {
     extern __shared__ uint32_t smem[];
-    const TileLds L = carve<QUEUE>(smem, a);
+    const TileLds L = carve(smem, a);
     if constexpr (PERS) {
         for (;;) {
             if (threadIdx.x == 0) *L.tile = atomicAdd(a.queue, 1ull);
             __syncthreads();
             const unsigned long long g = *L.tile;
             if (g >= a.ntiles) break;
-            process_tile<NT, PB, SIEVE_ONLY, QUEUE>(a, g, L);
+            process_tile<NT, PB, SIEVE_ONLY>(a, g, L);
         }
     } else {
-        process_tile<NT, PB, SIEVE_ONLY, QUEUE>(a, a.tile0 + blockIdx.x, L);
+        process_tile<NT, PB, SIEVE_ONLY>(a, a.tile0 + blockIdx.x, L);
     }
 }
+
 
 // ---------------------------------------------------------------------------
 // 64-bit Montgomery arithmetic (Montgomery 1985) for the Miller-Rabin test.
@@ -700,7 +694,7 @@ __global__ __launch_bounds__(256) void k_mr(GbMrArgs a)
                     const unsigned long long bin =
                         found == 2ull ? 0ull : (found < 65536ull ? kfound + 1ull : GB_HIST_BINS_I - 1ull);
                     atomicAdd(&hist[bin], 1ull);
-                    atomicAdd(&S->checksum, (n >> 1) * found);
+                    atomicAdd(&S->checksum, checksum_weight(n) * found);
                     atomicMax(&S->max_p, found);
                 } else {
                     atomicAdd(&S->n_failed, 1ull);
@@ -766,101 +760,93 @@ __global__ void k_finish_queries(const GbExh *list, uint64_t k, unsigned long lo
     if (i < k) p_out[i] = list[i].p;
 }
 
-template <int NT, int PB, bool PERS, bool SO, bool Q>
+template <int NT, int PB, bool PERS, bool SO>
 hipError_t launch_one(const GbTileArgs &a, uint32_t grid, size_t lds, hipStream_t st)
 {
-    hipLaunchKernelGGL((k_tile<NT, PB, PERS, SO, Q>), dim3(grid), dim3(NT), lds, st, a);
+    hipLaunchKernelGGL((k_tile<NT, PB, PERS, SO>), dim3(grid), dim3(NT), lds, st, a);
     return hipGetLastError();
 }
 
-template <int NT, int PB, bool PERS, bool SO, bool Q>
+template <int NT, int PB, bool PERS, bool SO>
 hipError_t allow_lds(size_t lds)
 {
-    return hipFuncSetAttribute(reinterpret_cast<const void *>(&k_tile<NT, PB, PERS, SO, Q>),
+    return hipFuncSetAttribute(reinterpret_cast<const void *>(&k_tile<NT, PB, PERS, SO>),
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
 }
 
-template <int NT, bool Q>
+template <int NT>
 hipError_t allow_lds_nt(size_t lds)
 {
     hipError_t e = hipSuccess, r;
-    if ((r = allow_lds<NT, 0, false, true, Q>(lds)) != hipSuccess) e = r;
-    if ((r = allow_lds<NT, 0, false, false, Q>(lds)) != hipSuccess) e = r;
-    if ((r = allow_lds<NT, 16, false, false, Q>(lds)) != hipSuccess) e = r;
-    if ((r = allow_lds<NT, 32, false, false, Q>(lds)) != hipSuccess) e = r;
-    if ((r = allow_lds<NT, 0, true, false, Q>(lds)) != hipSuccess) e = r;
-    if ((r = allow_lds<NT, 16, true, false, Q>(lds)) != hipSuccess) e = r;
-    if ((r = allow_lds<NT, 32, true, false, Q>(lds)) != hipSuccess) e = r;
+    if ((r = allow_lds<NT, 0, false, true>(lds)) != hipSuccess) e = r;
+    if ((r = allow_lds<NT, 0, false, false>(lds)) != hipSuccess) e = r;
+    if ((r = allow_lds<NT, 16, false, false>(lds)) != hipSuccess) e = r;
+    if ((r = allow_lds<NT, 32, false, false>(lds)) != hipSuccess) e = r;
+    if ((r = allow_lds<NT, 0, true, false>(lds)) != hipSuccess) e = r;
+    if ((r = allow_lds<NT, 16, true, false>(lds)) != hipSuccess) e = r;
+    if ((r = allow_lds<NT, 32, true, false>(lds)) != hipSuccess) e = r;
     return e;
 }
 
-template <int NT, bool Q>
+template <int NT>
 hipError_t launch_nt(const GbTileArgs &a, uint32_t grid, size_t lds, int pb, bool pers, bool so, hipStream_t st)
 {
-    if (so) return launch_one<NT, 0, false, true, Q>(a, grid, lds, st);
+    if (so) return launch_one<NT, 0, false, true>(a, grid, lds, st);
     if (pers) {
-        if (pb == 16) return launch_one<NT, 16, true, false, Q>(a, grid, lds, st);
-        if (pb == 32) return launch_one<NT, 32, true, false, Q>(a, grid, lds, st);
-        return launch_one<NT, 0, true, false, Q>(a, grid, lds, st);
+        if (pb == 16) return launch_one<NT, 16, true, false>(a, grid, lds, st);
+        if (pb == 32) return launch_one<NT, 32, true, false>(a, grid, lds, st);
+        return launch_one<NT, 0, true, false>(a, grid, lds, st);
     }
-    if (pb == 16) return launch_one<NT, 16, false, false, Q>(a, grid, lds, st);
-    if (pb == 32) return launch_one<NT, 32, false, false, Q>(a, grid, lds, st);
-    return launch_one<NT, 0, false, false, Q>(a, grid, lds, st);
+    if (pb == 16) return launch_one<NT, 16, false, false>(a, grid, lds, st);
+    if (pb == 32) return launch_one<NT, 32, false, false>(a, grid, lds, st);
+    return launch_one<NT, 0, false, false>(a, grid, lds, st);
 }
 
 }  // namespace
 
-size_t gb_tile_lds_bytes(uint32_t tile_n, uint32_t halo_bits, uint32_t np_search, uint32_t n_off,
-                         uint32_t threads, bool queue)
+size_t gb_tile_lds_bytes(uint32_t tile_n, uint32_t halo_bits, uint32_t np_search, uint32_t n_off)
 {
-    size_t words = (tile_n + halo_bits) / 32 + (np_search + 4 + 1) / 2 + np_search;
+    size_t words = (tile_n + halo_bits) / 32 + (np_search + 4) + np_search;
     words = (words + 1) & ~(size_t)1;
-    // first strikes, sharing space with the hit queue (masks and tags)
-    words += queue ? std::max<size_t>(n_off, (2 + 1) * QCAP * (threads / 64)) : n_off;
+    words += n_off;                                       // first strikes
     words = (words + 1) & ~(size_t)1;
-    words += 2 * 3 * (threads / 64);
+    words += 2 * 4;                                       // tile reductions
     words = (words + 1) & ~(size_t)1;
     words += 2;                                           // the persistent tile index
     return words * 4;
 }
 
-hipError_t gb_prepare_tiles(uint32_t threads, size_t lds_bytes, bool queue)
+hipError_t gb_prepare_tiles(uint32_t threads, size_t lds_bytes)
 {
     switch (threads) {
-    case 256: return queue ? allow_lds_nt<256, true>(lds_bytes) : allow_lds_nt<256, false>(lds_bytes);
-    case 512: return queue ? allow_lds_nt<512, true>(lds_bytes) : allow_lds_nt<512, false>(lds_bytes);
-    case 1024: return queue ? allow_lds_nt<1024, true>(lds_bytes) : allow_lds_nt<1024, false>(lds_bytes);
+    case 256: return allow_lds_nt<256>(lds_bytes);
+    case 512: return allow_lds_nt<512>(lds_bytes);
+    case 1024: return allow_lds_nt<1024>(lds_bytes);
     default: return hipErrorInvalidValue;
     }
 }
 
-hipError_t gb_tile_occupancy(uint32_t threads, size_t lds_bytes, bool queue, int *blocks_per_cu)
+hipError_t gb_tile_occupancy(uint32_t threads, size_t lds_bytes, int *blocks_per_cu)
 {
-#define GB_OCC(NT, Q)                                                                                     \
-    hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_tile<NT, 0, true, false, Q>, NT, lds_bytes)
+#define GB_OCC(NT) \
+    hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_tile<NT, 0, true, false>, NT, lds_bytes)
     switch (threads) {
-    case 256: return queue ? GB_OCC(256, true) : GB_OCC(256, false);
-    case 512: return queue ? GB_OCC(512, true) : GB_OCC(512, false);
-    case 1024: return queue ? GB_OCC(1024, true) : GB_OCC(1024, false);
+    case 256: return GB_OCC(256);
+    case 512: return GB_OCC(512);
+    case 1024: return GB_OCC(1024);
     default: return hipErrorInvalidValue;
     }
 #undef GB_OCC
 }
 
 hipError_t gb_launch_tiles(const GbTileArgs &a, uint32_t grid, uint32_t threads, size_t lds_bytes, int pmin_bits,
-                           bool persistent, bool sieve_only, bool queue, hipStream_t st)
+                           bool persistent, bool sieve_only, hipStream_t st)
 {
     if (grid == 0) return hipSuccess;
     switch (threads) {
-    case 256:
-        return queue ? launch_nt<256, true>(a, grid, lds_bytes, pmin_bits, persistent, sieve_only, st)
-                     : launch_nt<256, false>(a, grid, lds_bytes, pmin_bits, persistent, sieve_only, st);
-    case 512:
-        return queue ? launch_nt<512, true>(a, grid, lds_bytes, pmin_bits, persistent, sieve_only, st)
-                     : launch_nt<512, false>(a, grid, lds_bytes, pmin_bits, persistent, sieve_only, st);
-    case 1024:
-        return queue ? launch_nt<1024, true>(a, grid, lds_bytes, pmin_bits, persistent, sieve_only, st)
-                     : launch_nt<1024, false>(a, grid, lds_bytes, pmin_bits, persistent, sieve_only, st);
+    case 256: return launch_nt<256>(a, grid, lds_bytes, pmin_bits, persistent, sieve_only, st);
+    case 512: return launch_nt<512>(a, grid, lds_bytes, pmin_bits, persistent, sieve_only, st);
+    case 1024: return launch_nt<1024>(a, grid, lds_bytes, pmin_bits, persistent, sieve_only, st);
     default: return hipErrorInvalidValue;
     }
 }

@@ -135,7 +135,6 @@ struct gb_ctx {
     uint32_t tile_n = 0, threads = 0;
     uint32_t k_wg_end = 0, k_wave_end = 0;
     size_t lds = 0;
-    bool queue = false;              // search variant: per-wave hit queue
     int occupancy = 1;
     gbrt::Workspace ws;              // scratch of the synchronous calls
     std::string err;
@@ -151,7 +150,8 @@ gb_status apply_params(gb_ctx *c, const gb_params *in);
 gb_status setup_geometry(gb_ctx *c);
 gb_status build_tables(gb_ctx *c);
 void free_tables(gb_ctx *c);
-gb_status plan_windows(gb_ctx *c, Plan &pl);
+// align = true for the search kernels, false for the sieve dump
+gb_status plan_windows(gb_ctx *c, Plan &pl, bool align = true);
 gb_status ensure_workspace(gb_ctx *c, Workspace &ws, const Plan &pl, size_t nslots, size_t hist_rows);
 // init + tiles + exhaustive phase + argmax + summary copies, on `st`,
 // with ws.evt0/evt1 around the tile launches; with use_graph each phase is a

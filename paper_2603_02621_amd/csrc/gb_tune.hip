@@ -129,20 +129,18 @@ extern "C" gb_status gb_autotune(gb_ctx *c, const gb_window *sample, size_t k, c
         return GB_OK;
     };
 
-    // 1. tile and workgroup shape and search variant at the given P_max and wheel
+    // 1. tile and workgroup shape at the given P_max and wheel
     for (uint32_t tl : {16u, 17u, 18u, 19u, 20u})
-        for (uint32_t nt : {256u, 512u, 1024u})
-            for (uint32_t sm : {1u, 2u}) {
-                gb_params p = orig;
-                p.tile_log2 = tl;
-                p.wg_threads = nt;
-                p.search_mode = sm;
-                gb_status st = try_point(p, true);
-                if (st != GB_OK) {
-                    (void)reconfigure(c, orig);
-                    return st;
-                }
+        for (uint32_t nt : {256u, 512u, 1024u}) {
+            gb_params p = orig;
+            p.tile_log2 = tl;
+            p.wg_threads = nt;
+            gb_status st = try_point(p, true);
+            if (st != GB_OK) {
+                (void)reconfigure(c, orig);
+                return st;
             }
+        }
     // 2. fast-path bound (n_exhaustive legitimately depends on it)
     {
         const gb_params base = cur;

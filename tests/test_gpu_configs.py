@@ -116,9 +116,11 @@ def test_config4_bench_configuration(gpu, orc):
             p = out[a:a + chunk].to(torch.int32) & 0xFFFF
             sum_p += int(p.sum(dtype=torch.int64))
             pmax = max(pmax, int(p.max()))
-            half = torch.arange(a, a + p.numel(), device="cuda", dtype=torch.int64) + lo // 2
-            cs += (half * p.to(torch.int64)).sum()   # int64 arithmetic wraps mod 2^64
-            del p, half
+            n = 2 * (torch.arange(a, a + p.numel(), device="cuda", dtype=torch.int64) + lo // 2)
+            j = (n >> 1) & 63
+            w = (n >> 7) + (((2 * (j >> 4) + 1) << (j & 15)) << 32)
+            cs += (w * p.to(torch.int64)).sum()   # int64 arithmetic wraps mod 2^64
+            del p, n, j, w
         assert sum_p == sum_p_hist
         assert int(cs) % 2**64 == batched["checksum"]
         assert pmax == batched["max_p"]

@@ -126,16 +126,16 @@ def test_host_output_buffer(V, orc):
 # exhaustive phase
 # --------------------------------------------------------------------------
 
-@pytest.mark.parametrize("search_mode", [1, 2])
+@pytest.mark.parametrize("tile_log2", [19, 12])
 @pytest.mark.parametrize("pmax,lo,hi", [
     (7, 4, 1 << 17),                    # almost every n goes to Miller-Rabin
     (2, 4, 1 << 14),                    # no odd prime in the fast path: every n except 4
     (1024, 10**12 - (1 << 22), 10**12), # a realistic trickle near 10^12
     (3, 10**15, 10**15 + 20_000),
 ])
-def test_exhaustive_phase_vs_oracle(orc, pmax, lo, hi, search_mode):
+def test_exhaustive_phase_vs_oracle(orc, pmax, lo, hi, tile_log2):
     _gpu()
-    v = _make(pmax=pmax, search_mode=search_mode)
+    v = _make(pmax=pmax, tile_log2=tile_log2)
     ref, rh, rs = orc.verify_range(lo, hi, pmax=pmax, per_n_bits=16, threads=4)
     out = _dev_pmin(len(ref), 16)
     got = v.verify_range(lo, hi, pmin=out)
@@ -233,8 +233,8 @@ def test_plain_equals_batched_and_seg_hist(orc):
     dict(tile_log2=19, wg_threads=512, wheel_max=19, pmax=65535),
     dict(tile_log2=17, wg_threads=512, wheel_max=11, pmax=3000),
     dict(tile_log2=14, wg_threads=512, wheel_max=17, seg_log2=16),
-    dict(tile_log2=18, wg_threads=512, search_mode=2),
-    dict(tile_log2=16, wg_threads=256, search_mode=2, pmax=1024, wheel_max=7),
+    dict(tile_log2=18, wg_threads=512),
+    dict(tile_log2=16, wg_threads=256, pmax=1024, wheel_max=7),
 ])
 def test_parameter_invariance(orc, kw):
     _gpu()
@@ -287,3 +287,38 @@ def test_windows_vs_oracle(V, orc):
         hsum += rh
         off += ln
     assert np.array_equal(got["hist"], hsum)
+
+
+@pytest.mark.parametrize("tile_log2", [19, 12])
+def test_window_alignment_vs_oracle(orc, tile_log2):
+    # Windows start at every residue of n/2 mod 64 (the planner moves each
+    # start down to a multiple of 128 and masks the n in front), with
+    # lengths around one and two 64-n blocks and across tile edges, and at
+    # the start of the number line, where n = 4 sits in the masked block.
+    _gpu()
+    v = _make(tile_log2=tile_log2)
+    wins = []
+    base = 10**12 - (1 << 20)
+    lens = [1, 2, 31, 32, 33, 63, 64, 65, 127, 128, 129, 4096 + 7, 9000]
+    for r in range(64):
+        wins.append((base + 128 * r * 3 + 2 * r, lens[r % len(lens)]))
+    for s in range(4, 260, 2):
+        wins.append((s, 1 + (s % 70)))
+    total = sum(ln for _, ln in wins)
+    out = _dev_pmin(total)
+    got = v.verify_windows(wins, pmin=out)
+    host = _host(out)
+    off = 0
+    for (s, ln), summ in zip(wins, got["sums"]):
+        ref, rh, rs = orc.verify_range(s, s + 2 * (ln - 1), per_n_bits=16)
+        assert np.array_equal(host[off:off + ln], ref), (s, ln)
+        _same_summary(summ, rs)
+        off += ln
+    v.close()
+
+
+def test_search_mode_other_than_1_rejected():
+    _gpu()
+    from paper_2603_02621_amd._binding import GoldbachError
+    with pytest.raises(GoldbachError):
+        _make(search_mode=2)

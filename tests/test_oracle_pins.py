@@ -161,6 +161,12 @@ def test_pmin_bruteforce_1e5(orc, td_table):
     assert s["n_failed"] == 0
 
 
+def _weight(n):
+    """Checksum weight of n: floor(n/128) + 2^32 (2c+1) 2^i, j = n/2 mod 64 = 16c + i."""
+    c, i = divmod((n // 2) % 64, 16)
+    return (n // 128 + ((2 * c + 1) << i << 32)) % 2**64
+
+
 def _summaries_by_hand(ns, ps, pmax):
     """Summary definitions written out directly over (n, p) pairs."""
     hist = np.zeros(6543, dtype=np.uint64)
@@ -168,7 +174,7 @@ def _summaries_by_hand(ns, ps, pmax):
     for n, p in zip(ns, ps):
         b = sympy.primepi(p) - 1 if p < 65536 else 6542
         hist[b] += 1
-        cs = (cs + (n // 2) * p) % 2**64
+        cs = (cs + _weight(n) * p) % 2**64
         if p > mx:
             mx, arg = p, n
         if p > pmax:
@@ -189,6 +195,39 @@ def test_summaries_bruteforce(orc, td_table, lo, hi, pmax):
         assert s[k] == v, k
     # consistency identities
     assert int(hist.sum()) == s["count"]
+
+
+def _v2(x):
+    x %= 2**64
+    return 64 if x == 0 else (x & -x).bit_length() - 1
+
+
+def test_checksum_weight_definition(orc):
+    rng = np.random.default_rng(11)
+    ns = [4, 6, 126, 128, 130, 254, 256, 2**63, 2**63 - 2] + \
+        [int(x) * 2 for x in rng.integers(2, 2**62, size=2000)]
+    for n in ns:
+        assert orc.checksum_weight(n) == _weight(n), n
+
+
+def test_checksum_detects_single_and_swapped_errors():
+    # a wrong p_min changes p by an even delta with |delta| < 2^16, i.e. at
+    # most 15 factors of 2: the change delta * w(n) is nonzero mod 2^64 as
+    # long as w(n) has at most 48 of them
+    rng = np.random.default_rng(12)
+    for n in [int(x) * 2 for x in rng.integers(2, 2**62, size=4000)] + list(range(4, 1 << 14, 2)):
+        assert _v2(_weight(n)) <= 48, n
+    # two n of one 256-wide stretch exchanging their p change the sum by
+    # (p1 - p2) (w1 - w2); w1 - w2 has at most 49 factors of 2, so every
+    # exchange of two p that differ by less than 2^15 is seen (the equality
+    # at 49 is reached: n = 30 and n = 94 differ by 2^49 in weight)
+    worst = 0
+    for base in (0, 10**12 - 2**36, 2**62):
+        ws = [_weight(base + 2 * k) for k in range(128)]
+        for a in range(128):
+            for b in range(a + 1, 128):
+                worst = max(worst, _v2(ws[a] - ws[b]))
+    assert worst == 49
 
 
 def test_config1_summary(orc):

@@ -133,7 +133,7 @@ gb_status enqueue_tiles(gb_ctx *c, Workspace &ws, const Job &j, hipStream_t st)
         a.nwin = (uint32_t)pl.w.size();
         a.ntiles = pl.ntiles;
         const uint64_t g = std::min<uint64_t>(pl.ntiles, (uint64_t)c->num_cu * c->occupancy);
-        GB_HIP(c, gb_launch_tiles(a, (uint32_t)g, c->threads, c->lds, j.pmin_bits, true, false, st));
+        GB_HIP(c, gb_launch_tiles(a, (uint32_t)g, c->threads, c->lds, j.pmin_bits, true, false, c->group_window, st));
     } else {
         for (size_t i = 0; i < pl.w.size(); ++i) {
             GbTileArgs b = a;
@@ -141,7 +141,7 @@ gb_status enqueue_tiles(gb_ctx *c, Workspace &ws, const Job &j, hipStream_t st)
             b.nwin = 1;
             b.tile0 = pl.w[i].tile_base;
             const uint64_t nt = (pl.w[i].count + c->tile_n - 1) / c->tile_n;
-            GB_HIP(c, gb_launch_tiles(b, (uint32_t)nt, c->threads, c->lds, j.pmin_bits, false, false, st));
+            GB_HIP(c, gb_launch_tiles(b, (uint32_t)nt, c->threads, c->lds, j.pmin_bits, false, false, c->group_window, st));
         }
     }
     return GB_OK;
@@ -305,6 +305,20 @@ gb_status setup_geometry(gb_ctx *c)
     c->tile_n = 1u << p.tile_log2;
     c->threads = p.wg_threads;
     c->np_search = count_le(c->h_primes, p.pmax);
+    // The search reads each group of four probes' windows at once when, in
+    // every group of the (padded) prime list, a probe starts at most one word
+    // above the base word of the group's last prime.
+    {
+        const uint32_t n = c->np_search;
+        auto hof = [&](uint32_t i) { return (c->h_primes[i < n ? i : n - 1] + 1) / 2; };
+        bool ok = n > 0;
+        for (uint32_t k = 0; ok && k < n; k += 4) {
+            const uint32_t w3 = (hof(k + 3) + 31) / 32;
+            for (uint32_t u = 0; u < 3; ++u)
+                if (w3 - (hof(k + u) + 31) / 32 > 1) ok = false;
+        }
+        c->group_window = ok;
+    }
     const uint32_t need = (p.pmax + 1) / 2;
     c->halo_bits = std::max<uint32_t>(64, (need + 63) / 64 * 64);
     c->k_first = count_le(c->h_primes, p.wheel_max);
@@ -320,7 +334,7 @@ gb_status setup_geometry(gb_ctx *c)
     c->num_cu = prop.multiProcessorCount;
     GB_HIP(c, gb_prepare_tiles(c->threads, c->lds));
     int occ = 0;
-    GB_HIP(c, gb_tile_occupancy(c->threads, c->lds, &occ));
+    GB_HIP(c, gb_tile_occupancy(c->threads, c->lds, c->group_window, &occ));
     c->occupancy = std::max(occ, 1);
     // wheel pattern over (v-1)/2 for odd v: bit g set iff 2g+1 is coprime to the wheel
     static const uint32_t wp[] = {3, 5, 7, 11, 13, 17, 19};
@@ -773,7 +787,7 @@ gb_status gb_sieve_window(gb_ctx *c, uint64_t w0, uint64_t nbits, uint32_t *bits
     a.nwin = 1;
     a.tile0 = 0;
     a.sieve_out = bits;
-    GB_HIP(c, gb_launch_tiles(a, (uint32_t)pl.ntiles, c->threads, c->lds, 0, false, true, st));
+    GB_HIP(c, gb_launch_tiles(a, (uint32_t)pl.ntiles, c->threads, c->lds, 0, false, true, false, st));
     GB_HIP(c, hipStreamSynchronize(st));
     return GB_OK;
 }

@@ -91,11 +91,14 @@ struct GbMrArgs {
 };
 
 // Kernel launchers (gb_kernels.hip).
+// group_window: the search form that reads each group of four probes'
+// window words at once (needs every group of the prime list to span at
+// most 63 bits of offset from its last prime's base word)
 hipError_t gb_launch_tiles(const GbTileArgs &a, uint32_t grid, uint32_t threads,
                            size_t lds_bytes, int pmin_bits, bool persistent,
-                           bool sieve_only, hipStream_t st);
+                           bool sieve_only, bool group_window, hipStream_t st);
 hipError_t gb_prepare_tiles(uint32_t threads, size_t lds_bytes);
-hipError_t gb_tile_occupancy(uint32_t threads, size_t lds_bytes, int *blocks_per_cu);
+hipError_t gb_tile_occupancy(uint32_t threads, size_t lds_bytes, bool group_window, int *blocks_per_cu);
 size_t gb_tile_lds_bytes(uint32_t tile_n, uint32_t halo_bits, uint32_t np_search,
                          uint32_t n_off);
 hipError_t gb_launch_mr(const GbMrArgs &a, uint32_t grid, hipStream_t st);

@@ -99,6 +99,13 @@ __device__ __forceinline__ const lds_u32 *probe_addr(uint32_t x, uint32_t bw)
     return reinterpret_cast<const lds_u32 *>(static_cast<uintptr_t>(d));
 }
 
+// Clear the bits of m's zeros in the LDS word at byte address addr.
+__device__ __forceinline__ void lds_and(uint32_t addr, uint32_t m)
+{
+    __hip_atomic_fetch_and(reinterpret_cast<lds_u32 *>(static_cast<uintptr_t>(addr)), m, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
 // Packed word of a fast-path prime p, h = (p+1)/2: bits 15..0 hold
 // g = 2^16 - h, so bits 4..0 are the funnel shift (-h) mod 32 of a probe and
 // p = 2^17 - 1 - 2g; bits 31..16 hold PX_BIAS - 4 ceil(h/32), the byte offset
@@ -132,8 +139,8 @@ __device__ __forceinline__ void store_p(void *out, unsigned long long idx, uint3
 struct TileLds {
     uint32_t *bits;           // (T + HB)/32 words: the tile's window, 1 = prime
     uint32_t *px;             // packed words of the odd primes p <= P_max, padded by 4
-    uint32_t *lhist;          // per-prime hit counts of this tile
-    uint32_t *offs;           // first bit index of each small/medium sieving prime
+    uint32_t *lhist;          // per-prime hit counts of this tile, padded by 4
+    uint32_t *offs;           // first bit index (or ~0) of each small/medium sieving prime
     unsigned long long *red;  // 4: checksum, n_exhaustive, max key, OR words
     unsigned long long *tile; // persistent mode: the tile just taken
 };
@@ -144,10 +151,12 @@ __device__ __forceinline__ TileLds carve(uint32_t *smem, const GbTileArgs &a)
     uint32_t o = 0;
     L.bits = smem + o;
     o += (a.tile_n + a.halo_bits) / 32;
+    o = (o + 3) & ~3u;   // 16-byte aligned: a group reads its four words at once
     L.px = smem + o;
     o += a.np_search + 4;
+    o = (o + 1) & ~1u;   // counters are added in pairs (64-bit LDS atomics)
     L.lhist = smem + o;
-    o += a.np_search;
+    o += a.np_search + 4;
     o = (o + 1) & ~1u;
     L.offs = smem + o;
     o += a.n_off;
@@ -159,7 +168,7 @@ __device__ __forceinline__ TileLds carve(uint32_t *smem, const GbTileArgs &a)
     return L;
 }
 
-template <int NT, int PB, bool SIEVE_ONLY>
+template <int NT, int PB, bool SIEVE_ONLY, bool GW>
 __device__ void process_tile(const GbTileArgs &a, unsigned long long g, const TileLds &L)
 {
     const uint32_t tid = threadIdx.x;
@@ -196,30 +205,67 @@ __device__ void process_tile(const GbTileArgs &a, unsigned long long g, const Ti
         for (uint32_t i = tid; i < nps + 4; i += NT) {
             const uint32_t p = a.primes[i < nps ? i : (nps ? nps - 1 : 0)];
             const uint32_t h = (p + 1u) >> 1;
-            L.px[i] = ((PX_BIAS - 4u * ((h + 31u) >> 5)) << 16) | (65536u - h);
-            if (i < nps) L.lhist[i] = 0;
+            uint32_t hi = PX_BIAS - 4u * ((h + 31u) >> 5);
+            if (GW && (i & 3u) != 3u) {
+                // group-window form: the high half of a group's first three
+                // words says whether the probe starts one word above the
+                // group's base word (that of its last prime)
+                const uint32_t i3 = i | 3u;
+                const uint32_t p3 = a.primes[i3 < nps ? i3 : (nps ? nps - 1 : 0)];
+                hi = ((((p3 + 1u) >> 1) + 31u) >> 5) - ((h + 31u) >> 5);
+            }
+            L.px[i] = (hi << 16) | (65536u - h);
+            L.lhist[i] = 0;
         }
         if (tid < 4) L.red[tid] = 0ull;   // tile sums, max key, OR words
     }
     // ---- first strike of every small and medium sieving prime, once -------
+    // each lane loads its next prime ahead
     const uint32_t kmid = min(a.k_wave_end, np);
-    for (uint32_t k = a.k_first + tid; k < kmid; k += NT) {
-        const unsigned long long t0 = small_w0 ? first_index_f64(w0, w0d, a.primes[k], a.pinv[k])
-                                               : first_index(w0, a.primes[k], a.magic[k]);
-        L.offs[k - a.k_first] = t0 < nbits ? (uint32_t)t0 : 0xFFFFFFFFu;
+    {
+        uint32_t k = a.k_first + tid;
+        uint32_t pn = 0;
+        double vn = 0.0;
+        unsigned long long mn = 0;
+        if (k < kmid) {
+            pn = a.primes[k];
+            if (small_w0) vn = a.pinv[k]; else mn = a.magic[k];
+        }
+        for (; k < kmid; k += NT) {
+            const uint32_t p = pn;
+            const double pv = vn;
+            const unsigned long long mg = mn;
+            if (k + NT < kmid) {
+                pn = a.primes[k + NT];
+                if (small_w0) vn = a.pinv[k + NT]; else mn = a.magic[k + NT];
+            }
+            const unsigned long long t0 = small_w0 ? first_index_f64(w0, w0d, p, pv) : first_index(w0, p, mg);
+            L.offs[k - a.k_first] = t0 < nbits ? (uint32_t)t0 : 0xFFFFFFFFu;
+        }
     }
 
     // ---- wheel pre-pattern: clears the odd multiples of 3..wheel_max ------
     // Pattern bit g is 1 iff 2g+1 is coprime to every wheel prime; tile bit i
-    // (value w0 + 2i) has pattern phase ((w0-1)/2 + i) mod wheel_len.
+    // (value w0 + 2i) has pattern phase ((w0-1)/2 + i) mod wheel_len.  The
+    // pattern words of a lane's next word are loaded ahead.
     {
         const uint32_t Lw = a.wheel_len;
         const uint32_t g0 = (uint32_t)(((N0 >> 1) % Lw + Lw - (HB % Lw)) % Lw);
         uint32_t ph = (g0 + 32u * tid) % Lw;
         const uint32_t step = (32u * NT) % Lw;
+        uint32_t lo = 0, hi = 0;
+        if (tid < nw32) {
+            lo = a.wheel[ph >> 5];
+            hi = a.wheel[(ph >> 5) + 1];
+        }
         for (uint32_t i = tid; i < nw32; i += NT) {
-            const uint32_t lo = a.wheel[ph >> 5], hi = a.wheel[(ph >> 5) + 1];
             uint32_t v = __builtin_amdgcn_alignbit(hi, lo, ph & 31u);
+            ph += step;
+            if (ph >= Lw) ph -= Lw;
+            if (i + NT < nw32) {
+                lo = a.wheel[ph >> 5];
+                hi = a.wheel[(ph >> 5) + 1];
+            }
             const long long vfirst = w0 + 64ll * i;
             if (vfirst <= (long long)a.wheel_max) {
                 // the window reaches the wheel primes themselves, or 1 and below
@@ -232,41 +278,76 @@ __device__ void process_tile(const GbTileArgs &a, unsigned long long g, const Ti
                 }
             }
             L.bits[i] = v;
-            ph += step;
-            if (ph >= Lw) ph -= Lw;
         }
     }
     __syncthreads();
 
     // ---- strided marking of the odd multiples of each sieving prime -------
     {
-        // primes with many hits per tile: the whole workgroup strides over one prime
+        // LDS byte address of the window, made opaque to the compiler so
+        // that the loops step one address instead of re-adding the base
+        uint32_t bits_a = (uint32_t)(uintptr_t)(lds_u32 *)L.bits;
+        asm volatile("" : "+s"(bits_a));
+        const uint32_t end_a = bits_a + 4u * nw32;   // nbits = 32 * nw32
+        // primes with many hits per tile: the whole workgroup strides over
+        // one prime; the stride NT*p is a multiple of 32 bits, so the bit
+        // within the word stays put and only the word address moves
+        // (the next prime and its first strike are read ahead)
         const uint32_t kend = min(a.k_wg_end, np);
-        for (uint32_t k = a.k_first; k < kend; ++k) {
-            const uint32_t t0 = L.offs[k - a.k_first];
-            if (t0 == 0xFFFFFFFFu) continue;
-            const uint32_t p = a.primes[k];
-            for (uint32_t idx = t0 + tid * p; idx < nbits; idx += NT * p)
-                atomicAnd(&L.bits[idx >> 5], ~(1u << (idx & 31u)));
+        if (a.k_first < kend) {
+            uint32_t t0 = L.offs[0], p = a.primes[a.k_first];
+            for (uint32_t k = a.k_first; k < kend; ++k) {
+                const uint32_t kn = min(k + 1u, kend - 1u);
+                const uint32_t t0n = L.offs[kn - a.k_first], pn = a.primes[kn];
+                const uint32_t idx = t0 + tid * p;
+                if (t0 != 0xFFFFFFFFu && idx < nbits) {
+                    const uint32_t m = ~(1u << (idx & 31u));
+                    const uint32_t stride = (NT / 8u) * p;
+                    for (uint32_t wa = bits_a + 4u * (idx >> 5); wa < end_a; wa += stride) lds_and(wa, m);
+                }
+                t0 = t0n;
+                p = pn;
+            }
         }
-        // medium primes: one wavefront per prime, lanes stride by 64p
+        // medium primes: one wavefront per prime, lanes stride by 64p bits
         const uint32_t kbeg2 = max(a.k_wg_end, a.k_first);
-        for (uint32_t k = kbeg2 + wave; k < kmid; k += NWAVES) {
-            const uint32_t t0 = L.offs[k - a.k_first];
-            if (t0 == 0xFFFFFFFFu) continue;
-            const uint32_t p = a.primes[k];
-            for (uint32_t idx = t0 + lane * p; idx < nbits; idx += 64u * p)
-                atomicAnd(&L.bits[idx >> 5], ~(1u << (idx & 31u)));
+        if (kbeg2 + wave < kmid) {
+            uint32_t t0 = L.offs[kbeg2 + wave - a.k_first], p = a.primes[kbeg2 + wave];
+            for (uint32_t k = kbeg2 + wave; k < kmid; k += NWAVES) {
+                const uint32_t kn = min(k + NWAVES, kmid - 1u);
+                const uint32_t t0n = L.offs[kn - a.k_first], pn = a.primes[kn];
+                const uint32_t idx = t0 + lane * p;
+                if (t0 != 0xFFFFFFFFu && idx < nbits) {
+                    const uint32_t m = ~(1u << (idx & 31u));
+                    for (uint32_t wa = bits_a + 4u * (idx >> 5); wa < end_a; wa += 8u * p) lds_and(wa, m);
+                }
+                t0 = t0n;
+                p = pn;
+            }
         }
-        // large primes: one lane per prime, a few hits each
+        // large primes: one lane per prime, a few hits each; the lane loads
+        // its next prime ahead
         const uint32_t kbeg3 = max(a.k_wave_end, a.k_first);
-        for (uint32_t k = kbeg3 + tid; k < np; k += NT) {
-            const uint32_t p = a.primes[k];
-            const unsigned long long t0 = small_w0 ? first_index_f64(w0, w0d, p, a.pinv[k])
-                                                   : first_index(w0, p, a.magic[k]);
+        uint32_t k = kbeg3 + tid;
+        uint32_t pn = 0;
+        double vn = 0.0;
+        unsigned long long mn = 0;
+        if (k < np) {
+            pn = a.primes[k];
+            if (small_w0) vn = a.pinv[k]; else mn = a.magic[k];
+        }
+        for (; k < np; k += NT) {
+            const uint32_t p = pn;
+            const double pv = vn;
+            const unsigned long long mg = mn;
+            if (k + NT < np) {
+                pn = a.primes[k + NT];
+                if (small_w0) vn = a.pinv[k + NT]; else mn = a.magic[k + NT];
+            }
+            const unsigned long long t0 = small_w0 ? first_index_f64(w0, w0d, p, pv) : first_index(w0, p, mg);
             if (t0 >= nbits) continue;
             for (uint32_t idx = (uint32_t)t0; idx < nbits; idx += p)
-                atomicAnd(&L.bits[idx >> 5], ~(1u << (idx & 31u)));
+                lds_and(bits_a + 4u * (idx >> 5), ~(1u << (idx & 31u)));
         }
     }
     __syncthreads();
@@ -324,7 +405,10 @@ __device__ void process_tile(const GbTileArgs &a, unsigned long long g, const Ti
     // resolved, with p = 2^17 - 1 - 2g and the list of n it did not resolve
     // (masked in front or behind, or left to the exhaustive phase):
     //   sum of floor(n/128) dB, sum of 2^i per chunk dx0..dx3.
-    uint32_t minx = 0xFFFFFFFFu, mblk = 0;  // smallest packed word of a block's last hit
+    // largest p_min of the lane and its first block, as the smallest key
+    // (g << 16) | block over the blocks' last hits (g falls as p grows; the
+    // key 0xFFFF << 16 stands for p = 2, and ~0 for no hit)
+    uint32_t minkey = 0xFFFFFFFFu;
     uint32_t nexh = 0;                 // n left to the exhaustive phase
     uint32_t sumg = 0;
     unsigned long long sprefg = 0;
@@ -363,16 +447,15 @@ __device__ void process_tile(const GbTileArgs &a, unsigned long long g, const Ti
     };
 
     // block state: unresolved mask U, next prime index k, LDS byte address
-    // of the block's base word minus PX_BIAS (bw), packed word of the block's
-    // last hit (the last hit carries the block's largest p_min; packed words
-    // decrease as p grows)
+    // of the block's base word minus PX_BIAS (bw), g << 16 of the block's
+    // last hit (the last hit carries the block's largest p_min)
     const uint32_t bits_addr = (uint32_t)(uintptr_t)(lds_u32 *)L.bits;
-    uint32_t b = tid, k = 0, Ulo = 0, Uhi = 0, lastx = 0xFFFFFFFFu;
+    uint32_t b = tid, k = 0, Ulo = 0, Uhi = 0, lastkey = 0xFFFFFFFFu;
     uint32_t bw = bits_addr + 8u * tid + HB / 8u - PX_BIAS;
     if (b < nblk) {
         block_mask(b, Ulo, Uhi);
         if (b == 0u && has4) {
-            lastx = 0xFFFFFFFEu;      // stands for p = 2, above every real word
+            lastkey = 0xFFFF0000u;    // p = 2
             atomicAdd(&hist[0], 1ull);
             if (a.pmin) store_p<PB>(a.pmin, outb + 2u, 2u);
         }
@@ -383,30 +466,47 @@ __device__ void process_tile(const GbTileArgs &a, unsigned long long g, const Ti
             // copies of its last prime, which cannot hit an n twice
             // the group's twelve window words do not depend on the hits, so
             // they are all read before the first test
-            uint32_t xs[4], dw[4][3];
+            const uint4 xv = *reinterpret_cast<const uint4 *>(L.px + k);
+            const uint32_t xs[4] = {xv.x, xv.y, xv.z, xv.w};
+            uint32_t dw[4][3], pcs[4];
+            if constexpr (GW) {
+                // the four windows lie in the four words from the base word
+                // of the group's last (largest) prime: two reads for the group
+                const lds_u32 *wp = probe_addr(xs[3], bw);
+                const uint32_t w0 = wp[0], w1 = wp[1], w2 = wp[2], w3 = wp[3];
 #pragma unroll
-            for (uint32_t u = 0; u < 4; ++u) xs[u] = L.px[k + u];
+                for (uint32_t u = 0; u < 3; ++u) {
+                    const bool up = xs[u] >= 0x10000u;
+                    dw[u][0] = up ? w1 : w0;
+                    dw[u][1] = up ? w2 : w1;
+                    dw[u][2] = up ? w3 : w2;
+                }
+                dw[3][0] = w0;
+                dw[3][1] = w1;
+                dw[3][2] = w2;
+            } else {
 #pragma unroll
-            for (uint32_t u = 0; u < 4; ++u) {
-                const lds_u32 *wp = probe_addr(xs[u], bw);
-                dw[u][0] = wp[0];
-                dw[u][1] = wp[1];
-                dw[u][2] = wp[2];
+                for (uint32_t u = 0; u < 4; ++u) {
+                    const lds_u32 *wp = probe_addr(xs[u], bw);
+                    dw[u][0] = wp[0];
+                    dw[u][1] = wp[1];
+                    dw[u][2] = wp[2];
+                }
             }
 #pragma unroll
             for (uint32_t u = 0; u < 4; ++u) {
                 const uint32_t x = xs[u];
                 const uint32_t hlo = __builtin_amdgcn_alignbit(dw[u][1], dw[u][0], x) & Ulo;
                 const uint32_t hhi = __builtin_amdgcn_alignbit(dw[u][2], dw[u][1], x) & Uhi;
-                if (hlo | hhi) {
-                    const uint32_t pc = __popc(hlo) + __popc(hhi);
-                    atomicAdd(&L.lhist[k + u], pc);
+                pcs[u] = __popc(hlo) + __popc(hhi);
+                if ((((unsigned long long)hhi << 32) | hlo) != 0ull) {
+                    const uint32_t pc = pcs[u];
                     sumg = mad_lo16(x, pc, sumg);
                     g0 = mad_lo16(x, hlo, g0);
                     g1 = mad_hi16(x, hlo, g1);
                     g2 = mad_lo16(x, hhi, g2);
                     g3 = mad_hi16(x, hhi, g3);
-                    lastx = x;
+                    lastkey = x << 16;
                     if constexpr (PB != 0) {
                         if (a.pmin) {
                             const uint32_t p = 131071u - 2u * (x & 0xFFFFu);
@@ -422,23 +522,28 @@ __device__ void process_tile(const GbTileArgs &a, unsigned long long g, const Ti
                     Uhi ^= hhi;
                 }
             }
+            // the group's hit counts, two primes per 64-bit LDS atomic
+            unsigned long long *lh2 = reinterpret_cast<unsigned long long *>(L.lhist + k);
+            if (pcs[0] | pcs[1]) atomicAdd(&lh2[0], (unsigned long long)pcs[0] | ((unsigned long long)pcs[1] << 32));
+            if (pcs[2] | pcs[3]) atomicAdd(&lh2[1], (unsigned long long)pcs[2] | ((unsigned long long)pcs[3] << 32));
             k += 4;
         }
         if ((Ulo | Uhi) == 0u || k >= nps) {
             sprefg += sumg;
-            if (lastx < minx) {
-                minx = lastx;
-                mblk = b;
-            }
+            minkey = min(minkey, lastkey | b);
             if (Ulo | Uhi) push_unresolved(b, Ulo, Uhi);
             b += NT;
             bw += 8u * NT;
             k = 0;
             Ulo = ~0u;
             Uhi = ~0u;
-            if (ragged && b + 1u == nblk) {
-                Ulo = last_lo;
-                Uhi = last_hi;
+            // the tile's last block may be partial: a wave-level test keeps
+            // the masking off the common path
+            if (ragged && __ballot(b + 1u == nblk) != 0ull) {
+                if (b + 1u == nblk) {
+                    Ulo = last_lo;
+                    Uhi = last_hi;
+                }
             }
         }
     }
@@ -471,7 +576,8 @@ __device__ void process_tile(const GbTileArgs &a, unsigned long long g, const Ti
                     5u * (131071u * (full - dx2) - 2u * g2) + 7u * (131071u * (full - dx3) - 2u * g3);
     if (has4 && tid == 0u) zsum += 8u;   // n = 4: p = 2 at i = 2 of chunk 0
     const unsigned long long cs = ysum + ((unsigned long long)zsum << 32);
-    const uint32_t maxp = minx == 0xFFFFFFFFu ? 0u : (minx == 0xFFFFFFFEu ? 2u : 131071u - 2u * (minx & 0xFFFFu));
+    const uint32_t gmax = minkey >> 16, mblk = minkey & 0xFFFFu;
+    const uint32_t maxp = minkey == 0xFFFFFFFFu ? 0u : (gmax == 0xFFFFu ? 2u : 131071u - 2u * gmax);
     const unsigned long long key = ((unsigned long long)maxp << 32) | (0xFFFFFFFFu - mblk);
     // LDS atomics instead of shuffles: nothing per lane stays live for them
     // across the tiles of a persistent workgroup
@@ -534,7 +640,7 @@ __device__ void process_tile(const GbTileArgs &a, unsigned long long g, const Ti
     __syncthreads();
 }
 
-template <int NT, int PB, bool PERS, bool SIEVE_ONLY>
+template <int NT, int PB, bool PERS, bool SIEVE_ONLY, bool GW>
 __global__ __launch_bounds__(NT) void k_tile(GbTileArgs a)
 {
     extern __shared__ uint32_t smem[];
@@ -545,10 +651,10 @@ __global__ __launch_bounds__(NT) void k_tile(GbTileArgs a)
             __syncthreads();
             const unsigned long long g = *L.tile;
             if (g >= a.ntiles) break;
-            process_tile<NT, PB, SIEVE_ONLY>(a, g, L);
+            process_tile<NT, PB, SIEVE_ONLY, GW>(a, g, L);
         }
     } else {
-        process_tile<NT, PB, SIEVE_ONLY>(a, a.tile0 + blockIdx.x, L);
+        process_tile<NT, PB, SIEVE_ONLY, GW>(a, a.tile0 + blockIdx.x, L);
     }
 }
 
@@ -760,53 +866,72 @@ __global__ void k_finish_queries(const GbExh *list, uint64_t k, unsigned long lo
     if (i < k) p_out[i] = list[i].p;
 }
 
-template <int NT, int PB, bool PERS, bool SO>
+template <int NT, int PB, bool PERS, bool SO, bool GW>
 hipError_t launch_one(const GbTileArgs &a, uint32_t grid, size_t lds, hipStream_t st)
 {
-    hipLaunchKernelGGL((k_tile<NT, PB, PERS, SO>), dim3(grid), dim3(NT), lds, st, a);
+    hipLaunchKernelGGL((k_tile<NT, PB, PERS, SO, GW>), dim3(grid), dim3(NT), lds, st, a);
     return hipGetLastError();
 }
 
-template <int NT, int PB, bool PERS, bool SO>
+template <int NT, int PB, bool PERS, bool SO, bool GW>
 hipError_t allow_lds(size_t lds)
 {
-    return hipFuncSetAttribute(reinterpret_cast<const void *>(&k_tile<NT, PB, PERS, SO>),
+    return hipFuncSetAttribute(reinterpret_cast<const void *>(&k_tile<NT, PB, PERS, SO, GW>),
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+}
+
+template <int NT, bool GW>
+hipError_t allow_lds_search(size_t lds)
+{
+    hipError_t e = hipSuccess, r;
+    if ((r = allow_lds<NT, 0, false, false, GW>(lds)) != hipSuccess) e = r;
+    if ((r = allow_lds<NT, 16, false, false, GW>(lds)) != hipSuccess) e = r;
+    if ((r = allow_lds<NT, 32, false, false, GW>(lds)) != hipSuccess) e = r;
+    if ((r = allow_lds<NT, 0, true, false, GW>(lds)) != hipSuccess) e = r;
+    if ((r = allow_lds<NT, 16, true, false, GW>(lds)) != hipSuccess) e = r;
+    if ((r = allow_lds<NT, 32, true, false, GW>(lds)) != hipSuccess) e = r;
+    return e;
 }
 
 template <int NT>
 hipError_t allow_lds_nt(size_t lds)
 {
     hipError_t e = hipSuccess, r;
-    if ((r = allow_lds<NT, 0, false, true>(lds)) != hipSuccess) e = r;
-    if ((r = allow_lds<NT, 0, false, false>(lds)) != hipSuccess) e = r;
-    if ((r = allow_lds<NT, 16, false, false>(lds)) != hipSuccess) e = r;
-    if ((r = allow_lds<NT, 32, false, false>(lds)) != hipSuccess) e = r;
-    if ((r = allow_lds<NT, 0, true, false>(lds)) != hipSuccess) e = r;
-    if ((r = allow_lds<NT, 16, true, false>(lds)) != hipSuccess) e = r;
-    if ((r = allow_lds<NT, 32, true, false>(lds)) != hipSuccess) e = r;
+    if ((r = allow_lds<NT, 0, false, true, false>(lds)) != hipSuccess) e = r;
+    if ((r = allow_lds_search<NT, false>(lds)) != hipSuccess) e = r;
+    if ((r = allow_lds_search<NT, true>(lds)) != hipSuccess) e = r;
     return e;
 }
 
-template <int NT>
-hipError_t launch_nt(const GbTileArgs &a, uint32_t grid, size_t lds, int pb, bool pers, bool so, hipStream_t st)
+template <int NT, bool GW>
+hipError_t launch_search(const GbTileArgs &a, uint32_t grid, size_t lds, int pb, bool pers, hipStream_t st)
 {
-    if (so) return launch_one<NT, 0, false, true>(a, grid, lds, st);
     if (pers) {
-        if (pb == 16) return launch_one<NT, 16, true, false>(a, grid, lds, st);
-        if (pb == 32) return launch_one<NT, 32, true, false>(a, grid, lds, st);
-        return launch_one<NT, 0, true, false>(a, grid, lds, st);
+        if (pb == 16) return launch_one<NT, 16, true, false, GW>(a, grid, lds, st);
+        if (pb == 32) return launch_one<NT, 32, true, false, GW>(a, grid, lds, st);
+        return launch_one<NT, 0, true, false, GW>(a, grid, lds, st);
     }
-    if (pb == 16) return launch_one<NT, 16, false, false>(a, grid, lds, st);
-    if (pb == 32) return launch_one<NT, 32, false, false>(a, grid, lds, st);
-    return launch_one<NT, 0, false, false>(a, grid, lds, st);
+    if (pb == 16) return launch_one<NT, 16, false, false, GW>(a, grid, lds, st);
+    if (pb == 32) return launch_one<NT, 32, false, false, GW>(a, grid, lds, st);
+    return launch_one<NT, 0, false, false, GW>(a, grid, lds, st);
+}
+
+template <int NT>
+hipError_t launch_nt(const GbTileArgs &a, uint32_t grid, size_t lds, int pb, bool pers, bool so, bool gw,
+                     hipStream_t st)
+{
+    if (so) return launch_one<NT, 0, false, true, false>(a, grid, lds, st);
+    return gw ? launch_search<NT, true>(a, grid, lds, pb, pers, st) : launch_search<NT, false>(a, grid, lds, pb, pers, st);
 }
 
 }  // namespace
 
 size_t gb_tile_lds_bytes(uint32_t tile_n, uint32_t halo_bits, uint32_t np_search, uint32_t n_off)
 {
-    size_t words = (tile_n + halo_bits) / 32 + (np_search + 4) + np_search;
+    size_t words = ((tile_n + halo_bits) / 32 + 3) & ~(size_t)3;
+    words += np_search + 4;
+    words = (words + 1) & ~(size_t)1;
+    words += np_search + 4;
     words = (words + 1) & ~(size_t)1;
     words += n_off;                                       // first strikes
     words = (words + 1) & ~(size_t)1;
@@ -826,10 +951,14 @@ hipError_t gb_prepare_tiles(uint32_t threads, size_t lds_bytes)
     }
 }
 
-hipError_t gb_tile_occupancy(uint32_t threads, size_t lds_bytes, int *blocks_per_cu)
+hipError_t gb_tile_occupancy(uint32_t threads, size_t lds_bytes, bool group_window, int *blocks_per_cu)
 {
-#define GB_OCC(NT) \
-    hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_tile<NT, 0, true, false>, NT, lds_bytes)
+#define GB_OCC(NT)                                                                                        \
+    (group_window                                                                                         \
+         ? hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_tile<NT, 0, true, false, true>, NT,  \
+                                                        lds_bytes)                                        \
+         : hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_tile<NT, 0, true, false, false>, NT, \
+                                                        lds_bytes))
     switch (threads) {
     case 256: return GB_OCC(256);
     case 512: return GB_OCC(512);
@@ -840,13 +969,13 @@ hipError_t gb_tile_occupancy(uint32_t threads, size_t lds_bytes, int *blocks_per
 }
 
 hipError_t gb_launch_tiles(const GbTileArgs &a, uint32_t grid, uint32_t threads, size_t lds_bytes, int pmin_bits,
-                           bool persistent, bool sieve_only, hipStream_t st)
+                           bool persistent, bool sieve_only, bool group_window, hipStream_t st)
 {
     if (grid == 0) return hipSuccess;
     switch (threads) {
-    case 256: return launch_nt<256>(a, grid, lds_bytes, pmin_bits, persistent, sieve_only, st);
-    case 512: return launch_nt<512>(a, grid, lds_bytes, pmin_bits, persistent, sieve_only, st);
-    case 1024: return launch_nt<1024>(a, grid, lds_bytes, pmin_bits, persistent, sieve_only, st);
+    case 256: return launch_nt<256>(a, grid, lds_bytes, pmin_bits, persistent, sieve_only, group_window, st);
+    case 512: return launch_nt<512>(a, grid, lds_bytes, pmin_bits, persistent, sieve_only, group_window, st);
+    case 1024: return launch_nt<1024>(a, grid, lds_bytes, pmin_bits, persistent, sieve_only, group_window, st);
     default: return hipErrorInvalidValue;
     }
 }

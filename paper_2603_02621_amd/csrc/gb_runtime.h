@@ -135,6 +135,7 @@ struct gb_ctx {
     uint32_t tile_n = 0, threads = 0;
     uint32_t k_wg_end = 0, k_wave_end = 0;
     size_t lds = 0;
+    bool group_window = false;       // search form: one window read per group of four probes
     int occupancy = 1;
     gbrt::Workspace ws;              // scratch of the synchronous calls
     std::string err;

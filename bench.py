@@ -38,7 +38,8 @@ ALU_PEAK_OPS = 256 * 64 * 2.4e9
 # HBM bytes per launch of the tile kernel on this workload, from rocprofv3
 # FETCH_SIZE and WRITE_SIZE scaled by a 1 GiB copy's readings (factors 2.000
 # and 1.000), valid only for the kernel source they were taken on.
-TRAFFIC = {"kernel_sha256_prefix": "522681225de16f4d", "bytes_per_launch": 8.15e6 + 122.8e6}
+TRAFFIC = {"kernel_sha256_prefix": "b315bc4eb38c4157", "tile_log2": 20, "wg_threads": 1024,
+           "bytes_per_launch": 8.174e6 + 64.766e6}
 
 
 def _load_tuned():
@@ -167,7 +168,8 @@ def main():
     import hashlib
     src = os.path.join(ROOT, "paper_2603_02621_amd", "csrc", "gb_kernels.hip")
     sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
-    same = sha == TRAFFIC["kernel_sha256_prefix"] and params.get("tile_log2") == 19
+    same = (sha == TRAFFIC["kernel_sha256_prefix"] and p["tile_log2"] == TRAFFIC["tile_log2"]
+            and p["wg_threads"] == TRAFFIC["wg_threads"])
     roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": ALU_PEAK_OPS / 1e12,
             "unit": "Tops/s (int32 lane ops)", "frac": achieved / ALU_PEAK_OPS,
             "traffic": TRAFFIC["bytes_per_launch"] if same else None,

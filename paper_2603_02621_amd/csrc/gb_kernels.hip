@@ -143,6 +143,7 @@ struct TileLds {
     uint32_t *offs;           // first bit index (or ~0) of each small/medium sieving prime
     unsigned long long *red;  // 4: checksum, n_exhaustive, max key, OR words
     unsigned long long *tile; // persistent mode: the tile just taken
+    uint32_t *next;           // next block of the tile to hand out
 };
 
 __device__ __forceinline__ TileLds carve(uint32_t *smem, const GbTileArgs &a)
@@ -165,6 +166,8 @@ __device__ __forceinline__ TileLds carve(uint32_t *smem, const GbTileArgs &a)
     o += 2 * 4;
     o = (o + 1) & ~1u;
     L.tile = reinterpret_cast<unsigned long long *>(smem + o);
+    o += 2;
+    L.next = smem + o;
     return L;
 }
 
@@ -218,6 +221,7 @@ __device__ void process_tile(const GbTileArgs &a, unsigned long long g, const Ti
             L.lhist[i] = 0;
         }
         if (tid < 4) L.red[tid] = 0ull;   // tile sums, max key, OR words
+        if (tid == 0) *L.next = NT;       // blocks 0..NT-1 go to the threads in order
     }
     // ---- first strike of every small and medium sieving prime, once -------
     // each lane loads its next prime ahead
@@ -397,25 +401,23 @@ __device__ void process_tile(const GbTileArgs &a, unsigned long long g, const Ti
 
     // Lane summaries.  A hit of the prime p = 2^17 - 1 - 2g on the mask h of
     // n is accumulated through g (the low half of the prime's packed word):
-    //   sumg = sum of g * popcount(h), and sprefg, the sum of sumg taken at
-    //     each block's end, so that sum_i i G_i = m * sumg - sprefg after m
-    //     blocks, G_i being block i's part of sumg;
+    //   sumg = sum of g * popcount(h), and accbg, the sum over the lane's
+    //     blocks b of b times block b's part of sumg;
     //   g0..g3 = sum of g * (16-bit chunk c of h), mod 2^32.
     // At the tile's end these turn into the checksum of the n the search
-    // resolved, with p = 2^17 - 1 - 2g and the list of n it did not resolve
-    // (masked in front or behind, or left to the exhaustive phase):
+    // resolved, with p = 2^17 - 1 - 2g, together with the n it did not
+    // resolve (masked in front or behind, or left to the exhaustive phase):
     //   sum of floor(n/128) dB, sum of 2^i per chunk dx0..dx3.
     // largest p_min of the lane and its first block, as the smallest key
     // (g << 16) | block over the blocks' last hits (g falls as p grows; the
     // key 0xFFFF << 16 stands for p = 2, and ~0 for no hit)
     uint32_t minkey = 0xFFFFFFFFu;
     uint32_t nexh = 0;                 // n left to the exhaustive phase
-    uint32_t sumg = 0;
-    unsigned long long sprefg = 0;
+    uint32_t sumg = 0, sumg0 = 0;      // sumg0: sumg when the current block began
+    unsigned long long accbg = 0;
     uint32_t g0 = 0, g1 = 0, g2 = 0, g3 = 0;
     uint32_t dx0 = 0, dx1 = 0, dx2 = 0, dx3 = 0;
     unsigned long long dB = 0;
-    const unsigned long long B0 = (N0 >> 7) + tid;   // floor(n/128) of the lane's first block
     auto deficit = [&](uint32_t blk, uint32_t mlo, uint32_t mhi) {
         const uint32_t c = __popc(mlo) + __popc(mhi);
         dB += ((N0 >> 7) + blk) * (unsigned long long)c;
@@ -528,54 +530,68 @@ __device__ void process_tile(const GbTileArgs &a, unsigned long long g, const Ti
             if (pcs[2] | pcs[3]) atomicAdd(&lh2[1], (unsigned long long)pcs[2] | ((unsigned long long)pcs[3] << 32));
             k += 4;
         }
-        if ((Ulo | Uhi) == 0u || k >= nps) {
-            sprefg += sumg;
-            minkey = min(minkey, lastkey | b);
-            if (Ulo | Uhi) push_unresolved(b, Ulo, Uhi);
-            b += NT;
-            bw += 8u * NT;
-            k = 0;
-            Ulo = ~0u;
-            Uhi = ~0u;
+        // Blocks are handed out by a workgroup counter as lanes finish, so
+        // that no lane idles while others still have long blocks: one LDS
+        // atomic per wave for all its lanes that finished in this round.
+        const bool done = (Ulo | Uhi) == 0u || k >= nps;
+        const unsigned long long dm = __ballot(done);
+        if (dm != 0ull) {
+            const uint32_t leader = (uint32_t)__builtin_ctzll(dm);
+            uint32_t nb = 0;
+            if (lane == leader) nb = atomicAdd(L.next, (uint32_t)__popcll(dm));
+            nb = __builtin_amdgcn_readlane(nb, leader);
+            if (done) {
+                accbg += (unsigned long long)b * (sumg - sumg0);
+                sumg0 = sumg;
+                minkey = min(minkey, lastkey | b);
+                if (Ulo | Uhi) push_unresolved(b, Ulo, Uhi);
+                b = nb + __builtin_amdgcn_mbcnt_hi((uint32_t)(dm >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)dm, 0u));
+                bw = bits_addr + 8u * b + HB / 8u - PX_BIAS;
+                k = 0;
+                Ulo = ~0u;
+                Uhi = ~0u;
             // the tile's last block may be partial: a wave-level test keeps
             // the masking off the common path
-            if (ragged && __ballot(b + 1u == nblk) != 0ull) {
-                if (b + 1u == nblk) {
-                    Ulo = last_lo;
-                    Uhi = last_hi;
+                if (ragged && __ballot(b + 1u == nblk) != 0ull) {
+                    if (b + 1u == nblk) {
+                        Ulo = last_lo;
+                        Uhi = last_hi;
+                    }
                 }
             }
         }
     }
 
     // ---- tile summary ------------------------------------------------------
-    const uint32_t m = tid < nblk ? (nblk - 1u - tid) / NT + 1u : 0u;
-    {
-        // masked n of the tile's first and last blocks
+    // Lane part of the checksum of the resolved n, with p = 2^17 - 1 - 2g:
+    //   sum of p floor(n/128)   = 131071 (sum of floor(n/128) over resolved n)
+    //                             - 2 (sum over hits of floor(n/128) g popcount)
+    //   sum of p (2c+1) 2^i     = sum over chunks c of (2c+1) (131071 (sum of
+    //                             2^i over resolved n of chunk c) - 2 g_c)
+    // where the sums over resolved n are the sums over the whole tile minus
+    // the deficits; thread 0 adds the whole-tile terms and the masked n.
+    if (tid == 0u) {
         uint32_t lo, hi;
-        if (tid == 0u) {
-            block_mask(0u, lo, hi);
-            deficit(0u, ~lo, ~hi);
-        }
-        if (nblk > 1u && (nblk - 1u) % NT == tid) {
+        block_mask(0u, lo, hi);
+        deficit(0u, ~lo, ~hi);
+        if (nblk > 1u) {
             block_mask(nblk - 1u, lo, hi);
             deficit(nblk - 1u, ~lo, ~hi);
         }
     }
-    const unsigned long long mm = m;
-    // sum of floor(n/128) over the lane's n, then over the n its search resolved
-    const unsigned long long sumB = mm * B0 + (unsigned long long)NT * (mm * (mm - 1ull) / 2ull);
-    const unsigned long long sumBR = 64ull * sumB - dB;
-    // sum over hits of floor(n/128) * g * popcount
-    const unsigned long long sumBG = B0 * sumg + (unsigned long long)NT * (mm * sumg - sprefg);
-    // sum of p * floor(n/128), p = 2^17 - 1 - 2g
-    const unsigned long long ysum = 131071ull * sumBR - 2ull * sumBG;
-    // sum of p * (2c+1) 2^i mod 2^32, from the chunk sums of the resolved n
-    const uint32_t full = m * 0xFFFFu;
-    uint32_t zsum = (131071u * (full - dx0) - 2u * g0) + 3u * (131071u * (full - dx1) - 2u * g1) +
-                    5u * (131071u * (full - dx2) - 2u * g2) + 7u * (131071u * (full - dx3) - 2u * g3);
-    if (has4 && tid == 0u) zsum += 8u;   // n = 4: p = 2 at i = 2 of chunk 0
-    const unsigned long long cs = ysum + ((unsigned long long)zsum << 32);
+    const unsigned long long ysum = 0ull - 131071ull * dB - 2ull * ((N0 >> 7) * sumg + accbg);
+    uint32_t zsum = (0u - 131071u * dx0 - 2u * g0) + 3u * (0u - 131071u * dx1 - 2u * g1) +
+                    5u * (0u - 131071u * dx2 - 2u * g2) + 7u * (0u - 131071u * dx3 - 2u * g3);
+    unsigned long long cs = ysum;
+    if (tid == 0u) {
+        // every block's floor(n/128) for its 64 n, and every chunk's 2^i sum
+        const unsigned long long nb = nblk;
+        const unsigned long long sum_b = nb * (N0 >> 7) + nb * (nb - 1ull) / 2ull;
+        cs += 131071ull * 64ull * sum_b;
+        zsum += 16u * 131071u * (nblk * 0xFFFFu);
+        if (has4) zsum += 8u;   // n = 4: p = 2 at i = 2 of chunk 0
+    }
+    cs += (unsigned long long)zsum << 32;
     const uint32_t gmax = minkey >> 16, mblk = minkey & 0xFFFFu;
     const uint32_t maxp = minkey == 0xFFFFFFFFu ? 0u : (gmax == 0xFFFFu ? 2u : 131071u - 2u * gmax);
     const unsigned long long key = ((unsigned long long)maxp << 32) | (0xFFFFFFFFu - mblk);
@@ -938,6 +954,7 @@ size_t gb_tile_lds_bytes(uint32_t tile_n, uint32_t halo_bits, uint32_t np_search
     words += 2 * 4;                                       // tile reductions
     words = (words + 1) & ~(size_t)1;
     words += 2;                                           // the persistent tile index
+    words += 2;                                           // the block counter (and padding)
     return words * 4;
 }
 

@@ -323,8 +323,16 @@ gb_status setup_geometry(gb_ctx *c)
     c->halo_bits = std::max<uint32_t>(64, (need + 63) / 64 * 64);
     c->k_first = count_le(c->h_primes, p.wheel_max);
     const uint32_t nbits = c->tile_n + c->halo_bits;
-    c->k_wg_end = std::max(c->k_first, count_le(c->h_primes, nbits / c->threads));
-    c->k_wave_end = std::max(c->k_wg_end, count_le(c->h_primes, nbits / 64));
+    // Marking classes by hits per tile, H = nbits/p.  A class pays a fixed
+    // cost per prime (first strike, loop set-up) in every thread it uses:
+    // - whole workgroup for p < nbits/(32 threads): H/threads >= 32 strides
+    //   per thread, the only primes that would unbalance the waves;
+    // - one wave per prime while H >= 256: 64 lanes x set-up plus 2 VALU
+    //   per clear beats one lane's 6 VALU per clear (measured flat between
+    //   H >= 96 and H >= 384, and for 4 to 64 strides per thread);
+    // - one lane per prime above.
+    c->k_wg_end = std::max(c->k_first, count_le(c->h_primes, nbits / (32 * c->threads)));
+    c->k_wave_end = std::max(c->k_wg_end, count_le(c->h_primes, nbits / 256));
     c->lds = gb_tile_lds_bytes(c->tile_n, c->halo_bits, c->np_search, c->k_wave_end - c->k_first);
     if (c->lds > 160 * 1024)
         return fail(c, GB_EINVAL, "tile does not fit in LDS (" + std::to_string(c->lds) +

@@ -174,7 +174,11 @@ __device__ __forceinline__ TileLds carve(uint32_t *smem, const GbTileArgs &a)
 template <int NT, int PB, bool SIEVE_ONLY, bool GW>
 __device__ void process_tile(const GbTileArgs &a, unsigned long long g, const TileLds &L)
 {
-    const uint32_t tid = threadIdx.x;
+    // made opaque per tile: otherwise the compiler hoists values derived
+    // from the thread index out of a persistent workgroup's tile loop and
+    // keeps them live in registers across it (87 instead of 49 VGPRs)
+    uint32_t tid = threadIdx.x;
+    asm volatile("" : "+v"(tid));
     const uint32_t lane = tid & 63u, wave = tid >> 6;
     constexpr uint32_t NWAVES = NT / 64;
 
@@ -534,11 +538,18 @@ __device__ void process_tile(const GbTileArgs &a, unsigned long long g, const Ti
         // that no lane idles while others still have long blocks: one LDS
         // atomic per wave for all its lanes that finished in this round.
         const bool done = (Ulo | Uhi) == 0u || k >= nps;
-        const unsigned long long dm = __ballot(done);
+        const unsigned long long dm = __builtin_amdgcn_ballot_w64(done);
         if (dm != 0ull) {
             const uint32_t leader = (uint32_t)__builtin_ctzll(dm);
             uint32_t nb = 0;
-            if (lane == leader) nb = atomicAdd(L.next, (uint32_t)__popcll(dm));
+            if (lane == leader) {
+                // the counter's address is made opaque so that the compiler
+                // does not wrap this one-lane atomic in its wave aggregation
+                uint32_t na = (uint32_t)(uintptr_t)(lds_u32 *)L.next;
+                asm volatile("" : "+v"(na));
+                nb = __hip_atomic_fetch_add(reinterpret_cast<lds_u32 *>(static_cast<uintptr_t>(na)),
+                                            (uint32_t)__popcll(dm), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            }
             nb = __builtin_amdgcn_readlane(nb, leader);
             if (done) {
                 accbg += (unsigned long long)b * (sumg - sumg0);
@@ -552,7 +563,7 @@ __device__ void process_tile(const GbTileArgs &a, unsigned long long g, const Ti
                 Uhi = ~0u;
             // the tile's last block may be partial: a wave-level test keeps
             // the masking off the common path
-                if (ragged && __ballot(b + 1u == nblk) != 0ull) {
+                if (ragged && __builtin_amdgcn_ballot_w64(b + 1u == nblk) != 0ull) {
                     if (b + 1u == nblk) {
                         Ulo = last_lo;
                         Uhi = last_hi;

@@ -108,8 +108,8 @@ typedef struct gb_result {
     uint64_t argmax_n;        /* smallest n attaining max_p */
     uint64_t checksum;        /* sum of w(n) * p_min(n) modulo 2^64 over the
                                  n with a partition, where
-                                 w(n) = floor(n/128) + 2^32 (2c+1) 2^i and
-                                 (n/2) mod 64 = 16c + i, 0 <= i < 16.  The
+                                 w(n) = 2^33 floor(n/128) + (2c+1) 2^i and
+                                 (n/2) mod 64 = 32c + i, 0 <= i < 32.  The
                                  paper defines no checksum; sums over
                                  disjoint sets of n add up. */
     uint64_t n_exhaustive;    /* n that no odd prime p <= P_max resolved */

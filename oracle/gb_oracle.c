@@ -21,13 +21,13 @@
  *   count          number of even n examined
  *   max_p/argmax_n largest p_min and the smallest n attaining it
  *   checksum       sum over n of w(n) * p_min(n), modulo 2^64, with the
- *                  weight w(n) = floor(n/128) + 2^32 * (2c+1) * 2^i, where
- *                  j = (n/2) mod 64, c = floor(j/16), i = j mod 16
- *                  (orc_checksum_weight).  A single wrong p_min changes
- *                  it whenever w(n) has at most 48 factors of 2 (the
- *                  difference of two p below 2^16 has at most 15); two n
- *                  within 256 of each other exchanging p values that differ
- *                  by less than 2^15 change it too.
+ *                  weight w(n) = 2^33 * floor(n/128) + (2c+1) * 2^i, where
+ *                  j = (n/2) mod 64, c = floor(j/32), i = j mod 32
+ *                  (orc_checksum_weight).  w(n) has exactly i <= 31
+ *                  factors of 2 and the difference of two p below 2^16 at
+ *                  most 15, so any single wrong p_min changes it; so does
+ *                  any exchange of p between two n within 256 of each other
+ *                  (their weights differ by at most 33 factors of 2).
  *   hist[i]        number of n whose p_min is the i-th prime (2 -> 0,
  *                  3 -> 1, ...) for p_min < 2^16; bin 6542 counts larger p
  *   n_exhaustive   number of n that no prime p <= P_max resolves (the n a
@@ -223,9 +223,8 @@ static uint32_t hist_bin(uint64_t p, const uint32_t *small, uint64_t nsmall)
 uint64_t orc_checksum_weight(uint64_t n)
 {
     uint64_t j = (n / 2) % 64;
-    uint64_t c = j / 16, i = j % 16;
-    uint64_t chunk_weight = (2 * c + 1) << i;
-    return n / 128 + (chunk_weight << 32);
+    uint64_t c = j / 32, i = j % 32;
+    return ((n / 128) << 33) + ((2 * c + 1) << i);
 }
 
 static void record(orc_summary *s, uint64_t *hist, const uint32_t *small,

@@ -17,7 +17,7 @@
 // n that no p <= P_max resolves go to a device list for k_mr, the
 // exhaustive phase (the paper's Phase 2; on the GPU here).
 // A hit (prime p, mask h of the n it settles) costs a popcount for the
-// per-prime histogram and five multiply-adds for the checksum; a block only
+// per-prime histogram and three multiply-adds for the checksum; a block only
 // remembers the p of its last hit, which is its largest p_min, and the tile
 // recovers the smallest n with the tile's largest p_min at its end.
 //
@@ -73,19 +73,11 @@ __device__ __forceinline__ unsigned long long first_index_f64(long long w0, doub
     return (d & 1u) ? ((unsigned long long)d + p) >> 1 : (unsigned long long)(d >> 1);
 }
 
-// p * (bits 15..0 of x) + acc and p * (bits 31..16 of x) + acc, p < 2^16, in
-// one v_mad_u32_u16 each (op_sel picks the half of x).
+// p * (bits 15..0 of x) + acc, p < 2^16, in one v_mad_u32_u16.
 __device__ __forceinline__ uint32_t mad_lo16(uint32_t p, uint32_t x, uint32_t acc)
 {
     uint32_t d;
     asm("v_mad_u32_u16 %0, %1, %2, %3" : "=v"(d) : "v"(p), "v"(x), "v"(acc));
-    return d;
-}
-
-__device__ __forceinline__ uint32_t mad_hi16(uint32_t p, uint32_t x, uint32_t acc)
-{
-    uint32_t d;
-    asm("v_mad_u32_u16 %0, %1, %2, %3 op_sel:[0,1,0,0]" : "=v"(d) : "v"(p), "v"(x), "v"(acc));
     return d;
 }
 
@@ -112,14 +104,14 @@ __device__ __forceinline__ void lds_and(uint32_t addr, uint32_t m)
 // of the probe's first word below the block's base word, biased to be >= 0.
 constexpr uint32_t PX_BIAS = 4096;   // 4 ceil(h/32) <= 4096 for h <= 32768
 
-// Checksum weight of an even n: floor(n/128) + 2^32 (2c+1) 2^i, where
-// (n/2) mod 64 = 16c + i.  The checksum is the sum of weight * p_min mod
+// Checksum weight of an even n: 2^33 floor(n/128) + (2c+1) 2^i, where
+// (n/2) mod 64 = 32c + i.  The checksum is the sum of weight * p_min mod
 // 2^64; it is not in the paper, and this form is the one the bit-sliced
-// search can accumulate with a few multiply-adds per hit.
+// search can accumulate with two 32x32 -> 64-bit multiply-adds per hit.
 __device__ __forceinline__ unsigned long long checksum_weight(unsigned long long n)
 {
     const uint32_t j = (uint32_t)(n >> 1) & 63u;
-    return (n >> 7) + ((unsigned long long)((2u * (j >> 4) + 1u) << (j & 15u)) << 32);
+    return ((n >> 7) << 33) + ((unsigned long long)(2u * (j >> 5) + 1u) << (j & 31u));
 }
 
 __device__ __forceinline__ bool is_wheel_prime(long long v, uint32_t wmax)
@@ -139,6 +131,7 @@ __device__ __forceinline__ void store_p(void *out, unsigned long long idx, uint3
 struct TileLds {
     uint32_t *bits;           // (T + HB)/32 words: the tile's window, 1 = prime
     uint32_t *px;             // packed words of the odd primes p <= P_max, padded by 4
+    uint32_t *gl;             // g = 2^16 - (p+1)/2 of the same primes, padded by 4
     uint32_t *lhist;          // per-prime hit counts of this tile, padded by 4
     uint32_t *offs;           // first bit index (or ~0) of each small/medium sieving prime
     unsigned long long *red;  // 4: checksum, n_exhaustive, max key, OR words
@@ -154,6 +147,9 @@ __device__ __forceinline__ TileLds carve(uint32_t *smem, const GbTileArgs &a)
     o += (a.tile_n + a.halo_bits) / 32;
     o = (o + 3) & ~3u;   // 16-byte aligned: a group reads its four words at once
     L.px = smem + o;
+    o += a.np_search + 4;
+    o = (o + 3) & ~3u;
+    L.gl = smem + o;
     o += a.np_search + 4;
     o = (o + 1) & ~1u;   // counters are added in pairs (64-bit LDS atomics)
     L.lhist = smem + o;
@@ -222,6 +218,7 @@ __device__ void process_tile(const GbTileArgs &a, unsigned long long g, const Ti
                 hi = ((((p3 + 1u) >> 1) + 31u) >> 5) - ((h + 31u) >> 5);
             }
             L.px[i] = (hi << 16) | (65536u - h);
+            L.gl[i] = 65536u - h;
             L.lhist[i] = 0;
         }
         if (tid < 4) L.red[tid] = 0ull;   // tile sums, max key, OR words
@@ -407,11 +404,11 @@ __device__ void process_tile(const GbTileArgs &a, unsigned long long g, const Ti
     // n is accumulated through g (the low half of the prime's packed word):
     //   sumg = sum of g * popcount(h), and accbg, the sum over the lane's
     //     blocks b of b times block b's part of sumg;
-    //   g0..g3 = sum of g * (16-bit chunk c of h), mod 2^32.
+    //   s0, s1 = sum of g * (32-bit half c of h), exact in 64 bits.
     // At the tile's end these turn into the checksum of the n the search
     // resolved, with p = 2^17 - 1 - 2g, together with the n it did not
     // resolve (masked in front or behind, or left to the exhaustive phase):
-    //   sum of floor(n/128) dB, sum of 2^i per chunk dx0..dx3.
+    //   sum of floor(n/128) dB, sum of 2^i per half dx0, dx1.
     // largest p_min of the lane and its first block, as the smallest key
     // (g << 16) | block over the blocks' last hits (g falls as p grows; the
     // key 0xFFFF << 16 stands for p = 2, and ~0 for no hit)
@@ -419,16 +416,14 @@ __device__ void process_tile(const GbTileArgs &a, unsigned long long g, const Ti
     uint32_t nexh = 0;                 // n left to the exhaustive phase
     uint32_t sumg = 0, sumg0 = 0;      // sumg0: sumg when the current block began
     unsigned long long accbg = 0;
-    uint32_t g0 = 0, g1 = 0, g2 = 0, g3 = 0;
-    uint32_t dx0 = 0, dx1 = 0, dx2 = 0, dx3 = 0;
+    unsigned long long s0 = 0, s1 = 0;
+    unsigned long long dx0 = 0, dx1 = 0;
     unsigned long long dB = 0;
     auto deficit = [&](uint32_t blk, uint32_t mlo, uint32_t mhi) {
         const uint32_t c = __popc(mlo) + __popc(mhi);
         dB += ((N0 >> 7) + blk) * (unsigned long long)c;
-        dx0 += mlo & 0xFFFFu;
-        dx1 += mlo >> 16;
-        dx2 += mhi & 0xFFFFu;
-        dx3 += mhi >> 16;
+        dx0 += mlo;
+        dx1 += mhi;
     };
 
     // n no fast-path prime resolves go to the exhaustive phase's list
@@ -474,6 +469,11 @@ __device__ void process_tile(const GbTileArgs &a, unsigned long long g, const Ti
             // they are all read before the first test
             const uint4 xv = *reinterpret_cast<const uint4 *>(L.px + k);
             const uint32_t xs[4] = {xv.x, xv.y, xv.z, xv.w};
+            uint4 gv = *reinterpret_cast<const uint4 *>(L.gl + k);
+            // one 16-byte read up front (otherwise the compiler sinks single
+            // reads into the hit branches)
+            asm volatile("" : "+v"(gv.x), "+v"(gv.y), "+v"(gv.z), "+v"(gv.w));
+            const uint32_t gs[4] = {gv.x, gv.y, gv.z, gv.w};
             uint32_t dw[4][3], pcs[4];
             if constexpr (GW) {
                 // the four windows lie in the four words from the base word
@@ -508,10 +508,8 @@ __device__ void process_tile(const GbTileArgs &a, unsigned long long g, const Ti
                 if ((((unsigned long long)hhi << 32) | hlo) != 0ull) {
                     const uint32_t pc = pcs[u];
                     sumg = mad_lo16(x, pc, sumg);
-                    g0 = mad_lo16(x, hlo, g0);
-                    g1 = mad_hi16(x, hlo, g1);
-                    g2 = mad_lo16(x, hhi, g2);
-                    g3 = mad_hi16(x, hhi, g3);
+                    s0 += (unsigned long long)gs[u] * hlo;
+                    s1 += (unsigned long long)gs[u] * hhi;
                     lastkey = x << 16;
                     if constexpr (PB != 0) {
                         if (a.pmin) {
@@ -577,8 +575,8 @@ __device__ void process_tile(const GbTileArgs &a, unsigned long long g, const Ti
     // Lane part of the checksum of the resolved n, with p = 2^17 - 1 - 2g:
     //   sum of p floor(n/128)   = 131071 (sum of floor(n/128) over resolved n)
     //                             - 2 (sum over hits of floor(n/128) g popcount)
-    //   sum of p (2c+1) 2^i     = sum over chunks c of (2c+1) (131071 (sum of
-    //                             2^i over resolved n of chunk c) - 2 g_c)
+    //   sum of p (2c+1) 2^i     = sum over halves c of (2c+1) (131071 (sum of
+    //                             2^i over resolved n of half c) - 2 s_c)
     // where the sums over resolved n are the sums over the whole tile minus
     // the deficits; thread 0 adds the whole-tile terms and the masked n.
     if (tid == 0u) {
@@ -590,19 +588,17 @@ __device__ void process_tile(const GbTileArgs &a, unsigned long long g, const Ti
             deficit(nblk - 1u, ~lo, ~hi);
         }
     }
-    const unsigned long long ysum = 0ull - 131071ull * dB - 2ull * ((N0 >> 7) * sumg + accbg);
-    uint32_t zsum = (0u - 131071u * dx0 - 2u * g0) + 3u * (0u - 131071u * dx1 - 2u * g1) +
-                    5u * (0u - 131071u * dx2 - 2u * g2) + 7u * (0u - 131071u * dx3 - 2u * g3);
-    unsigned long long cs = ysum;
+    unsigned long long ysum = 0ull - 131071ull * dB - 2ull * ((N0 >> 7) * sumg + accbg);
+    unsigned long long zsum = (0ull - 131071ull * dx0 - 2ull * s0) + 3ull * (0ull - 131071ull * dx1 - 2ull * s1);
     if (tid == 0u) {
-        // every block's floor(n/128) for its 64 n, and every chunk's 2^i sum
+        // every block's floor(n/128) for its 64 n, and every half's 2^i sum
         const unsigned long long nb = nblk;
         const unsigned long long sum_b = nb * (N0 >> 7) + nb * (nb - 1ull) / 2ull;
-        cs += 131071ull * 64ull * sum_b;
-        zsum += 16u * 131071u * (nblk * 0xFFFFu);
-        if (has4) zsum += 8u;   // n = 4: p = 2 at i = 2 of chunk 0
+        ysum += 131071ull * 64ull * sum_b;
+        zsum += 4ull * 131071ull * (nb * 0xFFFFFFFFull);
+        if (has4) zsum += 8ull;   // n = 4: p = 2 at i = 2 of half 0
     }
-    cs += (unsigned long long)zsum << 32;
+    const unsigned long long cs = (ysum << 33) + zsum;
     const uint32_t gmax = minkey >> 16, mblk = minkey & 0xFFFFu;
     const uint32_t maxp = minkey == 0xFFFFFFFFu ? 0u : (gmax == 0xFFFFu ? 2u : 131071u - 2u * gmax);
     const unsigned long long key = ((unsigned long long)maxp << 32) | (0xFFFFFFFFu - mblk);
@@ -956,6 +952,8 @@ hipError_t launch_nt(const GbTileArgs &a, uint32_t grid, size_t lds, int pb, boo
 size_t gb_tile_lds_bytes(uint32_t tile_n, uint32_t halo_bits, uint32_t np_search, uint32_t n_off)
 {
     size_t words = ((tile_n + halo_bits) / 32 + 3) & ~(size_t)3;
+    words += np_search + 4;
+    words = (words + 3) & ~(size_t)3;
     words += np_search + 4;
     words = (words + 1) & ~(size_t)1;
     words += np_search + 4;

@@ -118,7 +118,7 @@ def test_config4_bench_configuration(gpu, orc):
             pmax = max(pmax, int(p.max()))
             n = 2 * (torch.arange(a, a + p.numel(), device="cuda", dtype=torch.int64) + lo // 2)
             j = (n >> 1) & 63
-            w = (n >> 7) + (((2 * (j >> 4) + 1) << (j & 15)) << 32)
+            w = ((n >> 7) << 33) + ((2 * (j >> 5) + 1) << (j & 31))
             cs += (w * p.to(torch.int64)).sum()   # int64 arithmetic wraps mod 2^64
             del p, n, j, w
         assert sum_p == sum_p_hist

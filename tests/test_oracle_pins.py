@@ -162,9 +162,9 @@ def test_pmin_bruteforce_1e5(orc, td_table):
 
 
 def _weight(n):
-    """Checksum weight of n: floor(n/128) + 2^32 (2c+1) 2^i, j = n/2 mod 64 = 16c + i."""
-    c, i = divmod((n // 2) % 64, 16)
-    return (n // 128 + ((2 * c + 1) << i << 32)) % 2**64
+    """Checksum weight of n: 2^33 floor(n/128) + (2c+1) 2^i, j = n/2 mod 64 = 32c + i."""
+    c, i = divmod((n // 2) % 64, 32)
+    return ((n // 128 << 33) + ((2 * c + 1) << i)) % 2**64
 
 
 def _summaries_by_hand(ns, ps, pmax):
@@ -212,22 +212,22 @@ def test_checksum_weight_definition(orc):
 
 def test_checksum_detects_single_and_swapped_errors():
     # a wrong p_min changes p by an even delta with |delta| < 2^16, i.e. at
-    # most 15 factors of 2: the change delta * w(n) is nonzero mod 2^64 as
-    # long as w(n) has at most 48 of them
+    # most 15 factors of 2: the change delta * w(n) is nonzero mod 2^64
+    # because w(n) has exactly (n/2) mod 32 <= 31 of them
     rng = np.random.default_rng(12)
     for n in [int(x) * 2 for x in rng.integers(2, 2**62, size=4000)] + list(range(4, 1 << 14, 2)):
-        assert _v2(_weight(n)) <= 48, n
+        assert _v2(_weight(n)) == (n // 2) % 32, n
     # two n of one 256-wide stretch exchanging their p change the sum by
-    # (p1 - p2) (w1 - w2); w1 - w2 has at most 49 factors of 2, so every
-    # exchange of two p that differ by less than 2^15 is seen (the equality
-    # at 49 is reached: n = 30 and n = 94 differ by 2^49 in weight)
+    # (p1 - p2) (w1 - w2); w1 - w2 has at most 33 factors of 2 (n and n + 128
+    # with the same (n/2) mod 64), and p1 - p2 at most 15, so every such
+    # exchange is seen
     worst = 0
-    for base in (0, 10**12 - 2**36, 2**62):
+    for base in (0, 10**12 - 2**36, 2**62, 2**63 - 256):
         ws = [_weight(base + 2 * k) for k in range(128)]
         for a in range(128):
             for b in range(a + 1, 128):
                 worst = max(worst, _v2(ws[a] - ws[b]))
-    assert worst == 49
+    assert worst == 33
 
 
 def test_config1_summary(orc):

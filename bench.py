@@ -74,6 +74,7 @@ def main():
     ap.add_argument("--plain-steps", type=int, default=1)
     ap.add_argument("--no-windows", action="store_true")
     ap.add_argument("--params", default="", help="JSON object of gb_params fields overriding the tuned ones")
+    ap.add_argument("--no-bulk", action="store_true", help="skip the bulk-verification line")
     ap.add_argument("--copy-calibrate", type=int, default=0, metavar="MIB",
                     help="also run one device-to-device copy of this many MiB (a reference "
                          "kernel of known traffic for the HBM byte counters)")
@@ -138,6 +139,26 @@ def main():
                  "segments": rp["n_segments"],
                  "tile_launch_ms": sum(plain_tile) / len(plain_tile)}
 
+    # ---- bulk verification of the same range (no per-n minimal p) --------
+    bulk = None
+    if not args.no_bulk:
+        v.verify_range_bulk(LO, HI)                  # graph capture
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        bulk_tile = []
+        for _ in range(2):
+            rb = v.verify_range_bulk(LO, HI)
+            bulk_tile.append(rb["tile_ms"])
+        torch.cuda.synchronize()
+        bulk_wall = (time.perf_counter() - t0) / 2
+        for k in ("count", "max_p", "argmax_n", "n_exhaustive", "n_failed"):
+            assert rb[k] == ref[k], k
+        print(f"# bulk: {1e3*bulk_wall:.1f} ms/step, tile kernel {sum(bulk_tile)/2:.1f} ms",
+              file=sys.stderr, flush=True)
+        bulk = {"value": count / bulk_wall, "ms_per_step": 1e3 * bulk_wall,
+                "tile_launch_ms": sum(bulk_tile) / 2,
+                "reports": "count, max p_min and its n, n_exhaustive, n_failed (no per-n p, histogram or checksum)"}
+
     # ---- batched windows: 4096 uneven windows in one persistent launch ---
     windows = None
     if not args.no_windows:
@@ -188,6 +209,7 @@ def main():
                    "wheel_max": p["wheel_max"], "parallelism": "1 GPU"},
         "plain": plain,
         "batched_windows": windows,
+        "bulk_verify": bulk,
         "summary": {k: ref[k] for k in ("count", "max_p", "argmax_n", "checksum",
                                         "n_exhaustive", "n_failed")},
         "roofline": roof,

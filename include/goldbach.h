@@ -161,6 +161,20 @@ gb_status gb_verify_range(gb_ctx *ctx, uint64_t lo, uint64_t hi,
 gb_status gb_verify_range_batched(gb_ctx *ctx, uint64_t lo, uint64_t hi,
                                   gb_result *res, void *stream);
 
+/* Bulk verification of the same range (paper section "Discussion",
+ * "Algorithmic gap with the state of the art": the verified set kept as a
+ * bitset into which each prime's shifted segment window is OR-ed, instead of
+ * a per-n lookup).  Every even n in [max(lo,4), hi] is shown to have a
+ * partition p + q with p <= P_max from the tile sieve, or goes to the
+ * exhaustive phase as in gb_verify_range.  No minimal p per n is recorded:
+ * res->pmin, res->hist and res->seg_hist must be NULL (GB_EINVAL otherwise)
+ * and res->checksum is 0.  res->count, max_p, argmax_n, n_exhaustive,
+ * n_failed and first_failed_n equal those of gb_verify_range (the largest
+ * p_min of a 64-n block is the prime that resolves its last n).  Batched
+ * (persistent, graph-replayed) form only; same status codes. */
+gb_status gb_verify_range_bulk(gb_ctx *ctx, uint64_t lo, uint64_t hi,
+                               gb_result *res, void *stream);
+
 /* Batched windows: k windows of uneven length in one persistent graph
  * launch.  pmin (nullable) is device memory of sum(len) uint16 entries,
  * window j's n at offset sum_{i<j} len_i.  sums (nullable, host, k entries)

@@ -108,6 +108,19 @@ class Verifier:
                    tile_launches=int(r.tile_launches))
         return out
 
+    def verify_range_bulk(self, lo: int, hi: int, stream=None, allow_unresolved=False):
+        """Bulk verification of every even n in [max(lo,4), hi]: every n gets a
+        partition, without recording each minimal p.  Returns count, max_p,
+        argmax_n, n_exhaustive, n_failed, first_failed_n (checksum is 0) and
+        the timings."""
+        r = Result()
+        st = self._lib.gb_verify_range_bulk(self._h, lo, hi, ctypes.byref(r), _stream_ptr(stream))
+        self._check(st, allow=(5,) if allow_unresolved else ())
+        out = r.summary()
+        out.update(status=st, n_segments=int(r.n_segments), device_ms=float(r.device_ms),
+                   tile_ms=float(r.tile_ms), tile_launches=int(r.tile_launches))
+        return out
+
     def verify_windows(self, windows, pmin=None, sums=True, hist=True, stream=None,
                        allow_unresolved=False):
         """Batched windows: ``windows`` is a sequence of (start, len)."""

@@ -82,6 +82,7 @@ SIGNATURES = {
     "gb_get_params": ([vp, ctypes.POINTER(Params)], i32),
     "gb_verify_range": ([vp, u64, u64, ctypes.POINTER(Result), vp], i32),
     "gb_verify_range_batched": ([vp, u64, u64, ctypes.POINTER(Result), vp], i32),
+    "gb_verify_range_bulk": ([vp, u64, u64, ctypes.POINTER(Result), vp], i32),
     "gb_verify_windows": ([vp, ctypes.POINTER(Window), ctypes.c_size_t, vp,
                            ctypes.POINTER(Summary), vp, vp], i32),
     "gb_verify_one": ([vp, u64, ctypes.POINTER(u64), vp], i32),

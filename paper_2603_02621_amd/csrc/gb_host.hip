@@ -484,7 +484,10 @@ gb_status finish_list(gb_ctx *c)
     return GB_OK;
 }
 
-gb_status run_range(gb_ctx *c, uint64_t lo, uint64_t hi, gb_result *res, void *stream, bool batched)
+// bulk: verification only (no per-n p_min, histogram or checksum), which
+// the tile kernel selects by a per-n output width of 1
+gb_status run_range(gb_ctx *c, uint64_t lo, uint64_t hi, gb_result *res, void *stream, bool batched,
+                    bool bulk = false)
 {
     if (!c || !res) return fail(c, GB_EINVAL, "null context or result");
     if (hi > GB_MAX_N) return fail(c, GB_EINVAL, "hi above 2^63");
@@ -502,6 +505,8 @@ gb_status run_range(gb_ctx *c, uint64_t lo, uint64_t hi, gb_result *res, void *s
     if (lo > hi) return GB_OK;
     if (res->pmin && res->pmin_bits != 16 && res->pmin_bits != 32)
         return fail(c, GB_EINVAL, "pmin_bits must be 16 or 32");
+    if (bulk && (res->pmin || res->hist || res->seg_hist))
+        return fail(c, GB_EINVAL, "the bulk form gives no per-n output or histograms");
     const uint64_t C = (hi - lo) / 2 + 1;
     const uint64_t S = 1ull << c->prm.seg_log2;
     const uint64_t nseg = (C + S - 1) / S;
@@ -518,7 +523,7 @@ gb_status run_range(gb_ctx *c, uint64_t lo, uint64_t hi, gb_result *res, void *s
     const size_t hist_rows = res->seg_hist ? nseg : 1;
     stt = ensure_workspace(c, ws, pl, nseg, hist_rows);
     if (stt != GB_OK) return stt;
-    const int pb = res->pmin ? (int)res->pmin_bits : 0;
+    const int pb = bulk ? 1 : (res->pmin ? (int)res->pmin_bits : 0);
     void *pmin_dev = nullptr;
     if (res->pmin) {
         if (res->pmin_on_device) {
@@ -561,7 +566,7 @@ gb_status run_range(gb_ctx *c, uint64_t lo, uint64_t hi, gb_result *res, void *s
     res->count = tot.count;
     res->max_p = tot.max_p;
     res->argmax_n = tot.argmax_n;
-    res->checksum = tot.checksum;
+    res->checksum = bulk ? 0 : tot.checksum;
     res->n_exhaustive = tot.n_exhaustive;
     res->n_failed = tot.n_failed;
     res->first_failed_n = tot.first_failed_n;
@@ -659,6 +664,13 @@ gb_status gb_verify_range_batched(gb_ctx *c, uint64_t lo, uint64_t hi, gb_result
     if (!c) return GB_EINVAL;
     if (hipSetDevice(c->prm.device) != hipSuccess) return fail(c, GB_EDEVICE, "hipSetDevice failed");
     return run_range(c, lo, hi, res, stream, true);
+}
+
+gb_status gb_verify_range_bulk(gb_ctx *c, uint64_t lo, uint64_t hi, gb_result *res, void *stream)
+{
+    if (!c) return GB_EINVAL;
+    if (hipSetDevice(c->prm.device) != hipSuccess) return fail(c, GB_EDEVICE, "hipSetDevice failed");
+    return run_range(c, lo, hi, res, stream, true, true);
 }
 
 gb_status gb_verify_windows(gb_ctx *c, const gb_window *w, size_t k, uint16_t *pmin, gb_summary *sums,

@@ -173,6 +173,11 @@ __device__ void process_tile(const GbTileArgs &a, unsigned long long g, const Ti
     // made opaque per tile: otherwise the compiler hoists values derived
     // from the thread index out of a persistent workgroup's tile loop and
     // keeps them live in registers across it (87 instead of 49 VGPRs)
+    // PB == 1: bulk verification (section "Discussion": the verified set as
+    // a bitset that each prime's shifted window is OR-ed into); no per-n
+    // output, histogram or checksum, only count, max p_min and its n,
+    // n_exhaustive and failures
+    constexpr bool VERIFY = PB == 1;
     uint32_t tid = threadIdx.x;
     asm volatile("" : "+v"(tid));
     const uint32_t lane = tid & 63u, wave = tid >> 6;
@@ -218,7 +223,7 @@ __device__ void process_tile(const GbTileArgs &a, unsigned long long g, const Ti
                 hi = ((((p3 + 1u) >> 1) + 31u) >> 5) - ((h + 31u) >> 5);
             }
             L.px[i] = (hi << 16) | (65536u - h);
-            L.gl[i] = 65536u - h;
+            L.gl[i] = VERIFY ? (65536u - h) << 16 : 65536u - h;
             L.lhist[i] = 0;
         }
         if (tid < 4) L.red[tid] = 0ull;   // tile sums, max key, OR words
@@ -447,6 +452,29 @@ __device__ void process_tile(const GbTileArgs &a, unsigned long long g, const Ti
         }
     };
 
+    // key (g << 16) of the last hit on block bb, found by searching it again
+    // one prime at a time (bulk mode, for the rare blocks the fast path
+    // leaves with unresolved n)
+    auto last_hit_key = [&](uint32_t bb) -> uint32_t {
+        uint32_t ulo, uhi;
+        block_mask(bb, ulo, uhi);
+        uint32_t key = (bb == 0u && has4) ? 0xFFFF0000u : 0xFFFFFFFFu;
+        const uint32_t base = 64u * bb + HB;
+        for (uint32_t kk = 0; kk < nps; ++kk) {
+            const uint32_t g = L.px[kk] & 0xFFFFu;
+            const uint32_t s = base - (65536u - g);
+            const uint32_t *wp = L.bits + (s >> 5);
+            const uint32_t hlo = __builtin_amdgcn_alignbit(wp[1], wp[0], s) & ulo;
+            const uint32_t hhi = __builtin_amdgcn_alignbit(wp[2], wp[1], s) & uhi;
+            if (hlo | hhi) {
+                key = g << 16;
+                ulo ^= hlo;
+                uhi ^= hhi;
+            }
+        }
+        return key;
+    };
+
     // block state: unresolved mask U, next prime index k, LDS byte address
     // of the block's base word minus PX_BIAS (bw), g << 16 of the block's
     // last hit (the last hit carries the block's largest p_min)
@@ -457,7 +485,7 @@ __device__ void process_tile(const GbTileArgs &a, unsigned long long g, const Ti
         block_mask(b, Ulo, Uhi);
         if (b == 0u && has4) {
             lastkey = 0xFFFF0000u;    // p = 2
-            atomicAdd(&hist[0], 1ull);
+            if (!VERIFY) atomicAdd(&hist[0], 1ull);
             if (a.pmin) store_p<PB>(a.pmin, outb + 2u, 2u);
         }
     }
@@ -499,6 +527,20 @@ __device__ void process_tile(const GbTileArgs &a, unsigned long long g, const Ti
                     dw[u][2] = wp[2];
                 }
             }
+            if constexpr (VERIFY) {
+                // every n the prime resolves leaves U; the last probe that
+                // starts on a nonempty U is the one that empties it, i.e. the
+                // block's last hit (when the block resolves completely)
+#pragma unroll
+                for (uint32_t u = 0; u < 4; ++u) {
+                    const uint32_t x = xs[u];
+                    const uint32_t wlo = __builtin_amdgcn_alignbit(dw[u][1], dw[u][0], x);
+                    const uint32_t whi = __builtin_amdgcn_alignbit(dw[u][2], dw[u][1], x);
+                    lastkey = (Ulo | Uhi) != 0u ? gs[u] : lastkey;
+                    Ulo &= ~wlo;
+                    Uhi &= ~whi;
+                }
+            } else {
 #pragma unroll
             for (uint32_t u = 0; u < 4; ++u) {
                 const uint32_t x = xs[u];
@@ -530,6 +572,7 @@ __device__ void process_tile(const GbTileArgs &a, unsigned long long g, const Ti
             unsigned long long *lh2 = reinterpret_cast<unsigned long long *>(L.lhist + k);
             if (pcs[0] | pcs[1]) atomicAdd(&lh2[0], (unsigned long long)pcs[0] | ((unsigned long long)pcs[1] << 32));
             if (pcs[2] | pcs[3]) atomicAdd(&lh2[1], (unsigned long long)pcs[2] | ((unsigned long long)pcs[3] << 32));
+            }
             k += 4;
         }
         // Blocks are handed out by a workgroup counter as lanes finish, so
@@ -550,8 +593,14 @@ __device__ void process_tile(const GbTileArgs &a, unsigned long long g, const Ti
             }
             nb = __builtin_amdgcn_readlane(nb, leader);
             if (done) {
-                accbg += (unsigned long long)b * (sumg - sumg0);
-                sumg0 = sumg;
+                if constexpr (VERIFY) {
+                    // a block left with unresolved n: the last probe was not
+                    // necessarily a hit, so its last hit is found again
+                    if (Ulo | Uhi) lastkey = last_hit_key(b);
+                } else {
+                    accbg += (unsigned long long)b * (sumg - sumg0);
+                    sumg0 = sumg;
+                }
                 minkey = min(minkey, lastkey | b);
                 if (Ulo | Uhi) push_unresolved(b, Ulo, Uhi);
                 b = nb + __builtin_amdgcn_mbcnt_hi((uint32_t)(dm >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)dm, 0u));
@@ -598,7 +647,7 @@ __device__ void process_tile(const GbTileArgs &a, unsigned long long g, const Ti
         zsum += 4ull * 131071ull * (nb * 0xFFFFFFFFull);
         if (has4) zsum += 8ull;   // n = 4: p = 2 at i = 2 of half 0
     }
-    const unsigned long long cs = (ysum << 33) + zsum;
+    const unsigned long long cs = VERIFY ? 0ull : (ysum << 33) + zsum;
     const uint32_t gmax = minkey >> 16, mblk = minkey & 0xFFFFu;
     const uint32_t maxp = minkey == 0xFFFFFFFFu ? 0u : (gmax == 0xFFFFu ? 2u : 131071u - 2u * gmax);
     const unsigned long long key = ((unsigned long long)maxp << 32) | (0xFFFFFFFFu - mblk);
@@ -608,9 +657,11 @@ __device__ void process_tile(const GbTileArgs &a, unsigned long long g, const Ti
     if (nexh) atomicAdd(&L.red[1], (unsigned long long)nexh);
     if (maxp) atomicMax(&L.red[2], key);
     __syncthreads();
-    for (uint32_t i = tid; i < nps; i += NT) {
-        const uint32_t c = L.lhist[i];
-        if (c) atomicAdd(&hist[i + 1], (unsigned long long)c);
+    if (!VERIFY) {
+        for (uint32_t i = tid; i < nps; i += NT) {
+            const uint32_t c = L.lhist[i];
+            if (c) atomicAdd(&hist[i + 1], (unsigned long long)c);
+        }
     }
     if (wave == 0) {
         const unsigned long long csum = L.red[0], xsum = L.red[1], kmax = L.red[2];
@@ -908,6 +959,7 @@ hipError_t allow_lds_search(size_t lds)
 {
     hipError_t e = hipSuccess, r;
     if ((r = allow_lds<NT, 0, false, false, GW>(lds)) != hipSuccess) e = r;
+    if ((r = allow_lds<NT, 1, true, false, GW>(lds)) != hipSuccess) e = r;
     if ((r = allow_lds<NT, 16, false, false, GW>(lds)) != hipSuccess) e = r;
     if ((r = allow_lds<NT, 32, false, false, GW>(lds)) != hipSuccess) e = r;
     if ((r = allow_lds<NT, 0, true, false, GW>(lds)) != hipSuccess) e = r;
@@ -930,6 +982,7 @@ template <int NT, bool GW>
 hipError_t launch_search(const GbTileArgs &a, uint32_t grid, size_t lds, int pb, bool pers, hipStream_t st)
 {
     if (pers) {
+        if (pb == 1) return launch_one<NT, 1, true, false, GW>(a, grid, lds, st);
         if (pb == 16) return launch_one<NT, 16, true, false, GW>(a, grid, lds, st);
         if (pb == 32) return launch_one<NT, 32, true, false, GW>(a, grid, lds, st);
         return launch_one<NT, 0, true, false, GW>(a, grid, lds, st);

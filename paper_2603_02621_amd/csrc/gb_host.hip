@@ -83,7 +83,6 @@ GbTileArgs base_args(gb_ctx *c, Workspace &ws)
     a.np_search = c->np_search;
     a.primes = c->d_primes;
     a.magic = c->d_magic;
-    a.pinv = c->d_pinv;
     a.k_first = c->k_first;
     a.k_wg_end = c->k_wg_end;
     a.k_wave_end = c->k_wave_end;
@@ -272,17 +271,11 @@ gb_status build_tables(gb_ctx *c)
     c->table_limit = lim;
     c->ntab = c->h_primes.size();
     std::vector<unsigned long long> magic(c->ntab);
-    std::vector<double> pinv(c->ntab);
-    for (uint64_t i = 0; i < c->ntab; ++i) {
-        magic[i] = ~0ull / c->h_primes[i];
-        pinv[i] = 1.0 / (double)c->h_primes[i];
-    }
+    for (uint64_t i = 0; i < c->ntab; ++i) magic[i] = ~0ull / c->h_primes[i];
     GB_HIP(c, hipMalloc(&c->d_primes, c->ntab * 4));
     GB_HIP(c, hipMalloc(&c->d_magic, c->ntab * 8));
-    GB_HIP(c, hipMalloc(&c->d_pinv, c->ntab * 8));
     GB_HIP(c, hipMemcpy(c->d_primes, c->h_primes.data(), c->ntab * 4, hipMemcpyHostToDevice));
     GB_HIP(c, hipMemcpy(c->d_magic, magic.data(), c->ntab * 8, hipMemcpyHostToDevice));
-    GB_HIP(c, hipMemcpy(c->d_pinv, pinv.data(), c->ntab * 8, hipMemcpyHostToDevice));
     return GB_OK;
 }
 
@@ -290,11 +283,9 @@ void free_tables(gb_ctx *c)
 {
     if (c->d_primes) (void)hipFree(c->d_primes);
     if (c->d_magic) (void)hipFree(c->d_magic);
-    if (c->d_pinv) (void)hipFree(c->d_pinv);
     if (c->d_wheel) (void)hipFree(c->d_wheel);
     c->d_primes = nullptr;
     c->d_magic = nullptr;
-    c->d_pinv = nullptr;
     c->d_wheel = nullptr;
 }
 

@@ -56,7 +56,6 @@ struct GbTileArgs {
     uint32_t np_search;     // odd primes <= P_max
     const uint32_t *primes; // odd primes 3, 5, 7, ... ascending
     const unsigned long long *magic;  // floor((2^64-1)/p) per prime
-    const double *pinv;               // 1/p per prime, rounded to double
     uint32_t k_first;       // first prime index above the wheel
     uint32_t k_wg_end;      // primes [k_first, k_wg_end): whole-workgroup marking
     uint32_t k_wave_end;    // primes [k_wg_end, k_wave_end): one wave per prime

@@ -27,6 +27,7 @@
 // is confirmed with the other eleven bases of the deterministic 64-bit test
 // (bases 2..37), one base per lane.
 #include <algorithm>
+#include <type_traits>
 
 #include "gb_internal.h"
 
@@ -55,22 +56,26 @@ __device__ __forceinline__ unsigned long long first_index(long long w0, uint32_t
     return (d & 1u) ? ((unsigned long long)d + p) >> 1 : (unsigned long long)(d >> 1);
 }
 
-// Same as first_index for a window start below 2^53, with the residue
-// w0 mod p from double precision: q = floor(w0 * (1/p)) is off by at most one
-// from w0 / p, and the FMA residual w0 - q*p is an exact small integer.
-__device__ __forceinline__ unsigned long long first_index_f64(long long w0, double w0d, uint32_t p,
-                                                              double pinv)
+// Same as first_index when p*p <= w0 < 2^53, from the prime alone.  With
+// b = 2p and y = w0 - p the gap to the next odd multiple of p is
+// d = ceil(y/b)*b - y.  The reciprocal of b is the hardware estimate refined
+// by two Newton steps (relative error near 2^-52), so the quotient y/b < 2^52
+// is off by less than one and ceil() by at most one either way; the FMA
+// residual is an exact small integer, corrected once in each direction.
+__device__ __forceinline__ uint32_t first_index_rcp(double w0d, uint32_t p)
 {
-    const unsigned long long pp = (unsigned long long)p * p;
-    if (w0 <= 0 || (unsigned long long)w0 <= pp)
-        return (pp - (unsigned long long)w0) >> 1;
     const double pd = (double)p;
-    const double q = floor(w0d * pinv);
-    int r = (int)fma(-q, pd, w0d);
-    if (r < 0) r += (int)p;
-    if (r >= (int)p) r -= (int)p;
-    const uint32_t d = r ? p - (uint32_t)r : 0u;
-    return (d & 1u) ? ((unsigned long long)d + p) >> 1 : (unsigned long long)(d >> 1);
+    const double b = pd + pd;
+    double x = __builtin_amdgcn_rcp(b);
+    x = fma(x, fma(-b, x, 1.0), x);
+    x = fma(x, fma(-b, x, 1.0), x);
+    const double y = w0d - pd;
+    const double q = ceil(y * x);
+    int d = (int)fma(q, b, -y);
+    const int b2 = (int)(2u * p);
+    if (d < 0) d += b2;
+    if (d >= b2) d -= b2;
+    return (uint32_t)d >> 1;
 }
 
 // p * (bits 15..0 of x) + acc, p < 2^16, in one v_mad_u32_u16.
@@ -230,29 +235,34 @@ __device__ void process_tile(const GbTileArgs &a, unsigned long long g, const Ti
         if (tid == 0) *L.next = NT;       // blocks 0..NT-1 go to the threads in order
     }
     // ---- first strike of every small and medium sieving prime, once -------
-    // each lane loads its next prime ahead
+    // When the window starts at or above the square of its largest sieving
+    // prime (and below 2^53) every first strike comes from the prime alone
+    // (first_index_rcp); otherwise from the 64-bit reciprocal table.  Each
+    // lane loads its next prime ahead.
     const uint32_t kmid = min(a.k_wave_end, np);
-    {
+    const uint32_t ptop = np ? a.primes[np - 1] : 0u;
+    const bool fast = small_w0 && w0 >= (long long)((unsigned long long)ptop * ptop);
+    auto strikes = [&](auto fast_c) {
+        constexpr bool FAST = decltype(fast_c)::value;
         uint32_t k = a.k_first + tid;
         uint32_t pn = 0;
-        double vn = 0.0;
         unsigned long long mn = 0;
         if (k < kmid) {
             pn = a.primes[k];
-            if (small_w0) vn = a.pinv[k]; else mn = a.magic[k];
+            if (!FAST) mn = a.magic[k];
         }
         for (; k < kmid; k += NT) {
             const uint32_t p = pn;
-            const double pv = vn;
             const unsigned long long mg = mn;
             if (k + NT < kmid) {
                 pn = a.primes[k + NT];
-                if (small_w0) vn = a.pinv[k + NT]; else mn = a.magic[k + NT];
+                if (!FAST) mn = a.magic[k + NT];
             }
-            const unsigned long long t0 = small_w0 ? first_index_f64(w0, w0d, p, pv) : first_index(w0, p, mg);
+            const unsigned long long t0 = FAST ? first_index_rcp(w0d, p) : first_index(w0, p, mg);
             L.offs[k - a.k_first] = t0 < nbits ? (uint32_t)t0 : 0xFFFFFFFFu;
         }
-    }
+    };
+    if (fast) strikes(std::true_type{}); else strikes(std::false_type{});
 
     // ---- wheel pre-pattern: clears the odd multiples of 3..wheel_max ------
     // Pattern bit g is 1 iff 2g+1 is coprime to every wheel prime; tile bit i
@@ -338,27 +348,29 @@ __device__ void process_tile(const GbTileArgs &a, unsigned long long g, const Ti
         // large primes: one lane per prime, a few hits each; the lane loads
         // its next prime ahead
         const uint32_t kbeg3 = max(a.k_wave_end, a.k_first);
-        uint32_t k = kbeg3 + tid;
-        uint32_t pn = 0;
-        double vn = 0.0;
-        unsigned long long mn = 0;
-        if (k < np) {
-            pn = a.primes[k];
-            if (small_w0) vn = a.pinv[k]; else mn = a.magic[k];
-        }
-        for (; k < np; k += NT) {
-            const uint32_t p = pn;
-            const double pv = vn;
-            const unsigned long long mg = mn;
-            if (k + NT < np) {
-                pn = a.primes[k + NT];
-                if (small_w0) vn = a.pinv[k + NT]; else mn = a.magic[k + NT];
+        auto large = [&](auto fast_c) {
+            constexpr bool FAST = decltype(fast_c)::value;
+            uint32_t k = kbeg3 + tid;
+            uint32_t pn = 0;
+            unsigned long long mn = 0;
+            if (k < np) {
+                pn = a.primes[k];
+                if (!FAST) mn = a.magic[k];
             }
-            const unsigned long long t0 = small_w0 ? first_index_f64(w0, w0d, p, pv) : first_index(w0, p, mg);
-            if (t0 >= nbits) continue;
-            for (uint32_t idx = (uint32_t)t0; idx < nbits; idx += p)
-                lds_and(bits_a + 4u * (idx >> 5), ~(1u << (idx & 31u)));
-        }
+            for (; k < np; k += NT) {
+                const uint32_t p = pn;
+                const unsigned long long mg = mn;
+                if (k + NT < np) {
+                    pn = a.primes[k + NT];
+                    if (!FAST) mn = a.magic[k + NT];
+                }
+                const unsigned long long t0 = FAST ? first_index_rcp(w0d, p) : first_index(w0, p, mg);
+                if (t0 >= nbits) continue;
+                for (uint32_t idx = (uint32_t)t0; idx < nbits; idx += p)
+                    lds_and(bits_a + 4u * (idx >> 5), ~(1u << (idx & 31u)));
+            }
+        };
+        if (fast) large(std::true_type{}); else large(std::false_type{});
     }
     __syncthreads();
 

@@ -126,7 +126,6 @@ struct gb_ctx {
     std::vector<uint32_t> h_primes;  // odd primes 3, 5, 7, ...
     uint32_t *d_primes = nullptr;
     unsigned long long *d_magic = nullptr;
-    double *d_pinv = nullptr;
     uint64_t ntab = 0;
     uint64_t table_limit = 0;        // every odd prime <= table_limit is in the table
     uint32_t np_search = 0, k_first = 0, halo_bits = 0;

@@ -63,6 +63,8 @@ def _same_summary(got, ref):
     (1_000_003**2 - (1 << 19), 1 << 20),           # across 1000003^2
     ((1 << 50) - (1 << 22) - 1, 1 << 20),          # top of the default table
     (999_999_999_999_999_001, 64 * 4099),          # ragged tile count
+    ((1 << 53) - (1 << 21) - 1, 1 << 20),          # last windows whose start is below 2^53
+    ((1 << 53) - (1 << 20) + 1, 1 << 20),          # tiles on both sides of 2^53
 ])
 def test_sieve_window_vs_oracle(orc, w0, nbits):
     _gpu()
@@ -106,6 +108,24 @@ def test_range_uint16_vs_oracle(V, orc, lo, hi):
     assert np.array_equal(_host(out), ref)
     assert np.array_equal(got["hist"], rh)
     _same_summary(got, rs)
+
+
+@pytest.mark.parametrize("lo,hi", [
+    ((1 << 53) - (1 << 21), (1 << 53) + (1 << 20)),   # first strikes on both sides of 2^53
+    (1_000_003**2 - 200_000, 1_000_003**2 + 200_000),   # window starts on both sides of the top prime's square
+    (94_906_249**2 - 200_000, 94_906_249**2 + 200_000),  # the same below 2^53 with the largest such prime
+])
+def test_range_near_2p53_vs_oracle(orc, lo, hi):
+    _gpu()
+    from paper_2603_02621_amd import Verifier
+    v = Verifier(0, max_hi=1 << 54)
+    ref, rh, rs = orc.verify_range(lo, hi, per_n_bits=16, threads=4)
+    out = _dev_pmin(len(ref), 16)
+    got = v.verify_range(lo, hi, pmin=out)
+    assert np.array_equal(_host(out), ref)
+    assert np.array_equal(got["hist"], rh)
+    _same_summary(got, rs)
+    v.close()
 
 
 def test_empty_range(V):

@@ -86,7 +86,26 @@ __device__ __forceinline__ uint32_t mad_lo16(uint32_t p, uint32_t x, uint32_t ac
     return d;
 }
 
+// Bit 16 of x copied to all 32 bits (v_bfe_i32).
+__device__ __forceinline__ uint32_t sext_bit16(uint32_t x)
+{
+    uint32_t d;
+    asm("v_bfe_i32 %0, %1, 16, 1" : "=v"(d) : "v"(x));
+    return d;
+}
+
+// (m & a) | (~m & b) in one v_bfi_b32.
+__device__ __forceinline__ uint32_t bitsel(uint32_t m, uint32_t a, uint32_t b)
+{
+    uint32_t d;
+    asm("v_bfi_b32 %0, %1, %2, %3" : "=v"(d) : "v"(m), "v"(a), "v"(b));
+    return d;
+}
+
 typedef __attribute__((address_space(3))) uint32_t lds_u32;
+typedef __attribute__((address_space(3))) unsigned long long lds_u64;
+typedef uint32_t v4u32 __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(3))) v4u32 lds_v4;
 
 // LDS byte address bw + bits 31..16 of the packed prime word x.
 __device__ __forceinline__ const lds_u32 *probe_addr(uint32_t x, uint32_t bw)
@@ -132,12 +151,18 @@ __device__ __forceinline__ void store_p(void *out, unsigned long long idx, uint3
     if constexpr (PB == 32) static_cast<uint32_t *>(out)[idx] = p;
 }
 
+// Word offsets of prime i's packed word, g and hit count in TileLds::pr.
+__device__ __forceinline__ uint32_t pr_px(uint32_t i) { return 12u * (i >> 2) + (i & 3u); }
+__device__ __forceinline__ uint32_t pr_gl(uint32_t i) { return pr_px(i) + 4u; }
+__device__ __forceinline__ uint32_t pr_lh(uint32_t i) { return pr_px(i) + 8u; }
+
 // LDS carve-up of one tile workgroup (offsets in 32-bit words).
 struct TileLds {
     uint32_t *bits;           // (T + HB)/32 words: the tile's window, 1 = prime
-    uint32_t *px;             // packed words of the odd primes p <= P_max, padded by 4
-    uint32_t *gl;             // g = 2^16 - (p+1)/2 of the same primes, padded by 4
-    uint32_t *lhist;          // per-prime hit counts of this tile, padded by 4
+    // odd primes p <= P_max (padded by 4 copies of the last) in groups of
+    // four, 12 words per group: the four packed words, the four g =
+    // 2^16 - (p+1)/2, the four hit counts of this tile
+    uint32_t *pr;
     uint32_t *offs;           // first bit index (or ~0) of each small/medium sieving prime
     unsigned long long *red;  // 4: checksum, n_exhaustive, max key, OR words
     unsigned long long *tile; // persistent mode: the tile just taken
@@ -151,15 +176,8 @@ __device__ __forceinline__ TileLds carve(uint32_t *smem, const GbTileArgs &a)
     L.bits = smem + o;
     o += (a.tile_n + a.halo_bits) / 32;
     o = (o + 3) & ~3u;   // 16-byte aligned: a group reads its four words at once
-    L.px = smem + o;
-    o += a.np_search + 4;
-    o = (o + 3) & ~3u;
-    L.gl = smem + o;
-    o += a.np_search + 4;
-    o = (o + 1) & ~1u;   // counters are added in pairs (64-bit LDS atomics)
-    L.lhist = smem + o;
-    o += a.np_search + 4;
-    o = (o + 1) & ~1u;
+    L.pr = smem + o;
+    o += 12u * ((a.np_search + 7u) / 4u);
     L.offs = smem + o;
     o += a.n_off;
     o = (o + 1) & ~1u;
@@ -227,9 +245,9 @@ __device__ void process_tile(const GbTileArgs &a, unsigned long long g, const Ti
                 const uint32_t p3 = a.primes[i3 < nps ? i3 : (nps ? nps - 1 : 0)];
                 hi = ((((p3 + 1u) >> 1) + 31u) >> 5) - ((h + 31u) >> 5);
             }
-            L.px[i] = (hi << 16) | (65536u - h);
-            L.gl[i] = VERIFY ? (65536u - h) << 16 : 65536u - h;
-            L.lhist[i] = 0;
+            L.pr[pr_px(i)] = (hi << 16) | (65536u - h);
+            L.pr[pr_gl(i)] = VERIFY ? (65536u - h) << 16 : 65536u - h;
+            L.pr[pr_lh(i)] = 0;
         }
         if (tid < 4) L.red[tid] = 0ull;   // tile sums, max key, OR words
         if (tid == 0) *L.next = NT;       // blocks 0..NT-1 go to the threads in order
@@ -473,7 +491,7 @@ __device__ void process_tile(const GbTileArgs &a, unsigned long long g, const Ti
         uint32_t key = (bb == 0u && has4) ? 0xFFFF0000u : 0xFFFFFFFFu;
         const uint32_t base = 64u * bb + HB;
         for (uint32_t kk = 0; kk < nps; ++kk) {
-            const uint32_t g = L.px[kk] & 0xFFFFu;
+            const uint32_t g = L.pr[pr_px(kk)] & 0xFFFFu;
             const uint32_t s = base - (65536u - g);
             const uint32_t *wp = L.bits + (s >> 5);
             const uint32_t hlo = __builtin_amdgcn_alignbit(wp[1], wp[0], s) & ulo;
@@ -487,12 +505,19 @@ __device__ void process_tile(const GbTileArgs &a, unsigned long long g, const Ti
         return key;
     };
 
-    // block state: unresolved mask U, next prime index k, LDS byte address
-    // of the block's base word minus PX_BIAS (bw), g << 16 of the block's
-    // last hit (the last hit carries the block's largest p_min)
+    // block state: unresolved mask U, LDS byte address of the next group of
+    // four primes (ka), LDS byte address of the block's base word minus
+    // PX_BIAS (bw), g << 16 of the block's last hit (the last hit carries
+    // the block's largest p_min)
     const uint32_t bits_addr = (uint32_t)(uintptr_t)(lds_u32 *)L.bits;
-    uint32_t b = tid, k = 0, Ulo = 0, Uhi = 0, lastkey = 0xFFFFFFFFu;
+    const uint32_t pr_addr = (uint32_t)(uintptr_t)(lds_u32 *)L.pr;
+    const uint32_t ka_end = pr_addr + 48u * ((nps + 3u) / 4u);
+    uint32_t b = tid, ka = pr_addr, Ulo = 0, Uhi = 0, lastkey = 0xFFFFFFFFu;
     uint32_t bw = bits_addr + 8u * tid + HB / 8u - PX_BIAS;
+    // Blocks are handed out in chunks of 64 that a wave holds in scalar
+    // registers ([c_next, c_end)); its lanes start on blocks tid, and the
+    // workgroup counter hands out the chunks from NT on.
+    uint32_t c_next = 0, c_end = 0;
     if (b < nblk) {
         block_mask(b, Ulo, Uhi);
         if (b == 0u && has4) {
@@ -507,13 +532,8 @@ __device__ void process_tile(const GbTileArgs &a, unsigned long long g, const Ti
             // copies of its last prime, which cannot hit an n twice
             // the group's twelve window words do not depend on the hits, so
             // they are all read before the first test
-            const uint4 xv = *reinterpret_cast<const uint4 *>(L.px + k);
+            const v4u32 xv = *reinterpret_cast<const lds_v4 *>(static_cast<uintptr_t>(ka));
             const uint32_t xs[4] = {xv.x, xv.y, xv.z, xv.w};
-            uint4 gv = *reinterpret_cast<const uint4 *>(L.gl + k);
-            // one 16-byte read up front (otherwise the compiler sinks single
-            // reads into the hit branches)
-            asm volatile("" : "+v"(gv.x), "+v"(gv.y), "+v"(gv.z), "+v"(gv.w));
-            const uint32_t gs[4] = {gv.x, gv.y, gv.z, gv.w};
             uint32_t dw[4][3], pcs[4];
             if constexpr (GW) {
                 // the four windows lie in the four words from the base word
@@ -522,10 +542,12 @@ __device__ void process_tile(const GbTileArgs &a, unsigned long long g, const Ti
                 const uint32_t w0 = wp[0], w1 = wp[1], w2 = wp[2], w3 = wp[3];
 #pragma unroll
                 for (uint32_t u = 0; u < 3; ++u) {
-                    const bool up = xs[u] >= 0x10000u;
-                    dw[u][0] = up ? w1 : w0;
-                    dw[u][1] = up ? w2 : w1;
-                    dw[u][2] = up ? w3 : w2;
+                    // all ones when the flag (bit 16) is set: one bit-field
+                    // extract, then three bit-wise selects
+                    const uint32_t m = sext_bit16(xs[u]);
+                    dw[u][0] = bitsel(m, w1, w0);
+                    dw[u][1] = bitsel(m, w2, w1);
+                    dw[u][2] = bitsel(m, w3, w2);
                 }
                 dw[3][0] = w0;
                 dw[3][1] = w1;
@@ -539,6 +561,11 @@ __device__ void process_tile(const GbTileArgs &a, unsigned long long g, const Ti
                     dw[u][2] = wp[2];
                 }
             }
+            // the group's four g with one 16-byte read up front (otherwise
+            // the compiler sinks single reads into the hit branches)
+            v4u32 gv = *reinterpret_cast<const lds_v4 *>(static_cast<uintptr_t>(ka + 16u));
+            asm volatile("" : "+v"(gv.x), "+v"(gv.y), "+v"(gv.z), "+v"(gv.w));
+            const uint32_t gs[4] = {gv.x, gv.y, gv.z, gv.w};
             if constexpr (VERIFY) {
                 // every n the prime resolves leaves U; the last probe that
                 // starts on a nonempty U is the one that empties it, i.e. the
@@ -559,7 +586,7 @@ __device__ void process_tile(const GbTileArgs &a, unsigned long long g, const Ti
                 const uint32_t hlo = __builtin_amdgcn_alignbit(dw[u][1], dw[u][0], x) & Ulo;
                 const uint32_t hhi = __builtin_amdgcn_alignbit(dw[u][2], dw[u][1], x) & Uhi;
                 pcs[u] = __popc(hlo) + __popc(hhi);
-                if ((((unsigned long long)hhi << 32) | hlo) != 0ull) {
+                if (pcs[u] != 0u) {
                     const uint32_t pc = pcs[u];
                     sumg = mad_lo16(x, pc, sumg);
                     s0 += (unsigned long long)gs[u] * hlo;
@@ -581,30 +608,44 @@ __device__ void process_tile(const GbTileArgs &a, unsigned long long g, const Ti
                 }
             }
             // the group's hit counts, two primes per 64-bit LDS atomic
-            unsigned long long *lh2 = reinterpret_cast<unsigned long long *>(L.lhist + k);
-            if (pcs[0] | pcs[1]) atomicAdd(&lh2[0], (unsigned long long)pcs[0] | ((unsigned long long)pcs[1] << 32));
-            if (pcs[2] | pcs[3]) atomicAdd(&lh2[1], (unsigned long long)pcs[2] | ((unsigned long long)pcs[3] << 32));
+            lds_u64 *lh2 = reinterpret_cast<lds_u64 *>(static_cast<uintptr_t>(ka + 32u));
+            const unsigned long long c01 = (unsigned long long)pcs[0] | ((unsigned long long)pcs[1] << 32);
+            const unsigned long long c23 = (unsigned long long)pcs[2] | ((unsigned long long)pcs[3] << 32);
+            if (c01 != 0ull) __hip_atomic_fetch_add(&lh2[0], c01, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            if (c23 != 0ull) __hip_atomic_fetch_add(&lh2[1], c23, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
             }
-            k += 4;
+            ka += 48u;
         }
-        // Blocks are handed out by a workgroup counter as lanes finish, so
-        // that no lane idles while others still have long blocks: one LDS
-        // atomic per wave for all its lanes that finished in this round.
-        const bool done = (Ulo | Uhi) == 0u || k >= nps;
-        const unsigned long long dm = __builtin_amdgcn_ballot_w64(done);
+        // Lanes that finish a block take the next blocks of their wave's
+        // chunk, so that no lane idles while others still have long blocks;
+        // a wave whose chunk runs short takes a new one with one LDS atomic.
+        const unsigned long long dm =
+            __builtin_amdgcn_uicmp(Ulo | Uhi, 0u, 32) | __builtin_amdgcn_uicmp(ka, ka_end, 35);  // ==, >=
         if (dm != 0ull) {
-            const uint32_t leader = (uint32_t)__builtin_ctzll(dm);
-            uint32_t nb = 0;
-            if (lane == leader) {
-                // the counter's address is made opaque so that the compiler
-                // does not wrap this one-lane atomic in its wave aggregation
-                uint32_t na = (uint32_t)(uintptr_t)(lds_u32 *)L.next;
-                asm volatile("" : "+v"(na));
-                nb = __hip_atomic_fetch_add(reinterpret_cast<lds_u32 *>(static_cast<uintptr_t>(na)),
-                                            (uint32_t)__popcll(dm), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            const uint32_t cnt = (uint32_t)__popcll(dm);
+            const uint32_t r = __builtin_amdgcn_mbcnt_hi((uint32_t)(dm >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)dm, 0u));
+            uint32_t nb = c_next + r;
+            if (c_end - c_next >= cnt) {
+                c_next += cnt;
+            } else {
+                const uint32_t rem = c_end - c_next;
+                const uint32_t leader = (uint32_t)__builtin_ctzll(dm);
+                uint32_t cn = 0;
+                if (lane == leader) {
+                    // the counter's address is made opaque so that the
+                    // compiler does not wrap this one-lane atomic in its wave
+                    // aggregation
+                    uint32_t na = (uint32_t)(uintptr_t)(lds_u32 *)L.next;
+                    asm volatile("" : "+v"(na));
+                    cn = __hip_atomic_fetch_add(reinterpret_cast<lds_u32 *>(static_cast<uintptr_t>(na)), 64u,
+                                                __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                }
+                cn = __builtin_amdgcn_readlane(cn, leader);
+                nb = r < rem ? nb : cn + (r - rem);
+                c_next = cn + (cnt - rem);
+                c_end = cn + 64u;
             }
-            nb = __builtin_amdgcn_readlane(nb, leader);
-            if (done) {
+            if ((Ulo | Uhi) == 0u || ka >= ka_end) {
                 if constexpr (VERIFY) {
                     // a block left with unresolved n: the last probe was not
                     // necessarily a hit, so its last hit is found again
@@ -615,9 +656,9 @@ __device__ void process_tile(const GbTileArgs &a, unsigned long long g, const Ti
                 }
                 minkey = min(minkey, lastkey | b);
                 if (Ulo | Uhi) push_unresolved(b, Ulo, Uhi);
-                b = nb + __builtin_amdgcn_mbcnt_hi((uint32_t)(dm >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)dm, 0u));
+                b = nb;
                 bw = bits_addr + 8u * b + HB / 8u - PX_BIAS;
-                k = 0;
+                ka = pr_addr;
                 Ulo = ~0u;
                 Uhi = ~0u;
             // the tile's last block may be partial: a wave-level test keeps
@@ -671,7 +712,7 @@ __device__ void process_tile(const GbTileArgs &a, unsigned long long g, const Ti
     __syncthreads();
     if (!VERIFY) {
         for (uint32_t i = tid; i < nps; i += NT) {
-            const uint32_t c = L.lhist[i];
+            const uint32_t c = L.pr[pr_lh(i)];
             if (c) atomicAdd(&hist[i + 1], (unsigned long long)c);
         }
     }
@@ -690,7 +731,7 @@ __device__ void process_tile(const GbTileArgs &a, unsigned long long g, const Ti
             const uint32_t hmp = (mp + 1u) >> 1, mbase = 64u * mb + HB;
             uint32_t olo = 0, ohi = 0;
             for (uint32_t kk = lane; kk < nps; kk += 64u) {
-                const uint32_t h = 65536u - (L.px[kk] & 0xFFFFu);
+                const uint32_t h = 65536u - (L.pr[pr_px(kk)] & 0xFFFFu);
                 if (h < hmp) {
                     const uint32_t s = mbase - h;
                     const uint32_t *wp = L.bits + (s >> 5);
@@ -1016,13 +1057,9 @@ hipError_t launch_nt(const GbTileArgs &a, uint32_t grid, size_t lds, int pb, boo
 
 size_t gb_tile_lds_bytes(uint32_t tile_n, uint32_t halo_bits, uint32_t np_search, uint32_t n_off)
 {
+    // the same carve-up as carve()
     size_t words = ((tile_n + halo_bits) / 32 + 3) & ~(size_t)3;
-    words += np_search + 4;
-    words = (words + 3) & ~(size_t)3;
-    words += np_search + 4;
-    words = (words + 1) & ~(size_t)1;
-    words += np_search + 4;
-    words = (words + 1) & ~(size_t)1;
+    words += 12 * (((size_t)np_search + 7) / 4);          // prime groups
     words += n_off;                                       // first strikes
     words = (words + 1) & ~(size_t)1;
     words += 2 * 4;                                       // tile reductions

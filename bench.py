@@ -38,8 +38,8 @@ ALU_PEAK_OPS = 256 * 64 * 2.4e9
 # HBM bytes per launch of the tile kernel on this workload, from rocprofv3
 # FETCH_SIZE and WRITE_SIZE scaled by a 1 GiB copy's readings (factors 2.000
 # and 1.000), valid only for the kernel source they were taken on.
-TRAFFIC = {"kernel_sha256_prefix": "b315bc4eb38c4157", "tile_log2": 20, "wg_threads": 1024,
-           "bytes_per_launch": 8.174e6 + 64.766e6}
+TRAFFIC = {"kernel_sha256_prefix": "945768ebd4c1806f", "tile_log2": 20, "wg_threads": 1024,
+           "bytes_per_launch": 7.995e6 + 64.787e6}
 
 
 def _load_tuned():

@@ -3,7 +3,9 @@
 Plain, slow and obviously correct: a segmented byte-per-odd-number Sieve of
 Eratosthenes plus a scan of primes p upward from 2 for every even n (the
 paper's CPU baseline, section "Methods"), with a deterministic twelve-base
-Miller-Rabin test for single 64-bit n (section "GPU Single-Number Checker").
+Miller-Rabin test for single 64-bit n (section "GPU Single-Number Checker"),
+and Goldbach partition counts c(n) by their definition (section "Future
+work").
 Only tests, ``__graft_entry__.smoke()`` and the benchmark's CPU-baseline leg
 may import this package.  The product library never does.
 
@@ -25,6 +27,14 @@ _SRC = os.path.join(_HERE, "gb_oracle.c")
 _LIB = os.path.join(_HERE, "libgb_oracle.so")
 
 HIST_BINS = 6543
+
+
+class PcSummary(ctypes.Structure):
+    _fields_ = [(name, ctypes.c_uint64) for name in (
+        "count", "sum", "min_c", "argmin_n", "max_c", "argmax_n")]
+
+    def as_dict(self):
+        return {name: int(getattr(self, name)) for name, _ in self._fields_}
 
 
 class Summary(ctypes.Structure):
@@ -73,6 +83,8 @@ def lib():
         L.orc_hist_bins.argtypes, L.orc_hist_bins.restype = [], u32
         L.orc_checksum_weight.argtypes, L.orc_checksum_weight.restype = [u64], u64
         L.orc_odd_primality.argtypes, L.orc_odd_primality.restype = [u64, u64, vp], ip
+        L.orc_partition_counts.argtypes = [vp, vp, u64, ctypes.POINTER(PcSummary), ip]
+        L.orc_partition_counts.restype = ip
         _lib = L
     return _lib
 
@@ -158,3 +170,27 @@ def verify_many(ns, limit: int = 0, threads: int = 1) -> np.ndarray:
     if arr.size:
         lib().orc_verify_many(arr.ctypes.data, out.ctypes.data, arr.size, limit, threads)
     return out
+
+
+def partition_counts(ns, threads: int = 1):
+    """Goldbach partition counts c(n) (n = p + q, primes p <= q) for each even
+    n >= 4 of ``ns``.  Returns (uint64 array, summary dict)."""
+    arr = np.ascontiguousarray(np.asarray(ns, dtype=np.uint64))
+    out = np.zeros_like(arr)
+    s = PcSummary()
+    rc = lib().orc_partition_counts(arr.ctypes.data if arr.size else None,
+                                    out.ctypes.data if arr.size else None,
+                                    arr.size, ctypes.byref(s), threads)
+    if rc == -2:
+        raise ValueError("every n must be even and at least 4")
+    if rc != 0:
+        raise MemoryError("oracle allocation failed")
+    return out, s.as_dict()
+
+
+def partition_counts_range(lo: int, hi: int, threads: int = 1):
+    """c(n) for every even n in [max(lo, 4), hi]."""
+    cnt = n_even(lo, hi)
+    first = max(lo, 4)
+    first += first & 1
+    return partition_counts(first + 2 * np.arange(cnt, dtype=np.uint64), threads)

@@ -34,6 +34,8 @@
  *                  fast path bounded by P_max leaves to an exhaustive phase)
  *   n_failed       number of n with no partition at all (a counterexample)
  *   first_failed_n smallest such n, or 0
+ *
+ * The file also counts Goldbach partitions c(n) (orc_partition_counts).
  */
 #include <stdint.h>
 #include <stdlib.h>
@@ -484,5 +486,98 @@ int orc_odd_primality(uint64_t w0, uint64_t count, uint8_t *out)
     if (!base) return -1;
     sieve_window(out, w0, whi, base, nbase);
     free(base);
+    return 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* Goldbach partition counts                                           */
+/* ------------------------------------------------------------------ */
+
+/* c(n) = number of ways to write the even n >= 4 as p + q with primes
+ * p <= q (the counts the paper's "Future work" subsection lists as the next
+ * large-scale computation; the "Discussion" links their growth to the small
+ * p_min it observes).  4 = 2 + 2 is the one partition with an even prime;
+ * for n >= 6 both primes are odd, so c(n) counts the odd primes p <= n/2
+ * with n - p prime.  Plain definition: a byte per odd number up to the
+ * largest n, and for every n a scan over the odd primes p <= n/2.
+ *
+ * Summaries of a set of n:
+ *   count              number of even n examined
+ *   sum                sum of c(n), modulo 2^64
+ *   min_c / argmin_n   smallest c(n) and the smallest n attaining it
+ *   max_c / argmax_n   largest c(n) and the smallest n attaining it
+ */
+typedef struct {
+    uint64_t count, sum, min_c, argmin_n, max_c, argmax_n;
+} orc_pc_summary;
+
+typedef struct {
+    const uint64_t *n;      /* the even n, any order */
+    uint64_t *c;
+    uint64_t count, next;
+    const uint8_t *oddp;    /* oddp[k] = 1 iff 2k+1 is prime, k <= (top-1)/2 */
+} pc_job;
+
+static uint64_t partition_count(uint64_t n, const uint8_t *oddp)
+{
+    if (n == 4) return 1;
+    uint64_t c = 0;
+    for (uint64_t p = 3; p <= n / 2; p += 2)
+        if (oddp[(p - 1) / 2] && oddp[(n - p - 1) / 2]) c++;
+    return c;
+}
+
+static void *pc_worker(void *arg)
+{
+    pc_job *j = arg;
+    for (;;) {
+        uint64_t i = __atomic_fetch_add(&j->next, 1, __ATOMIC_RELAXED);
+        if (i >= j->count) break;
+        j->c[i] = partition_count(j->n[i], j->oddp);
+    }
+    return NULL;
+}
+
+/* c(n) for each even n >= 4 of n[0..count) into c[]; summaries into *s
+ * (nullable).  Returns 0, -1 on allocation failure, -2 on an odd or small n. */
+int orc_partition_counts(const uint64_t *n, uint64_t *c, uint64_t count,
+                         orc_pc_summary *s, int nthreads)
+{
+    uint64_t top = 3;
+    for (uint64_t i = 0; i < count; i++) {
+        if (n[i] < 4 || (n[i] & 1)) return -2;
+        if (n[i] > top) top = n[i];
+    }
+    if (!(top & 1)) top -= 1;
+    uint64_t nbase;
+    uint32_t *base = odd_primes_upto(orc_isqrt(top) + 1, &nbase);
+    uint8_t *oddp = malloc((top - 1) / 2 + 1);
+    if (!base || !oddp) { free(base); free(oddp); return -1; }
+    sieve_window(oddp, 1, top, base, nbase);
+    free(base);
+    pc_job j = {n, c, count, 0, oddp};
+    if (nthreads < 1) nthreads = 1;
+    pthread_t *th = malloc(sizeof(pthread_t) * (size_t)nthreads);
+    for (int t = 0; t < nthreads; t++) pthread_create(&th[t], NULL, pc_worker, &j);
+    for (int t = 0; t < nthreads; t++) pthread_join(th[t], NULL);
+    free(th);
+    free(oddp);
+    if (s) {
+        memset(s, 0, sizeof *s);
+        s->min_c = ~0ull;
+        for (uint64_t i = 0; i < count; i++) {
+            s->count++;
+            s->sum += c[i];
+            if (s->argmin_n == 0 || c[i] < s->min_c || (c[i] == s->min_c && n[i] < s->argmin_n)) {
+                s->min_c = c[i];
+                s->argmin_n = n[i];
+            }
+            if (s->argmax_n == 0 || c[i] > s->max_c || (c[i] == s->max_c && n[i] < s->argmax_n)) {
+                s->max_c = c[i];
+                s->argmax_n = n[i];
+            }
+        }
+        if (count == 0) s->min_c = 0;
+    }
     return 0;
 }

@@ -309,3 +309,80 @@ def test_paper_no_failures_1e9(orc):
             assert s["n_exhaustive"] == 0
             assert s["count"] == 499_999_999
             assert int(hist.sum()) == s["count"]
+
+
+# --------------------------------------------------------------------------
+# Goldbach partition counts c(n) (n = p + q, primes p <= q)
+# --------------------------------------------------------------------------
+
+# Worked by hand: the partitions of each n.  4 = 2+2; 6 = 3+3; 8 = 3+5;
+# 10 = 3+7 = 5+5; 12 = 5+7; 14 = 3+11 = 7+7; 16 = 3+13 = 5+11;
+# 18 = 5+13 = 7+11; 20 = 3+17 = 7+13; 22 = 3+19 = 5+17 = 11+11;
+# 24 = 5+19 = 7+17 = 11+13; 26 = 3+23 = 7+19 = 13+13; 28 = 5+23 = 11+17;
+# 30 = 7+23 = 11+19 = 13+17.
+_PC_BY_HAND = {4: 1, 6: 1, 8: 1, 10: 2, 12: 1, 14: 2, 16: 2, 18: 2, 20: 2,
+               22: 3, 24: 3, 26: 3, 28: 2, 30: 3}
+
+
+def test_partition_counts_by_hand(orc):
+    c, s = orc.partition_counts_range(4, 30)
+    assert [int(x) for x in c] == [_PC_BY_HAND[n] for n in range(4, 31, 2)]
+    # summaries of this list: sum, the first n with the fewest (4) and the
+    # first with the most (22)
+    assert s == {"count": 14, "sum": sum(_PC_BY_HAND.values()), "min_c": 1,
+                 "argmin_n": 4, "max_c": 3, "argmax_n": 22}
+
+
+def test_partition_counts_trial_division(orc, td_table):
+    ns = list(range(4, 6001, 2))
+    c, _ = orc.partition_counts(ns, threads=4)
+    for n, got in zip(ns, c):
+        want = sum(1 for p in range(2, n // 2 + 1) if td_table[p] and td_table[n - p])
+        assert int(got) == want, n
+
+
+def _np_odd_sieve(top):
+    """is_prime for the odd numbers 1, 3, ..., top (numpy, written here)."""
+    m = (top - 1) // 2 + 1
+    isp = np.ones(m, dtype=bool)
+    isp[0] = False
+    for k in range(1, (int(top ** 0.5) - 1) // 2 + 1):
+        if isp[k]:
+            p = 2 * k + 1
+            isp[(p * p - 1) // 2::p] = False
+    return isp
+
+
+def test_partition_counts_vs_vector_sieve(orc):
+    # a different computation: for each n, AND the odd-prime flags of p and
+    # of n - p as whole vectors
+    top = 2_000_000
+    isp = _np_odd_sieve(top)
+    ns = [10**6, 10**6 - 2, 999_000, 1_999_998, 2_000_000, 1_234_568, 65_536]
+    c, _ = orc.partition_counts(ns, threads=4)
+    for n, got in zip(ns, c):
+        k = np.arange(1, (n // 2 - 1) // 2 + 1)          # odd p = 2k+1 <= n/2
+        want = int(np.count_nonzero(isp[k] & isp[(n - 2 * k - 2) // 2]))
+        assert int(got) == want, n
+
+
+def test_partition_count_total_identity(orc):
+    # sum over even n <= N of c(n) counts the pairs of primes p <= q with
+    # p + q <= N: for each prime p <= N/2, the primes q in [p, N - p]
+    N = 40_000
+    isp = _np_odd_sieve(N)
+    odd_primes = 2 * np.nonzero(isp)[0] + 1
+    pi_odd = np.cumsum(isp)                               # odd primes <= 2i+1
+    pairs = 1                                             # 2 + 2
+    for p in odd_primes[odd_primes <= N // 2]:
+        q_hi = N - p
+        q_hi -= 1 - (q_hi & 1)                            # largest odd <= N - p
+        pairs += int(pi_odd[(q_hi - 1) // 2] - pi_odd[(p - 1) // 2] + 1)
+    _, s = orc.partition_counts_range(4, N, threads=4)
+    assert s["sum"] == pairs
+    assert s["count"] == N // 2 - 1
+
+
+def test_partition_counts_rejects_odd(orc):
+    with pytest.raises(ValueError):
+        orc.partition_counts([4, 7])

@@ -207,6 +207,36 @@ gb_status gb_verify_many(gb_ctx *ctx, const uint64_t *n, uint64_t *p, size_t k,
 gb_status gb_sieve_window(gb_ctx *ctx, uint64_t w0, uint64_t nbits,
                           uint32_t *bits, void *stream);
 
+/* Goldbach partition counts (paper section "Future work": large-scale
+ * counts c(n) of the partitions n = p + q into primes p <= q).  c(4) = 1;
+ * for even n >= 6, c(n) is the number of odd primes p <= n/2 with n - p
+ * prime.  For every even n in [max(lo,4), hi]:
+ *   counts (nullable) is device memory of one uint64 per n, n_first + 2i at
+ *     index i (n_first the first even n >= max(lo,4)), overwritten;
+ *   res receives the summaries below.
+ * The call sieves the odd numbers up to hi into a device bitset (the tile
+ * sieve of gb_sieve_window), then each workgroup counts for 512 consecutive n
+ * the pairs (p, n - p) word by word: the flags of 32 consecutive p ANDed with
+ * the bit-reversed flags of the matching q, and a popcount.  Limits:
+ * hi <= max_hi, at most 2^25 even n per call, and the bitset (hi/16 bytes)
+ * plus the internal counts (when counts is NULL) within prm.mem_budget.
+ * Status: GB_EINVAL for a NULL res or too many n, GB_ERANGE above max_hi,
+ * GB_ENOMEM over the budget, GB_EDEVICE on a HIP error.  lo > hi, or no even
+ * n >= 4 in the range, gives an empty result with GB_OK. */
+typedef struct gb_pc_result {
+    uint64_t count;        /* even n examined */
+    uint64_t sum;          /* sum of c(n), modulo 2^64 */
+    uint64_t min_c;        /* smallest c(n) (0 when count is 0) */
+    uint64_t argmin_n;     /* the smallest n attaining it */
+    uint64_t max_c;        /* largest c(n) */
+    uint64_t argmax_n;     /* the smallest n attaining it */
+    double device_ms;      /* sieve, counting and summary, device time */
+    double kernel_ms;      /* the counting kernel alone */
+} gb_pc_result;
+
+gb_status gb_partition_counts(gb_ctx *ctx, uint64_t lo, uint64_t hi,
+                              uint64_t *counts, gb_pc_result *res, void *stream);
+
 /* The (n, p) pairs the last range or window call sent to the exhaustive
  * phase (p = 0 for a failure), at most cap of them, into host arrays;
  * *count receives the total number. */

@@ -9,8 +9,8 @@ from __future__ import annotations
 
 import ctypes
 
-from ._binding import (HIST_BINS, MAX_N, GoldbachError, Params, Result, Summary, Window,
-                       lib)
+from ._binding import (HIST_BINS, MAX_N, GoldbachError, Params, PcResult, Result, Summary,
+                       Window, lib)
 
 __all__ = ["Verifier", "GoldbachError", "HIST_BINS", "MAX_N"]
 
@@ -119,6 +119,25 @@ class Verifier:
         out = r.summary()
         out.update(status=st, n_segments=int(r.n_segments), device_ms=float(r.device_ms),
                    tile_ms=float(r.tile_ms), tile_launches=int(r.tile_launches))
+        return out
+
+    def partition_counts(self, lo: int, hi: int, counts=None, stream=None):
+        """Goldbach partition counts c(n) (n = p + q, primes p <= q) of every
+        even n in [max(lo,4), hi].  ``counts`` (optional) is a contiguous
+        int64 tensor on the GPU with one entry per n, overwritten.  Returns
+        count, sum, min_c, argmin_n, max_c, argmax_n and the timings."""
+        ptr = None
+        if counts is not None:
+            import torch
+            if not (hasattr(counts, "data_ptr") and counts.is_cuda and counts.is_contiguous()
+                    and counts.dtype in (torch.int64, torch.uint64)):
+                raise ValueError("counts must be a contiguous 64-bit integer tensor on the GPU")
+            ptr = counts.data_ptr()
+        r = PcResult()
+        st = self._lib.gb_partition_counts(self._h, lo, hi, ptr, ctypes.byref(r), _stream_ptr(stream))
+        self._check(st)
+        out = r.summary()
+        out.update(device_ms=float(r.device_ms), kernel_ms=float(r.kernel_ms))
         return out
 
     def verify_windows(self, windows, pmin=None, sums=True, hist=True, stream=None,

@@ -66,6 +66,16 @@ class Completion(ctypes.Structure):
                 ("batch_requests", u32), ("stream", u32)]
 
 
+class PcResult(ctypes.Structure):
+    _fields_ = [(k, u64) for k in ("count", "sum", "min_c", "argmin_n", "max_c", "argmax_n")] + \
+               [("device_ms", dbl), ("kernel_ms", dbl)]
+
+    SUMMARY = ("count", "sum", "min_c", "argmin_n", "max_c", "argmax_n")
+
+    def summary(self):
+        return {k: int(getattr(self, k)) for k in self.SUMMARY}
+
+
 class ServerStats(ctypes.Structure):
     _fields_ = [(k, u64) for k in ("submitted", "completed", "rejected", "queued", "inflight",
                                    "bytes_inflight", "peak_bytes_inflight", "launches",
@@ -88,6 +98,7 @@ SIGNATURES = {
     "gb_verify_one": ([vp, u64, ctypes.POINTER(u64), vp], i32),
     "gb_verify_many": ([vp, vp, vp, ctypes.c_size_t, ctypes.c_int, vp], i32),
     "gb_sieve_window": ([vp, u64, u64, vp, vp], i32),
+    "gb_partition_counts": ([vp, u64, u64, vp, ctypes.POINTER(PcResult), vp], i32),
     "gb_exhaustive_list": ([vp, vp, vp, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)], i32),
     "gb_autotune": ([vp, ctypes.POINTER(Window), ctypes.c_size_t, ctypes.c_char_p,
                      ctypes.POINTER(Params)], i32),

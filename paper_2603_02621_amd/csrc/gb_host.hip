@@ -223,6 +223,10 @@ void Workspace::release()
     counters.release();
     pmin.release();
     q.release();
+    pc_bits.release();
+    pc_counts.release();
+    pc_red.release();
+    h_pc_red.release();
     h_slots.release();
     h_hist.release();
     h_counters.release();
@@ -436,6 +440,27 @@ gb_status enqueue_queries(gb_ctx *c, Workspace &ws, uint64_t k, const unsigned l
     const GbMrArgs m = mr_args(c, ws);
     GB_HIP(c, gb_launch_mr(m, (uint32_t)std::min<uint64_t>(mr_grid(c), (k + 3) / 4), st));
     GB_HIP(c, gb_launch_finish_queries(ws.list.p, k, dp, st));
+    return GB_OK;
+}
+
+gb_status enqueue_sieve(gb_ctx *c, Workspace &ws, uint64_t w0, uint64_t nbits, uint32_t *bits, hipStream_t st)
+{
+    Plan pl;
+    pl.w.resize(1);
+    pl.w[0].first_n = w0 - 1 + 2ull * c->halo_bits;  // makes the tile window start at w0
+    pl.w[0].count = nbits;
+    pl.w[0].slot = 0;
+    gb_status stt = plan_windows(c, pl, false);
+    if (stt != GB_OK) return stt;
+    stt = ensure_workspace(c, ws, pl, 1, 1);
+    if (stt != GB_OK) return stt;
+    GB_HIP(c, hipMemcpyAsync(ws.win.p, pl.w.data(), sizeof(GbWindow), hipMemcpyHostToDevice, st));
+    GbTileArgs a = base_args(c, ws);
+    a.win = ws.win.p;
+    a.nwin = 1;
+    a.tile0 = 0;
+    a.sieve_out = bits;
+    GB_HIP(c, gb_launch_tiles(a, (uint32_t)pl.ntiles, c->threads, c->lds, 0, false, true, false, st));
     return GB_OK;
 }
 
@@ -780,25 +805,10 @@ gb_status gb_sieve_window(gb_ctx *c, uint64_t w0, uint64_t nbits, uint32_t *bits
         return fail(c, GB_EINVAL, "w0 must be odd, nbits a positive multiple of 64");
     if (hipSetDevice(c->prm.device) != hipSuccess) return fail(c, GB_EDEVICE, "hipSetDevice failed");
     hipStream_t st = static_cast<hipStream_t>(stream);
-    Workspace &ws = c->ws;
     const uint64_t top = w0 + 2 * nbits;
     if (top < w0 || top > c->prm.max_hi) return fail(c, GB_ERANGE, "window above the context's max_hi");
-    Plan pl;
-    pl.w.resize(1);
-    pl.w[0].first_n = w0 - 1 + 2ull * c->halo_bits;  // makes the tile window start at w0
-    pl.w[0].count = nbits;
-    pl.w[0].slot = 0;
-    gb_status stt = plan_windows(c, pl, false);
+    gb_status stt = enqueue_sieve(c, c->ws, w0, nbits, bits, st);
     if (stt != GB_OK) return stt;
-    stt = ensure_workspace(c, ws, pl, 1, 1);
-    if (stt != GB_OK) return stt;
-    GB_HIP(c, hipMemcpyAsync(ws.win.p, pl.w.data(), sizeof(GbWindow), hipMemcpyHostToDevice, st));
-    GbTileArgs a = base_args(c, ws);
-    a.win = ws.win.p;
-    a.nwin = 1;
-    a.tile0 = 0;
-    a.sieve_out = bits;
-    GB_HIP(c, gb_launch_tiles(a, (uint32_t)pl.ntiles, c->threads, c->lds, 0, false, true, false, st));
     GB_HIP(c, hipStreamSynchronize(st));
     return GB_OK;
 }

@@ -90,6 +90,10 @@ struct Workspace {
     DevBuf<unsigned long long> counters;
     DevBuf<unsigned char> pmin;          // per-n output staging
     DevBuf<unsigned long long> q;        // single-n queries: n then p
+    DevBuf<uint32_t> pc_bits;            // partition counts: odd-number bitset
+    DevBuf<unsigned long long> pc_counts;  // partition counts when the caller passes none
+    DevBuf<unsigned long long> pc_red;   // partition counts: sum, min key, max key
+    PinBuf<unsigned long long> h_pc_red;
     PinBuf<GbSlot> h_slots;
     PinBuf<unsigned long long> h_hist;
     PinBuf<unsigned long long> h_counters;
@@ -161,6 +165,9 @@ gb_status run_job(gb_ctx *c, Workspace &ws, const Job &j, const GraphKey &key, b
 // single-n queries already in ws.q (device, k entries): results to ws.q + k
 gb_status enqueue_queries(gb_ctx *c, Workspace &ws, uint64_t k, const unsigned long long *dn,
                           unsigned long long *dp, hipStream_t st);
+// the tile sieve alone: bits (device, nbits/32 words) of the odd numbers
+// w0, w0 + 2, ... (w0 odd, nbits a multiple of 64), enqueued on st
+gb_status enqueue_sieve(gb_ctx *c, Workspace &ws, uint64_t w0, uint64_t nbits, uint32_t *bits, hipStream_t st);
 void merge_slot(gb_summary &acc, const GbSlot &s);
 
 }  // namespace gbrt

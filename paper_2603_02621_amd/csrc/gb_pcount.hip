@@ -41,6 +41,15 @@ __device__ __forceinline__ uint32_t funnel(uint32_t hi, uint32_t lo, uint32_t s)
     return __builtin_amdgcn_alignbit(hi, lo, s);
 }
 
+// popcount(x) + acc in one v_bcnt_u32_b32 (the compiler otherwise counts
+// from zero and adds the counts separately)
+__device__ __forceinline__ uint32_t popc_acc(uint32_t x, uint32_t acc)
+{
+    uint32_t d;
+    asm("v_bcnt_u32_b32 %0, %1, %2" : "=v"(d) : "v"(x), "v"(acc));
+    return d;
+}
+
 __global__ __launch_bounds__(PC_NT) void k_pcount(PcArgs a)
 {
     __shared__ __align__(16) uint32_t xs[PC_C + 4];
@@ -83,21 +92,31 @@ __global__ __launch_bounds__(PC_NT) void k_pcount(PcArgs a)
         __syncthreads();
 
         const uint64_t u0 = 32 * maxw + 31 - m + 32 * a0;   // >= 0: m <= m0 + PC_NT - 1
-        const uint32_t wu = (uint32_t)(u0 >> 5);
-        uint32_t lo = rs[wu];
+        const uint32_t *rp = rs + (uint32_t)(u0 >> 5);
+        uint32_t lo = rp[0];
         uint32_t s = 0;
         const uint32_t nfull = afull <= a0 ? 0u : (afull - a0 < ns ? (uint32_t)(afull - a0) : ns);
-        for (; s + 4 <= nfull; s += 4) {
+        // two running counts, so that consecutive popcounts do not wait on
+        // each other
+        uint32_t acc2 = 0;
+        for (; s + 8 <= nfull; s += 8) {
             const pc_v4 x = *reinterpret_cast<const pc_v4 *>(xs + s);
-            const uint32_t w1 = rs[wu + s + 1], w2 = rs[wu + s + 2], w3 = rs[wu + s + 3], w4 = rs[wu + s + 4];
-            acc += __popc(funnel(w1, lo, sh) & x.x);
-            acc += __popc(funnel(w2, w1, sh) & x.y);
-            acc += __popc(funnel(w3, w2, sh) & x.z);
-            acc += __popc(funnel(w4, w3, sh) & x.w);
-            lo = w4;
+            const pc_v4 y = *reinterpret_cast<const pc_v4 *>(xs + s + 4);
+            const uint32_t w1 = rp[s + 1], w2 = rp[s + 2], w3 = rp[s + 3], w4 = rp[s + 4];
+            const uint32_t w5 = rp[s + 5], w6 = rp[s + 6], w7 = rp[s + 7], w8 = rp[s + 8];
+            acc = popc_acc(funnel(w1, lo, sh) & x.x, acc);
+            acc2 = popc_acc(funnel(w2, w1, sh) & x.y, acc2);
+            acc = popc_acc(funnel(w3, w2, sh) & x.z, acc);
+            acc2 = popc_acc(funnel(w4, w3, sh) & x.w, acc2);
+            acc = popc_acc(funnel(w5, w4, sh) & y.x, acc);
+            acc2 = popc_acc(funnel(w6, w5, sh) & y.y, acc2);
+            acc = popc_acc(funnel(w7, w6, sh) & y.z, acc);
+            acc2 = popc_acc(funnel(w8, w7, sh) & y.w, acc2);
+            lo = w8;
         }
+        acc += acc2;
         for (; s < ns; ++s) {
-            const uint32_t hi = rs[wu + s + 1];
+            const uint32_t hi = rp[s + 1];
             uint32_t v = funnel(hi, lo, sh) & xs[s];
             // i = 32(a0 + s) + t must not exceed floor(m/2)
             const int64_t rem = (int64_t)lim - 32 * (int64_t)(a0 + s);

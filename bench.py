@@ -34,6 +34,7 @@ PROBES_PER_N = 1.01
 ALG_OPS_PER_N = CLEARS_PER_N * 3 + PROBES_PER_N * 7 + 5 / 32
 # 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz, one 32-bit integer op per lane-cycle
 ALU_PEAK_OPS = 256 * 64 * 2.4e9
+PC_N, PC_HI = 1 << 16, 10**9        # partition-count workload: 2^16 even n ending at 1e9
 
 # HBM bytes per launch of the tile kernel on this workload, from rocprofv3
 # FETCH_SIZE and WRITE_SIZE scaled by a 1 GiB copy's readings (factors 2.000
@@ -75,6 +76,7 @@ def main():
     ap.add_argument("--no-windows", action="store_true")
     ap.add_argument("--params", default="", help="JSON object of gb_params fields overriding the tuned ones")
     ap.add_argument("--no-bulk", action="store_true", help="skip the bulk-verification line")
+    ap.add_argument("--no-pcount", action="store_true", help="skip the partition-count line")
     ap.add_argument("--copy-calibrate", type=int, default=0, metavar="MIB",
                     help="also run one device-to-device copy of this many MiB (a reference "
                          "kernel of known traffic for the HBM byte counters)")
@@ -175,6 +177,35 @@ def main():
         windows = {"windows": len(wins), "even_n": wn, "ms_per_step": 1e3 * wt, "value": wn / wt}
         print(f"# windows: {1e3*wt:.1f} ms for {wn} n in 4096 windows", file=sys.stderr, flush=True)
 
+    # ---- Goldbach partition counts c(n) of 2^16 even n ending at 1e9 -------
+    pcount = None
+    if not args.no_pcount:
+        pc_lo, pc_hi = PC_HI - 2 * (PC_N - 1), PC_HI
+        v.partition_counts(pc_lo, pc_hi)             # buffers
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        pk = []
+        for _ in range(2):
+            rp = v.partition_counts(pc_lo, pc_hi)
+            pk.append(rp["kernel_ms"])
+        torch.cuda.synchronize()
+        pc_wall = (time.perf_counter() - t0) / 2
+        # AND + popcount per 32 candidate pairs (p, n - p), p <= n/2: for even
+        # n >= 6 the odd p = 2i + 1 with i <= floor((n/2 - 1)/2), in words of 32 i
+        words = sum((((n // 2) - 1) // 2) // 32 + 1 for n in range(pc_lo, pc_hi + 1, 2))
+        pc_t = sum(pk) / len(pk) / 1e3
+        pc_ach = 2 * words / pc_t
+        print(f"# partition counts: {1e3*pc_wall:.1f} ms/step, kernel {1e3*pc_t:.1f} ms",
+              file=sys.stderr, flush=True)
+        pcount = {"workload": f"Goldbach partition counts c(n) of the {PC_N} even n ending at {PC_HI}",
+                  "value": PC_N / pc_wall, "unit": "even n/s", "ms_per_step": 1e3 * pc_wall,
+                  "kernel_ms": 1e3 * pc_t,
+                  "summary": {k: rp[k] for k in ("count", "sum", "min_c", "argmin_n", "max_c", "argmax_n")},
+                  "roofline": {"bound": "alu", "achieved": pc_ach / 1e12, "peak": ALU_PEAK_OPS / 1e12,
+                               "unit": "Tops/s (int32 lane ops)", "frac": pc_ach / ALU_PEAK_OPS,
+                               "kernel": "k_pcount", "alg_ops": "2 per 32 candidate pairs",
+                               "alg_ops_per_launch": 2 * words}}
+
     if args.copy_calibrate:
         nb = args.copy_calibrate << 20
         src = torch.ones(nb // 4, dtype=torch.int32, device="cuda")
@@ -210,6 +241,7 @@ def main():
         "plain": plain,
         "batched_windows": windows,
         "bulk_verify": bulk,
+        "partition_counts": pcount,
         "summary": {k: ref[k] for k in ("count", "max_p", "argmax_n", "checksum",
                                         "n_exhaustive", "n_failed")},
         "roofline": roof,

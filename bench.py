@@ -206,6 +206,9 @@ def main():
                                "kernel": "k_pcount", "alg_ops": "2 per 32 candidate pairs",
                                "alg_ops_per_launch": 2 * words}}
 
+    # ---- measured ceilings of the units (beside the nominal peaks) --------
+    peaks = v.measure_peaks()
+
     if args.copy_calibrate:
         nb = args.copy_calibrate << 20
         src = torch.ones(nb // 4, dtype=torch.int32, device="cuda")
@@ -227,7 +230,12 @@ def main():
             "traffic": TRAFFIC["bytes_per_launch"] if same else None,
             "traffic_unit": "bytes per launch (HBM, rocprofv3)",
             "kernel": "k_tile (persistent)", "launch_ms": t_launch * 1e3,
-            "alg_ops_per_n": round(ALG_OPS_PER_N, 3)}
+            "alg_ops_per_n": round(ALG_OPS_PER_N, 3),
+            "frac_of_measured": {"valu_vop2": achieved / peaks["valu_vop2_ops"],
+                                 "valu_vop3": achieved / peaks["valu_vop3_ops"]}}
+    if pcount is not None:
+        pcount["roofline"]["frac_of_measured"] = {
+            "valu_vop2": pc_ach / peaks["valu_vop2_ops"], "valu_vop3": pc_ach / peaks["valu_vop3_ops"]}
 
     out = {
         "metric": METRIC, "value": value, "unit": "even n/s", "n_gpus": 1,
@@ -245,6 +253,7 @@ def main():
         "summary": {k: ref[k] for k in ("count", "max_p", "argmax_n", "checksum",
                                         "n_exhaustive", "n_failed")},
         "roofline": roof,
+        "measured_peaks": peaks,
     }
 
     if not args.no_serve:

@@ -237,6 +237,26 @@ typedef struct gb_pc_result {
 gb_status gb_partition_counts(gb_ctx *ctx, uint64_t lo, uint64_t hi,
                               uint64_t *counts, gb_pc_result *res, void *stream);
 
+/* Measured throughput ceilings of the units the kernels use, for roofline
+ * fractions beside the nominal peaks (every figure is for the whole device,
+ * the best of three timed launches after a warm-up launch):
+ *   valu_vop2_ops   int32 lane-ops/s of a two-operand instruction (v_xor_b32)
+ *   valu_vop3_ops   int32 lane-ops/s of a three-operand one (v_alignbit_b32)
+ *   lds_read_bytes  LDS bytes/s of 16-byte reads without bank conflicts
+ *   lds_atomic_ops  lane-ops/s of ds_and_b32 without bank conflicts
+ *   hbm_copy_bytes  HBM bytes/s (read plus write) of a 256 MiB device copy
+ * Allocates 512 MiB of device memory for the call (GB_ENOMEM if that exceeds
+ * prm.mem_budget); GB_EDEVICE on a HIP error. */
+typedef struct gb_peaks {
+    double valu_vop2_ops;
+    double valu_vop3_ops;
+    double lds_read_bytes;
+    double lds_atomic_ops;
+    double hbm_copy_bytes;
+} gb_peaks;
+
+gb_status gb_measure_peaks(gb_ctx *ctx, gb_peaks *out, void *stream);
+
 /* The (n, p) pairs the last range or window call sent to the exhaustive
  * phase (p = 0 for a failure), at most cap of them, into host arrays;
  * *count receives the total number. */

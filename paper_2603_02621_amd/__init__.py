@@ -9,8 +9,8 @@ from __future__ import annotations
 
 import ctypes
 
-from ._binding import (HIST_BINS, MAX_N, GoldbachError, Params, PcResult, Result, Summary,
-                       Window, lib)
+from ._binding import (HIST_BINS, MAX_N, GoldbachError, Params, PcResult, Peaks, Result,
+                       Summary, Window, lib)
 
 __all__ = ["Verifier", "GoldbachError", "HIST_BINS", "MAX_N"]
 
@@ -139,6 +139,12 @@ class Verifier:
         out = r.summary()
         out.update(device_ms=float(r.device_ms), kernel_ms=float(r.kernel_ms))
         return out
+
+    def measure_peaks(self, stream=None):
+        """Measured device throughput ceilings (see gb_measure_peaks)."""
+        r = Peaks()
+        self._check(self._lib.gb_measure_peaks(self._h, ctypes.byref(r), _stream_ptr(stream)))
+        return r.as_dict()
 
     def verify_windows(self, windows, pmin=None, sums=True, hist=True, stream=None,
                        allow_unresolved=False):

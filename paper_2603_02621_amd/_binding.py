@@ -76,6 +76,14 @@ class PcResult(ctypes.Structure):
         return {k: int(getattr(self, k)) for k in self.SUMMARY}
 
 
+class Peaks(ctypes.Structure):
+    _fields_ = [(k, dbl) for k in ("valu_vop2_ops", "valu_vop3_ops", "lds_read_bytes",
+                                   "lds_atomic_ops", "hbm_copy_bytes")]
+
+    def as_dict(self):
+        return {name: float(getattr(self, name)) for name, _ in self._fields_}
+
+
 class ServerStats(ctypes.Structure):
     _fields_ = [(k, u64) for k in ("submitted", "completed", "rejected", "queued", "inflight",
                                    "bytes_inflight", "peak_bytes_inflight", "launches",
@@ -99,6 +107,7 @@ SIGNATURES = {
     "gb_verify_many": ([vp, vp, vp, ctypes.c_size_t, ctypes.c_int, vp], i32),
     "gb_sieve_window": ([vp, u64, u64, vp, vp], i32),
     "gb_partition_counts": ([vp, u64, u64, vp, ctypes.POINTER(PcResult), vp], i32),
+    "gb_measure_peaks": ([vp, ctypes.POINTER(Peaks), vp], i32),
     "gb_exhaustive_list": ([vp, vp, vp, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)], i32),
     "gb_autotune": ([vp, ctypes.POINTER(Window), ctypes.c_size_t, ctypes.c_char_p,
                      ctypes.POINTER(Params)], i32),

@@ -60,7 +60,8 @@ def test_struct_layout_matches_the_c_compiler(tmp_path):
     from paper_2603_02621_amd import _binding as B
     structs = {"gb_params": B.Params, "gb_result": B.Result, "gb_window": B.Window,
                "gb_summary": B.Summary, "gb_request": B.Request, "gb_completion": B.Completion,
-               "gb_server_stats": B.ServerStats, "gb_pc_result": B.PcResult}
+               "gb_server_stats": B.ServerStats, "gb_pc_result": B.PcResult,
+               "gb_peaks": B.Peaks}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "goldbach.h"', "int main(void){"]
     for cname, py in structs.items():
         lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')

@@ -105,3 +105,4 @@ def test_bench_size_sampled(V, orc):
                    "kernel_ms": got["kernel_ms"]}
     # every n in this range has a partition
     assert got["min_c"] > 0
+

@@ -191,6 +191,21 @@ gb_status gb_verify_windows(gb_ctx *ctx, const gb_window *w, size_t k,
  * p_min(n), or 0 with GB_EUNRESOLVED if none exists within the budget. */
 gb_status gb_verify_one(gb_ctx *ctx, uint64_t n, uint64_t *p, void *stream);
 
+/* Even n beyond 64 bits (section "Arbitrary Precision Checker": small
+ * primes p in ascending order, q = n - p tested with Miller-Rabin), for
+ * 2^64 <= n < 2^(32 nlimbs), nlimbs <= 32 (n below 2^1024).  n holds k
+ * numbers of nlimbs little-endian 32-bit limbs each (host memory); p (host,
+ * k entries) receives for each the smallest odd prime p from the resident
+ * table whose q passes the strong probable-prime test to each of the 25
+ * prime bases 2..97.  Every smaller p's q failed one of those bases and is
+ * certainly composite; the returned q is a probable prime (the first 12
+ * bases alone are deterministic below 3.3e24).  One wavefront per n.
+ * Status: GB_EINVAL for an odd n, an n below 2^64, nlimbs outside 3..32 or
+ * more than 2^24 n; GB_EUNRESOLVED (entry 0) if no prime of the table
+ * works; GB_EDEVICE on a HIP error. */
+gb_status gb_verify_big(gb_ctx *ctx, const uint32_t *n, uint32_t nlimbs, size_t k,
+                        uint64_t *p, void *stream);
+
 /* Many single n in one launch (one wavefront per n).  n and p are arrays of
  * k uint64 entries, both in device memory when on_device is 1, else both in
  * host memory.  Entries with no partition within the budget get 0 and the

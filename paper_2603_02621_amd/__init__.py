@@ -140,6 +140,28 @@ class Verifier:
         out.update(device_ms=float(r.device_ms), kernel_ms=float(r.kernel_ms))
         return out
 
+    def verify_big(self, ns, stream=None, allow_unresolved=False):
+        """Minimal p (25-base probable-prime q) of each even n with
+        2^64 <= n < 2^1024 (Python integers).  Returns a list of ints (0 for
+        none in the prime table)."""
+        import numpy as np
+        ns = [int(x) for x in ns]
+        if not ns:
+            return []
+        bits = max(x.bit_length() for x in ns)
+        nl = max(3, (bits + 31) // 32)
+        if nl > 32:
+            raise ValueError("n must be below 2^1024")
+        words = np.zeros((len(ns), nl), dtype=np.uint32)
+        for i, x in enumerate(ns):
+            for j in range(nl):
+                words[i, j] = (x >> (32 * j)) & 0xFFFFFFFF
+        out = np.zeros(len(ns), dtype=np.uint64)
+        st = self._lib.gb_verify_big(self._h, words.ctypes.data, nl, len(ns), out.ctypes.data,
+                                     _stream_ptr(stream))
+        self._check(st, allow=(5,) if allow_unresolved else ())
+        return [int(x) for x in out]
+
     def measure_peaks(self, stream=None):
         """Measured device throughput ceilings (see gb_measure_peaks)."""
         r = Peaks()

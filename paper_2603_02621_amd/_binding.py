@@ -108,6 +108,7 @@ SIGNATURES = {
     "gb_sieve_window": ([vp, u64, u64, vp, vp], i32),
     "gb_partition_counts": ([vp, u64, u64, vp, ctypes.POINTER(PcResult), vp], i32),
     "gb_measure_peaks": ([vp, ctypes.POINTER(Peaks), vp], i32),
+    "gb_verify_big": ([vp, vp, u32, ctypes.c_size_t, vp, vp], i32),
     "gb_exhaustive_list": ([vp, vp, vp, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)], i32),
     "gb_autotune": ([vp, ctypes.POINTER(Window), ctypes.c_size_t, ctypes.c_char_p,
                      ctypes.POINTER(Params)], i32),

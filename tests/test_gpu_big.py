@@ -1,0 +1,55 @@
+"""Minimal Goldbach prime of even n beyond 64 bits on the GPU against the
+big-n oracle (GPU): the paper's Table 5 values, random n in every limb-count
+class (up to 1020 bits), n just above 2^64, a batch, and the argument checks."""
+import random
+
+import pytest
+
+from oracle import big
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def V():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2603_02621_amd import Verifier
+    v = Verifier(0)
+    yield v
+    v.close()
+
+
+def test_table5(V):
+    assert V.verify_big([10**50, 10**100]) == [383, 797]
+
+
+@pytest.mark.parametrize("bits", [65, 96, 127, 128, 200, 256, 333, 500, 512, 700, 1020])
+def test_random_vs_oracle(V, bits):
+    rng = random.Random(bits)
+    ns = [2 * rng.getrandbits(bits - 1) | (1 << (bits - 1)) for _ in range(6)]
+    ns = [n - (n & 1) for n in ns]
+    assert V.verify_big(ns) == [big.pmin_big(n) for n in ns]
+
+
+def test_just_above_2p64(V):
+    ns = [2**64, 2**64 + 2, 2**64 + 10**6, 2**96 - 2, 2**128 - 2]
+    assert V.verify_big(ns) == [big.pmin_big(n) for n in ns]
+
+
+def test_batch(V):
+    ns = [10**30 + 2 * i for i in range(300)]
+    assert V.verify_big(ns) == [big.pmin_big(n) for n in ns]
+
+
+def test_argument_checks(V):
+    from paper_2603_02621_amd import GoldbachError
+    with pytest.raises(GoldbachError):
+        V.verify_big([10**30 + 1])           # odd
+    with pytest.raises(GoldbachError):
+        V.verify_big([2**64 - 2])            # below 2^64
+    with pytest.raises(ValueError):
+        V.verify_big([2**1024])              # beyond 1024 bits
+    assert V.verify_big([]) == []

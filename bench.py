@@ -35,6 +35,7 @@ ALG_OPS_PER_N = CLEARS_PER_N * 3 + PROBES_PER_N * 7 + 5 / 32
 # 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz, one 32-bit integer op per lane-cycle
 ALU_PEAK_OPS = 256 * 64 * 2.4e9
 PC_N, PC_HI = 1 << 16, 10**9        # partition-count workload: 2^16 even n ending at 1e9
+BIG_N = 4096                        # beyond-64-bit workload: even n from 10^100 upward
 
 # HBM bytes per launch of the tile kernel on this workload, from rocprofv3
 # FETCH_SIZE and WRITE_SIZE scaled by a 1 GiB copy's readings (factors 2.000
@@ -77,6 +78,7 @@ def main():
     ap.add_argument("--params", default="", help="JSON object of gb_params fields overriding the tuned ones")
     ap.add_argument("--no-bulk", action="store_true", help="skip the bulk-verification line")
     ap.add_argument("--no-pcount", action="store_true", help="skip the partition-count line")
+    ap.add_argument("--no-big", action="store_true", help="skip the beyond-64-bit line")
     ap.add_argument("--copy-calibrate", type=int, default=0, metavar="MIB",
                     help="also run one device-to-device copy of this many MiB (a reference "
                          "kernel of known traffic for the HBM byte counters)")
@@ -206,6 +208,32 @@ def main():
                                "kernel": "k_pcount", "alg_ops": "2 per 32 candidate pairs",
                                "alg_ops_per_launch": 2 * words}}
 
+    # ---- even n beyond 64 bits: 4096 n from 10^100 upward ----------------
+    bign = None
+    if not args.no_big:
+        ns = [10**100 + 2 * i for i in range(BIG_N)]
+        v.verify_big(ns[:64])                         # code and tables warm
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ps = v.verify_big(ns)
+        big_wall = time.perf_counter() - t0
+        # algorithmic work: for each n, a base-2 strong test of n - p for every
+        # odd prime p up to p_min and 24 more for p_min's q; a test of a b-bit q
+        # is b - 1 squarings and about b/2 multiplications, each 2 k^2 32-bit
+        # multiply-adds with k = ceil(b / 32)
+        import bisect
+        primes_small = [q for q in range(3, max(ps) + 1, 2) if all(q % d for d in range(3, int(q**0.5) + 1, 2))]
+        mads = 0
+        for n, pm in zip(ns, ps):
+            b = n.bit_length()
+            k = (b + 31) // 32
+            per_test = 1.5 * (b - 1) * 2 * k * k
+            mads += (bisect.bisect_right(primes_small, pm) + 24) * per_test
+        print(f"# big n: {1e3*big_wall:.1f} ms for {BIG_N} n near 1e100", file=sys.stderr, flush=True)
+        bign = {"workload": f"minimal p of the {BIG_N} even n from 10^100 upward (333 bits)",
+                "value": BIG_N / big_wall, "unit": "even n/s", "ms_per_step": 1e3 * big_wall,
+                "max_p": max(ps), "alg_mads": mads, "alg_mads_per_s": mads / big_wall}
+
     # ---- measured ceilings of the units (beside the nominal peaks) --------
     peaks = v.measure_peaks()
 
@@ -233,6 +261,8 @@ def main():
             "alg_ops_per_n": round(ALG_OPS_PER_N, 3),
             "frac_of_measured": {"valu_vop2": achieved / peaks["valu_vop2_ops"],
                                  "valu_vop3": achieved / peaks["valu_vop3_ops"]}}
+    if bign is not None:
+        bign["frac_of_measured_valu_vop3"] = bign["alg_mads_per_s"] / peaks["valu_vop3_ops"]
     if pcount is not None:
         pcount["roofline"]["frac_of_measured"] = {
             "valu_vop2": pc_ach / peaks["valu_vop2_ops"], "valu_vop3": pc_ach / peaks["valu_vop3_ops"]}
@@ -250,6 +280,7 @@ def main():
         "batched_windows": windows,
         "bulk_verify": bulk,
         "partition_counts": pcount,
+        "big_n": bign,
         "summary": {k: ref[k] for k in ("count", "max_p", "argmax_n", "checksum",
                                         "n_exhaustive", "n_failed")},
         "roofline": roof,

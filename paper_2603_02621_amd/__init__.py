@@ -152,10 +152,8 @@ class Verifier:
         nl = max(3, (bits + 31) // 32)
         if nl > 32:
             raise ValueError("n must be below 2^1024")
-        words = np.zeros((len(ns), nl), dtype=np.uint32)
-        for i, x in enumerate(ns):
-            for j in range(nl):
-                words[i, j] = (x >> (32 * j)) & 0xFFFFFFFF
+        words = np.frombuffer(b"".join(x.to_bytes(4 * nl, "little") for x in ns),
+                              dtype="<u4").reshape(len(ns), nl).copy()
         out = np.zeros(len(ns), dtype=np.uint64)
         st = self._lib.gb_verify_big(self._h, words.ctypes.data, nl, len(ns), out.ctypes.data,
                                      _stream_ptr(stream))

@@ -80,8 +80,8 @@ gb_status gb_verify_big(gb_ctx *c, const uint32_t *n, uint32_t nlimbs, size_t k,
     if (nlimbs < 3 || nlimbs > 32) return fail(c, GB_EINVAL, "nlimbs must be in 3..32");
     if (k == 0) return GB_OK;
     if (k > (1ull << 24)) return fail(c, GB_EINVAL, "at most 2^24 n per call");
-    int K = 4;
-    while (K < (int)nlimbs) K *= 2;
+    // limb counts compiled: 4, 8, 12, 16, 24, 32
+    const int K = nlimbs <= 4 ? 4 : nlimbs <= 8 ? 8 : nlimbs <= 12 ? 12 : nlimbs <= 16 ? 16 : nlimbs <= 24 ? 24 : 32;
     // every n even and at least 2^64
     for (size_t i = 0; i < k; ++i) {
         const uint32_t *w = n + i * nlimbs;
@@ -103,7 +103,9 @@ gb_status gb_verify_big(gb_ctx *c, const uint32_t *n, uint32_t nlimbs, size_t k,
         switch (K) {
         case 4: e = launch_big<4>(dn, k, c->d_primes, c->ntab, dp, st); break;
         case 8: e = launch_big<8>(dn, k, c->d_primes, c->ntab, dp, st); break;
+        case 12: e = launch_big<12>(dn, k, c->d_primes, c->ntab, dp, st); break;
         case 16: e = launch_big<16>(dn, k, c->d_primes, c->ntab, dp, st); break;
+        case 24: e = launch_big<24>(dn, k, c->d_primes, c->ntab, dp, st); break;
         default: e = launch_big<32>(dn, k, c->d_primes, c->ntab, dp, st); break;
         }
     }

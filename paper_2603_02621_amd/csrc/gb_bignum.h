@@ -74,11 +74,15 @@ template <int K> __host__ __device__ inline void add_mod(Num<K> &a, const Num<K>
 template <int K>
 __host__ __device__ inline void mont_mul(Num<K> &r, const Num<K> &a, const Num<K> &b, const Num<K> &m, uint32_t ninv)
 {
+    // fully unrolled, so that every limb stays in a register
     uint32_t t[K + 2];
+#pragma unroll
     for (int i = 0; i < K + 2; ++i) t[i] = 0;
+#pragma unroll
     for (int i = 0; i < K; ++i) {
         uint64_t c = 0;
         const uint32_t bi = b.w[i];
+#pragma unroll
         for (int j = 0; j < K; ++j) {
             c = (uint64_t)a.w[j] * bi + t[j] + (c >> 32);
             t[j] = (uint32_t)c;
@@ -88,6 +92,7 @@ __host__ __device__ inline void mont_mul(Num<K> &r, const Num<K> &a, const Num<K
         t[K + 1] = (uint32_t)(c >> 32);
         const uint32_t q = t[0] * ninv;
         c = (uint64_t)q * m.w[0] + t[0];
+#pragma unroll
         for (int j = 1; j < K; ++j) {
             c = (uint64_t)q * m.w[j] + t[j] + (c >> 32);
             t[j - 1] = (uint32_t)c;
@@ -115,24 +120,32 @@ template <int K> __host__ __device__ inline int bit_length(const Num<K> &a)
     return 0;
 }
 
+// Limb j of a for a j known only at run time, by a chain of selects (an
+// indexed read would move the number out of registers).
+template <int K> __host__ __device__ inline uint32_t limb_at(const Num<K> &a, int j)
+{
+    uint32_t r = 0;
+#pragma unroll
+    for (int i = 0; i < K; ++i) r = (i == j) ? a.w[i] : r;
+    return r;
+}
+
 template <int K> __host__ __device__ inline uint32_t bit(const Num<K> &a, int i)
 {
-    return (a.w[i >> 5] >> (i & 31)) & 1u;
+    return (limb_at(a, i >> 5) >> (i & 31)) & 1u;
 }
 
 // Strong probable prime to base a (2 <= a < q), q odd, q < R = 2^(32K):
 // with q - 1 = d 2^s (d odd), a^d = 1 or a^(d 2^r) = -1 mod q for an r < s.
-// Exponentiation in Montgomery form, left to right, with one Montgomery
-// product per step (a squaring, or a multiplication by aR when the
-// exponent bit is set), so the product is inlined once.
+// Exponentiation in Montgomery form, left to right.
 template <int K> __host__ __device__ inline bool strong_prp(const Num<K> &q, uint32_t a)
 {
     const uint32_t ninv = neg_inv32(q.w[0]);
     const int nb = bit_length(q);
     // one = R mod q: 2^(nb-1) < q doubled 32K - nb + 1 times
     Num<K> one;
-    for (int i = 0; i < K; ++i) one.w[i] = 0;
-    one.w[(nb - 1) >> 5] = 1u << ((nb - 1) & 31);
+#pragma unroll
+    for (int i = 0; i < K; ++i) one.w[i] = (i == ((nb - 1) >> 5)) ? 1u << ((nb - 1) & 31) : 0u;
     for (int i = nb - 1; i < 32 * K; ++i) dbl_mod(one, q);
     // am = a R mod q (a < 2^7 in use; any 32-bit a works), by doubling and adding
     Num<K> am;
@@ -149,28 +162,39 @@ template <int K> __host__ __device__ inline bool strong_prp(const Num<K> &q, uin
     while (bit(q, s) == 0u) ++s;
     const int db = nb - s;            // bit length of d
     // x = a^d: start from the top bit of d (= aR), then for bits db-2 .. 0
-    // one squaring each and one multiplication for each set bit
+    // one squaring each and one multiplication for each set bit; then up to
+    // s - 1 more squarings.  One Montgomery product per step, with its second
+    // operand selected, so the product is inlined once.
     Num<K> x = am;
     int i = db - 2;
     bool mul_next = false;
-    while (i >= 0 || mul_next) {
-        if (mul_next) {
-            mont_mul(x, x, am, q, ninv);
-            mul_next = false;
-            --i;
-        } else {
-            mont_mul(x, x, x, q, ninv);
-            if (bit(q, i + s)) mul_next = true;
-            else --i;
+    int r = 0;                        // squarings after the exponentiation
+    for (;;) {
+        const bool expo = i >= 0 || mul_next;
+        if (!expo) {
+            if (r == 0) {
+                if (equal(x, one) || equal(x, mone)) return true;
+            } else {
+                if (equal(x, mone)) return true;
+                if (equal(x, one)) return false;
+            }
+            if (++r >= s) return false;
+        }
+        Num<K> y;
+#pragma unroll
+        for (int j = 0; j < K; ++j) y.w[j] = mul_next ? am.w[j] : x.w[j];
+        mont_mul(x, x, y, q, ninv);
+        if (expo) {
+            if (mul_next) {
+                mul_next = false;
+                --i;
+            } else if (bit(q, i + s)) {
+                mul_next = true;
+            } else {
+                --i;
+            }
         }
     }
-    if (equal(x, one) || equal(x, mone)) return true;
-    for (int r = 1; r < s; ++r) {
-        mont_mul(x, x, x, q, ninv);
-        if (equal(x, mone)) return true;
-        if (equal(x, one)) return false;
-    }
-    return false;
 }
 
 }  // namespace gbbig

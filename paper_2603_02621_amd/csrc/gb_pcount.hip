@@ -5,14 +5,14 @@
 // With m = n/2 - 1 and bit i of the bitset B standing for 2i + 1, the odd
 // partitions of n >= 6 are the pairs (i, m - i) with B[i] = B[m - i] = 1 and
 // i <= m/2, so c(n) = sum over i <= floor(m/2) of B[i] B[m - i].  A lane
-// owns one n; a workgroup of 512 lanes owns 512 consecutive n and walks i in
-// steps of 32: the word X = B[32a .. 32a + 31] is the same for every lane,
-// and a lane's partner bits B[m - 32a - t], t = 0..31, are 32 consecutive
-// bits of the bit-reversed bitset.  The workgroup stages both in LDS a chunk
-// of steps at a time (the q side reversed once per word), after which a step
-// is one funnel shift, one AND and one popcount-accumulate per lane.  The
-// range of steps of a block is split over several workgroups, which add
-// their partial counts with 64-bit atomics.
+// owns one n and walks i in steps of 32: the word B[32a .. 32a + 31] is the
+// same for every lane, and a lane's partner bits B[m - 32a - t], t = 0..31,
+// are 32 consecutive bits of the bit-reversed bitset.  Lanes are laid out so
+// that all lanes of a wave share those bits' offset within a word (one
+// residue of m mod 32 per wave); each wave then stages its partner words
+// shifted and reversed once per chunk of steps, and a step is one AND and
+// one popcount-accumulate per lane.  The steps of a block are split over
+// several workgroups, which add their partial counts with 64-bit atomics.
 #include <algorithm>
 #include <cstring>
 
@@ -20,21 +20,12 @@
 
 namespace {
 
-constexpr uint32_t PC_NT = 512;    // consecutive n (lanes) per workgroup
-constexpr uint32_t PC_C = 2048;    // steps of 32 values of i per staged chunk
-constexpr uint32_t PC_R = PC_C + PC_NT / 32 + 8;  // staged words of the q side
-
 typedef uint32_t pc_v4 __attribute__((ext_vector_type(4)));
-
-struct PcArgs {
-    const uint32_t *bits;          // odd-number bitset, bit i <-> 2i + 1
-    uint64_t nwords;               // its length in 32-bit words
-    uint64_t m_first;              // m = n/2 - 1 of the first n >= 6
-    uint64_t nm;                   // number of n >= 6
-    unsigned long long *counts;    // count of m_first + j at index out_off + j
-    uint64_t out_off;
-    uint32_t nsplit;               // workgroups per block of PC_NT n
-};
+typedef uint32_t pc_v16 __attribute__((ext_vector_type(16)));
+// the p-side words are the same for every lane: read through the constant
+// address space, they arrive in scalar registers, 16 per load
+typedef __attribute__((address_space(4))) const pc_v16 const_v16;
+typedef __attribute__((address_space(4))) const uint32_t const_u32;
 
 __device__ __forceinline__ uint32_t funnel(uint32_t hi, uint32_t lo, uint32_t s)
 {
@@ -50,82 +41,102 @@ __device__ __forceinline__ uint32_t popc_acc(uint32_t x, uint32_t acc)
     return d;
 }
 
-__global__ __launch_bounds__(PC_NT) void k_pcount(PcArgs a)
+// A block of 2048 consecutive m (m0 a multiple of 32) is covered by 4
+// workgroups of 8 waves,
+// wave w of group g taking the residue r = 8g + w and lane l the
+// m = m0 + 32l + r.  All lanes of a wave then share the partner window's bit
+// shift (r + 1) mod 32, so the wave builds its shifted, bit-reversed partner
+// words once per chunk and a lane reads one of them per step: a step is one
+// AND and one popcount-accumulate (no funnel shift per step).
+constexpr uint32_t PR_NT = 512;              // 8 waves = 8 residues
+constexpr uint32_t PR_BM = 2048;             // m per block (64 lanes x 32 residues)
+constexpr uint32_t PR_C = 1024;              // steps per staged chunk
+constexpr uint32_t PR_S = PR_C + 64;         // shifted partner words per wave
+constexpr uint32_t PR_B = PR_C + 72;         // staged bitset words per workgroup
+
+struct PcResArgs {
+    const uint32_t *bits;
+    uint64_t nwords;
+    uint64_t m_first, m_last;      // the m = n/2 - 1 of the first and last n >= 6
+    uint64_t m_base;               // m_first rounded down to a multiple of 32
+    unsigned long long *counts;    // count of m at index out_off + (m - m_first)
+    uint64_t out_off;
+    uint32_t nsplit;
+};
+
+__global__ __launch_bounds__(PR_NT) void k_pcount_res(PcResArgs a)
 {
-    __shared__ __align__(16) uint32_t xs[PC_C + 4];
-    __shared__ uint32_t rs[PC_R];
-    const uint32_t tid = threadIdx.x;
-    const uint64_t blk = blockIdx.x / a.nsplit;
+    __shared__ uint32_t bs[PR_B];
+    __shared__ uint32_t sw[PR_NT / 64][PR_S];
+    const uint32_t tid = threadIdx.x, wave = tid >> 6, lane = tid & 63u;
     const uint32_t part = blockIdx.x % a.nsplit;
-    const uint64_t m0 = a.m_first + blk * PC_NT;
-    const uint64_t mend = a.m_first + a.nm;
-    const uint64_t mlast = (m0 + PC_NT < mend ? m0 + PC_NT : mend) - 1;
-    const uint64_t m = m0 + tid;
-    const uint64_t lim = m / 2;                       // i <= floor(m/2)
-    // steps a = 0 .. amax cover i up to the block's largest floor(m/2); below
-    // afull every i of the step is within every lane's bound
-    const uint64_t amax = (mlast / 2) >> 5;
-    const uint64_t afull = (m0 / 2) >> 5;
+    const uint64_t grp = blockIdx.x / a.nsplit;       // block * 4 + residue group
+    const uint64_t blk = grp >> 2;
+    const uint32_t r = 8u * (uint32_t)(grp & 3u) + wave;
+    const uint64_t m0 = a.m_base + blk * PR_BM;
+    const uint64_t m = m0 + 32u * lane + r;
+    const bool valid = m >= a.m_first && m <= a.m_last;
+    const uint64_t lim = m / 2;
+    // the block's valid m and its steps
+    const uint64_t mlo = m0 > a.m_first ? m0 : a.m_first;
+    const uint64_t mhi = m0 + PR_BM - 1 < a.m_last ? m0 + PR_BM - 1 : a.m_last;
+    const uint64_t amax = (mhi / 2) >> 5;
+    const uint64_t afull = (mlo / 2) >> 5;
     const uint64_t per = (amax + a.nsplit) / a.nsplit;
     const uint64_t ab = (uint64_t)part * per;
     const uint64_t ae = ab + per < amax + 1 ? ab + per : amax + 1;
-    // bit offset of the lane's partner window within a staged word pair
-    const uint32_t sh = (uint32_t)((31u - (uint32_t)m) & 31u);
+    // the wave's partner windows start at bit m0 + r - 31 + 32 (l - a): word
+    // m0/32 - 1 + delta + (l - a), bit offset (r + 1) mod 32
+    const uint32_t sh = (r + 1u) & 31u;
+    const uint32_t delta = r == 31u ? 1u : 0u;
     uint32_t acc = 0;
 
-    for (uint64_t a0 = ab; a0 < ae; a0 += PC_C) {
-        const uint32_t ns = ae - a0 < PC_C ? (uint32_t)(ae - a0) : PC_C;
-        // The q side of step a for lane l spans bits m_l - 32a - 31 .. m_l - 32a
-        // of B: over the chunk and the block, words maxw down to maxw - K + 1.
-        // rs[k] holds word maxw - k bit-reversed (zero outside the bitset), so
-        // B bit x sits at rs position 32 maxw + 31 - x, and the 32 partner bits
-        // of a step are rs positions u .. u + 31, u = 32 maxw + 31 - m + 32a.
-        const uint64_t maxw = (m0 + PC_NT - 1 - 32 * a0) >> 5;
-        const uint32_t K = ns + PC_NT / 32 + 6;
-        __syncthreads();                                // the previous chunk is done
-        for (uint32_t k = tid; k < K; k += PC_NT) {
-            const uint64_t w = maxw - k;                 // wraps below zero
-            rs[k] = __builtin_bitreverse32(w < a.nwords ? a.bits[w] : 0u);
-        }
-        for (uint32_t k = tid; k < ((ns + 3u) & ~3u); k += PC_NT)
-            xs[k] = (k < ns && a0 + k < a.nwords) ? a.bits[a0 + k] : 0u;
+    for (uint64_t a0 = ab; a0 < ae; a0 += PR_C) {
+        const uint32_t ns = ae - a0 < PR_C ? (uint32_t)(ae - a0) : PR_C;
+        // bitset words m0/32 - 1 - (a0 + ns - 1) + k, k < ns + 66 (zero
+        // outside the bitset), and the p-side words a0 .. a0 + ns - 1
+        const uint64_t wlo = m0 / 32 - 1 - (a0 + ns - 1);   // wraps below zero
         __syncthreads();
-
-        const uint64_t u0 = 32 * maxw + 31 - m + 32 * a0;   // >= 0: m <= m0 + PC_NT - 1
-        const uint32_t *rp = rs + (uint32_t)(u0 >> 5);
-        uint32_t lo = rp[0];
+        for (uint32_t k = tid; k < ns + 66u; k += PR_NT) {
+            const uint64_t w = wlo + k;
+            bs[k] = w < a.nwords ? a.bits[w] : 0u;
+        }
+        __syncthreads();
+        // p side: words a0 .. a0 + ns - 1 of the bitset (a0 + ns - 1 <= amax
+        // < nwords: the bitset reaches the largest q >= the largest p)
+        const_u32 *xg = reinterpret_cast<const_u32 *>(reinterpret_cast<uintptr_t>(a.bits + a0));
+        // this wave's shifted, bit-reversed partner words, in the order the
+        // steps read them: the window of (l - a) with a = a0 + s is word
+        // j = l - s + ns - 1 of the staged bits (bs[j + delta], bs[j + delta
+        // + 1]), stored at sw[wave][ns + 62 - j], so lane l at step s reads
+        // sw[wave][63 - l + s]
+        for (uint32_t k = lane; k < ns + 63u; k += 64u) {
+            const uint32_t j = ns + 62u - k;
+            sw[wave][k] = __builtin_bitreverse32(funnel(bs[j + delta + 1u], bs[j + delta], sh));
+        }
+        __syncthreads();
+        const uint32_t *sp = sw[wave] + 63u - lane;   // step s reads sp[s]
         uint32_t s = 0;
         const uint32_t nfull = afull <= a0 ? 0u : (afull - a0 < ns ? (uint32_t)(afull - a0) : ns);
-        // two running counts, so that consecutive popcounts do not wait on
-        // each other
         uint32_t acc2 = 0;
-        for (; s + 8 <= nfull; s += 8) {
-            const pc_v4 x = *reinterpret_cast<const pc_v4 *>(xs + s);
-            const pc_v4 y = *reinterpret_cast<const pc_v4 *>(xs + s + 4);
-            const uint32_t w1 = rp[s + 1], w2 = rp[s + 2], w3 = rp[s + 3], w4 = rp[s + 4];
-            const uint32_t w5 = rp[s + 5], w6 = rp[s + 6], w7 = rp[s + 7], w8 = rp[s + 8];
-            acc = popc_acc(funnel(w1, lo, sh) & x.x, acc);
-            acc2 = popc_acc(funnel(w2, w1, sh) & x.y, acc2);
-            acc = popc_acc(funnel(w3, w2, sh) & x.z, acc);
-            acc2 = popc_acc(funnel(w4, w3, sh) & x.w, acc2);
-            acc = popc_acc(funnel(w5, w4, sh) & y.x, acc);
-            acc2 = popc_acc(funnel(w6, w5, sh) & y.y, acc2);
-            acc = popc_acc(funnel(w7, w6, sh) & y.z, acc);
-            acc2 = popc_acc(funnel(w8, w7, sh) & y.w, acc2);
-            lo = w8;
+        for (; s + 16 <= nfull; s += 16) {
+            const pc_v16 x = *reinterpret_cast<const_v16 *>(xg + s);
+            const uint32_t *q = sp + s;
+#pragma unroll
+            for (int t = 0; t < 16; t += 2) {
+                acc = popc_acc(q[t] & x[t], acc);
+                acc2 = popc_acc(q[t + 1] & x[t + 1], acc2);
+            }
         }
         acc += acc2;
         for (; s < ns; ++s) {
-            const uint32_t hi = rp[s + 1];
-            uint32_t v = funnel(hi, lo, sh) & xs[s];
-            // i = 32(a0 + s) + t must not exceed floor(m/2)
+            uint32_t v = sp[s] & xg[s];
             const int64_t rem = (int64_t)lim - 32 * (int64_t)(a0 + s);
             v &= rem >= 31 ? ~0u : (rem < 0 ? 0u : (2u << (uint32_t)rem) - 1u);
             acc += __popc(v);
-            lo = hi;
         }
     }
-    if (m <= mlast && acc) atomicAdd(&a.counts[a.out_off + (m - a.m_first)], (unsigned long long)acc);
+    if (valid && acc) atomicAdd(&a.counts[a.out_off + (m - a.m_first)], (unsigned long long)acc);
 }
 
 // counts[0..n) = 0 (1 at index 0 when the range starts at n = 4); the
@@ -211,21 +222,22 @@ gb_status gb_partition_counts(gb_ctx *c, uint64_t lo, uint64_t hi, uint64_t *cou
     if (any6) {
         gb_status stt = enqueue_sieve(c, ws, 1, nbits, ws.pc_bits.p, st);
         if (stt != GB_OK) return stt;
-        PcArgs a{};
+        PcResArgs a{};
         a.bits = ws.pc_bits.p;
         a.nwords = nbits / 32;
         a.m_first = n6 / 2 - 1;
-        a.nm = (n_last - n6) / 2 + 1;
+        a.m_last = n_last / 2 - 1;
+        a.m_base = a.m_first & ~31ull;
         a.counts = out;
         a.out_off = (n6 - n_first) / 2;
-        const uint64_t nblk = (a.nm + PC_NT - 1) / PC_NT;
-        const uint64_t steps = ((a.m_first + a.nm - 1) / 2 >> 5) + 1;   // of the last block, the most
+        const uint64_t ngrp = 4 * ((a.m_last + 1 - a.m_base + PR_BM - 1) / PR_BM);
+        const uint64_t steps = ((a.m_last / 2) >> 5) + 1;   // of the last block, the most
         // enough workgroups to fill the chip several times over, but at least
         // one chunk of steps each
-        const uint64_t want = (8ull * (uint64_t)c->num_cu + nblk - 1) / nblk;
-        a.nsplit = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(want, steps / PC_C));
+        const uint64_t want = (8ull * (uint64_t)c->num_cu + ngrp - 1) / ngrp;
+        a.nsplit = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(want, steps / PR_C));
         GB_HIP(c, hipEventRecord(ws.evt0, st));
-        hipLaunchKernelGGL(k_pcount, dim3((uint32_t)(nblk * a.nsplit)), dim3(PC_NT), 0, st, a);
+        hipLaunchKernelGGL(k_pcount_res, dim3((uint32_t)(ngrp * a.nsplit)), dim3(PR_NT), 0, st, a);
         GB_HIP(c, hipGetLastError());
         GB_HIP(c, hipEventRecord(ws.evt1, st));
     }

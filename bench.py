@@ -205,7 +205,7 @@ def main():
                   "summary": {k: rp[k] for k in ("count", "sum", "min_c", "argmin_n", "max_c", "argmax_n")},
                   "roofline": {"bound": "alu", "achieved": pc_ach / 1e12, "peak": ALU_PEAK_OPS / 1e12,
                                "unit": "Tops/s (int32 lane ops)", "frac": pc_ach / ALU_PEAK_OPS,
-                               "kernel": "k_pcount", "alg_ops": "2 per 32 candidate pairs",
+                               "kernel": "k_pcount_res", "alg_ops": "2 per 32 candidate pairs",
                                "alg_ops_per_launch": 2 * words}}
 
     # ---- even n beyond 64 bits: 4096 n from 10^100 upward ----------------

@@ -94,26 +94,20 @@ gb_status gb_verify_big(gb_ctx *c, const uint32_t *n, uint32_t nlimbs, size_t k,
     // padded to K limbs per n
     std::vector<uint32_t> h((size_t)k * K, 0u);
     for (size_t i = 0; i < k; ++i) std::memcpy(&h[i * K], n + i * nlimbs, nlimbs * 4);
-    uint32_t *dn = nullptr;
-    unsigned long long *dp = nullptr;
-    GB_HIP(c, hipMalloc(&dn, h.size() * 4));
-    hipError_t e = hipMalloc(&dp, k * 8);
-    if (e == hipSuccess) e = hipMemcpyAsync(dn, h.data(), h.size() * 4, hipMemcpyHostToDevice, st);
-    if (e == hipSuccess) {
-        switch (K) {
-        case 4: e = launch_big<4>(dn, k, c->d_primes, c->ntab, dp, st); break;
-        case 8: e = launch_big<8>(dn, k, c->d_primes, c->ntab, dp, st); break;
-        case 12: e = launch_big<12>(dn, k, c->d_primes, c->ntab, dp, st); break;
-        case 16: e = launch_big<16>(dn, k, c->d_primes, c->ntab, dp, st); break;
-        case 24: e = launch_big<24>(dn, k, c->d_primes, c->ntab, dp, st); break;
-        default: e = launch_big<32>(dn, k, c->d_primes, c->ntab, dp, st); break;
-        }
+    Workspace &ws = c->ws;
+    GB_HIP(c, ws.big_n.ensure(h.size()));
+    GB_HIP(c, ws.big_p.ensure(k));
+    GB_HIP(c, hipMemcpyAsync(ws.big_n.p, h.data(), h.size() * 4, hipMemcpyHostToDevice, st));
+    switch (K) {
+    case 4: GB_HIP(c, launch_big<4>(ws.big_n.p, k, c->d_primes, c->ntab, ws.big_p.p, st)); break;
+    case 8: GB_HIP(c, launch_big<8>(ws.big_n.p, k, c->d_primes, c->ntab, ws.big_p.p, st)); break;
+    case 12: GB_HIP(c, launch_big<12>(ws.big_n.p, k, c->d_primes, c->ntab, ws.big_p.p, st)); break;
+    case 16: GB_HIP(c, launch_big<16>(ws.big_n.p, k, c->d_primes, c->ntab, ws.big_p.p, st)); break;
+    case 24: GB_HIP(c, launch_big<24>(ws.big_n.p, k, c->d_primes, c->ntab, ws.big_p.p, st)); break;
+    default: GB_HIP(c, launch_big<32>(ws.big_n.p, k, c->d_primes, c->ntab, ws.big_p.p, st)); break;
     }
-    if (e == hipSuccess) e = hipMemcpyAsync(p, dp, k * 8, hipMemcpyDeviceToHost, st);
-    if (e == hipSuccess) e = hipStreamSynchronize(st);
-    (void)hipFree(dn);
-    if (dp) (void)hipFree(dp);
-    if (e != hipSuccess) return fail(c, GB_EDEVICE, std::string("gb_verify_big: ") + hipGetErrorString(e));
+    GB_HIP(c, hipMemcpyAsync(p, ws.big_p.p, k * 8, hipMemcpyDeviceToHost, st));
+    GB_HIP(c, hipStreamSynchronize(st));
     for (size_t i = 0; i < k; ++i)
         if (p[i] == 0) return fail(c, GB_EUNRESOLVED, "no partition with p in the resident prime table");
     return GB_OK;

@@ -227,6 +227,8 @@ void Workspace::release()
     pc_counts.release();
     pc_red.release();
     h_pc_red.release();
+    big_n.release();
+    big_p.release();
     h_slots.release();
     h_hist.release();
     h_counters.release();

@@ -94,6 +94,8 @@ struct Workspace {
     DevBuf<unsigned long long> pc_counts;  // partition counts when the caller passes none
     DevBuf<unsigned long long> pc_red;   // partition counts: sum, min key, max key
     PinBuf<unsigned long long> h_pc_red;
+    DevBuf<uint32_t> big_n;              // beyond 64 bits: the n, K limbs each
+    DevBuf<unsigned long long> big_p;    // and their p
     PinBuf<GbSlot> h_slots;
     PinBuf<unsigned long long> h_hist;
     PinBuf<unsigned long long> h_counters;

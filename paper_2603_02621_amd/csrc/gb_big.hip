@@ -2,13 +2,19 @@
 // section "Arbitrary Precision Checker": small primes p in ascending order,
 // q = n - p tested with Miller-Rabin), up to n < 2^1024.
 //
-// One wavefront per n.  Lane l takes the l-th next odd prime p of the
-// resident table and runs the strong probable-prime test to base 2 on its
-// q = n - p (multi-limb Montgomery arithmetic, gb_bignum.h).  The lowest
-// passing lane's q is then tested to the other 24 prime bases 3 .. 97, one
-// base per lane; if all pass, that p is the answer (every smaller p failed a
-// base, so its q is composite); otherwise the next passing lane is tried,
-// then the next 64 primes.
+// Two kernels.  The search takes one wavefront per n.  The odd primes p of
+// the resident table are first filtered, 64 at a time, by the 24 odd prime
+// bases r = 3 .. 97: a q = n - p that r divides fails the strong test to
+// base r (a^d and its squarings mod q are then multiples of r, never 1 or
+// q - 1), so dropping p = n (mod r) leaves the answer unchanged; about a
+// quarter of the p survive.  Lane l then takes the l-th of the next 64
+// surviving p and runs the strong probable-prime test to base 2 on its q
+// (multi-limb Montgomery arithmetic, gb_bignum.h); the lowest passing lane
+// gives the candidate.  The confirmation then tests each candidate's q to
+// the other 24 bases, one (n, base) per lane.  A candidate that fails a base
+// (a strong pseudoprime to base 2) sends its n back to the search, which
+// resumes after it.  The answer is the first p whose q passes all 25 bases;
+// every smaller p failed one, so its q is composite.
 #include <cstring>
 
 #include "gb_bignum.h"
@@ -21,36 +27,186 @@ using gbbig::Num;
 __constant__ uint32_t kBigBases[25] = {2, 3, 5, 7, 11, 13, 17, 19, 23, 29, 31, 37, 41,
                                        43, 47, 53, 59, 61, 67, 71, 73, 79, 83, 89, 97};
 
-template <int K>
-__global__ __launch_bounds__(256) void k_big(const uint32_t *n_all, uint64_t k, const uint32_t *primes,
-                                             uint64_t nprimes, unsigned long long *p_out)
+constexpr uint32_t kOddBases[24] = {3, 5, 7, 11, 13, 17, 19, 23, 29, 31, 37, 41,
+                                     43, 47, 53, 59, 61, 67, 71, 73, 79, 83, 89, 97};
+
+// n mod r for a small r (r < 2^12), most significant limb first
+template <int K> __device__ __forceinline__ uint32_t mod_small(const Num<K> &n, uint32_t r)
 {
+    const uint32_t t = (uint32_t)((1ull << 32) % r);
+    uint32_t acc = 0;
+#pragma unroll
+    for (int i = K - 1; i >= 0; --i) acc = (acc * t + n.w[i] % r) % r;
+    return acc;
+}
+
+// pos[idx]: in, the table index to resume from; out, the table index of
+// the first surviving p at or after it whose q passes base 2, or nprimes.
+template <int K>
+__global__ __launch_bounds__(256) void k_big_search(const uint32_t *n_all, const uint32_t *list, uint32_t nlist,
+                                                    const uint32_t *primes, uint32_t nprimes, uint32_t *pos)
+{
+    __shared__ uint32_t cand_all[4][64];
     const uint32_t lane = threadIdx.x & 63u;
-    const uint64_t idx = (uint64_t)blockIdx.x * 4u + (threadIdx.x >> 6);
-    if (idx >= k) return;                            // whole wave
+    const uint32_t wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const uint32_t slot = blockIdx.x * 4u + wv;
+    if (slot >= nlist) return;                       // whole wave
+    const uint32_t idx = list ? list[slot] : slot;
+    uint32_t *cand = cand_all[wv];
     Num<K> n;
-    for (int i = 0; i < K; ++i) n.w[i] = n_all[idx * K + i];
-    for (uint64_t base = 0; base < nprimes; base += 64) {
-        const uint64_t c = base + lane;
-        const bool valid = c < nprimes;
-        const uint32_t p = valid ? primes[c] : 3u;
+#pragma unroll
+    for (int i = 0; i < K; ++i) n.w[i] = n_all[(uint64_t)idx * K + i];
+    // n mod r for the 24 odd bases (the same in every lane)
+    uint32_t nres[24];
+#pragma unroll
+    for (int j = 0; j < 24; ++j) nres[j] = mod_small(n, kOddBases[j]);
+    uint32_t next = pos[idx];                        // next table index to filter
+    for (;;) {
+        // the table indices of the next (up to) 64 surviving p, ascending
+        uint32_t cnt = 0;
+        while (cnt < 64u && next < nprimes) {
+            const uint32_t c = next + lane;
+            const bool valid = c < nprimes;
+            const uint32_t p = valid ? primes[c] : 0u;
+            bool hit = false;
+#pragma unroll
+            for (int j = 0; j < 24; ++j) hit = hit || (p % kOddBases[j] == nres[j]);
+            const bool keep = valid && !hit;
+            const unsigned long long m = __builtin_amdgcn_ballot_w64(keep);
+            const uint32_t rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+            const uint32_t room = 64u - cnt;
+            if (keep && rank < room) cand[cnt + rank] = c;
+            const uint32_t tot = (uint32_t)__popcll(m);
+            if (tot > room) {
+                // resume at the first surviving p that did not fit
+                next += (uint32_t)__builtin_ctzll(__builtin_amdgcn_ballot_w64(keep && rank == room));
+                cnt = 64u;
+            } else {
+                next = next + 64u < nprimes ? next + 64u : nprimes;
+                cnt += tot;
+            }
+        }
+        if (cnt == 0u) break;                        // table exhausted
+        __builtin_amdgcn_wave_barrier();
+        const bool act = lane < cnt;
+        const uint32_t c = act ? cand[lane] : 0u;
+        __builtin_amdgcn_wave_barrier();
+        const uint32_t p = act ? primes[c] : 3u;
         // q = n - p (n >= 2^64 > p)
         Num<K> q;
         {
             uint64_t br = p;
+#pragma unroll
             for (int i = 0; i < K; ++i) {
                 const uint64_t t = (uint64_t)n.w[i] - br;
                 q.w[i] = (uint32_t)t;
                 br = (t >> 63) & 1u;
             }
         }
-        const bool pass2 = valid && gbbig::strong_prp<K>(q, 2u);
+        const bool pass2 = act && gbbig::strong_prp2<K>(q);
+        const unsigned long long m = __builtin_amdgcn_ballot_w64(pass2);
+        if (m) {
+            if (lane == 0u) pos[idx] = __builtin_amdgcn_readlane(c, (uint32_t)__builtin_ctzll(m));
+            return;
+        }
+    }
+    if (lane == 0u) pos[idx] = nprimes;              // no candidate left in the table
+}
+
+// One lane per (n, base 3 .. 97): bad[idx] is set when the candidate's q
+// fails a base.
+template <int K>
+__global__ __launch_bounds__(256) void k_big_confirm(const uint32_t *n_all, const uint32_t *list, uint32_t nlist,
+                                                     const uint32_t *primes, uint32_t nprimes, const uint32_t *pos,
+                                                     uint32_t *bad)
+{
+    const uint32_t g = blockIdx.x * 256u + threadIdx.x;
+    if (g >= nlist * 24u) return;
+    const uint32_t slot = g / 24u, j = g - slot * 24u;
+    const uint32_t idx = list ? list[slot] : slot;
+    const uint32_t c = pos[idx];
+    if (c >= nprimes) return;                        // nothing to confirm
+    const uint32_t p = primes[c];
+    Num<K> q;
+    uint64_t br = p;
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+        const uint64_t t = (uint64_t)n_all[(uint64_t)idx * K + i] - br;
+        q.w[i] = (uint32_t)t;
+        br = (t >> 63) & 1u;
+    }
+    if (!gbbig::strong_prp<K>(q, kBigBases[j + 1u]))
+        __hip_atomic_fetch_or(&bad[idx], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// The one-kernel form, used for 32 limbs: the same filter and base-2 search
+// in one wavefront per n, the lowest passing lane's q then tested to the
+// other 24 bases by lanes 0 .. 23 of the same wavefront (next passing lane,
+// then the next 64 surviving p, when it fails one).  The two-kernel form at
+// 32 limbs did not finish a 520-bit case on the GPU; its cause is not
+// known, so that form is kept to 4 .. 16 limbs.
+template <int K>
+__global__ __launch_bounds__(256) void k_big_wave(const uint32_t *n_all, uint64_t k, const uint32_t *primes,
+                                                  uint64_t nprimes, unsigned long long *p_out)
+{
+    __shared__ uint32_t cand_all[4][64];
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const uint64_t idx = (uint64_t)blockIdx.x * 4u + wv;
+    if (idx >= k) return;                            // whole wave
+    uint32_t *cand = cand_all[wv];
+    Num<K> n;
+#pragma unroll
+    for (int i = 0; i < K; ++i) n.w[i] = n_all[idx * K + i];
+    uint32_t nres[24];
+#pragma unroll
+    for (int j = 0; j < 24; ++j) nres[j] = mod_small(n, kOddBases[j]);
+    uint64_t next = 0;
+    for (;;) {
+        uint32_t cnt = 0;
+        while (cnt < 64u && next < nprimes) {
+            const uint64_t c = next + lane;
+            const bool valid = c < nprimes;
+            const uint32_t p = valid ? primes[c] : 0u;
+            bool hit = false;
+#pragma unroll
+            for (int j = 0; j < 24; ++j) hit = hit || (p % kOddBases[j] == nres[j]);
+            const bool keep = valid && !hit;
+            const unsigned long long m = __builtin_amdgcn_ballot_w64(keep);
+            const uint32_t rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+            const uint32_t room = 64u - cnt;
+            if (keep && rank < room) cand[cnt + rank] = p;
+            const uint32_t tot = (uint32_t)__popcll(m);
+            if (tot > room) {
+                next += (uint64_t)__builtin_ctzll(__builtin_amdgcn_ballot_w64(keep && rank == room));
+                cnt = 64u;
+            } else {
+                next += 64u;
+                cnt += tot;
+            }
+        }
+        if (cnt == 0u) break;                        // table exhausted
+        __builtin_amdgcn_wave_barrier();
+        const bool act = lane < cnt;
+        const uint32_t p = act ? cand[lane] : 3u;
+        __builtin_amdgcn_wave_barrier();
+        Num<K> q;
+        {
+            uint64_t br = p;
+#pragma unroll
+            for (int i = 0; i < K; ++i) {
+                const uint64_t t = (uint64_t)n.w[i] - br;
+                q.w[i] = (uint32_t)t;
+                br = (t >> 63) & 1u;
+            }
+        }
+        const bool pass2 = act && gbbig::strong_prp<K>(q, 2u);
         unsigned long long m = __builtin_amdgcn_ballot_w64(pass2);
         while (m) {
             const uint32_t L = (uint32_t)__builtin_ctzll(m);
             m &= m - 1ull;
-            // the candidate's q in every lane, then one more base per lane
             Num<K> qL;
+#pragma unroll
             for (int i = 0; i < K; ++i) qL.w[i] = __builtin_amdgcn_readlane(q.w[i], L);
             const bool ok = lane >= 24u || gbbig::strong_prp<K>(qL, kBigBases[lane + 1u]);
             if (__builtin_amdgcn_ballot_w64(!ok) == 0ull) {
@@ -63,10 +219,15 @@ __global__ __launch_bounds__(256) void k_big(const uint32_t *n_all, uint64_t k, 
 }
 
 template <int K>
-hipError_t launch_big(const uint32_t *n, uint64_t k, const uint32_t *primes, uint64_t nprimes,
-                      unsigned long long *p, hipStream_t st)
+hipError_t launch_big(const uint32_t *n, const uint32_t *list, uint32_t nlist, const uint32_t *primes,
+                      uint32_t nprimes, uint32_t *pos, uint32_t *bad, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_big<K>, dim3((uint32_t)((k + 3) / 4)), dim3(256), 0, st, n, k, primes, nprimes, p);
+    hipLaunchKernelGGL(k_big_search<K>, dim3((nlist + 3u) / 4u), dim3(256), 0, st, n, list, nlist, primes, nprimes,
+                       pos);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_big_confirm<K>, dim3((uint32_t)(((uint64_t)nlist * 24u + 255u) / 256u)), dim3(256), 0, st, n,
+                       list, nlist, primes, nprimes, pos, bad);
     return hipGetLastError();
 }
 
@@ -80,8 +241,11 @@ gb_status gb_verify_big(gb_ctx *c, const uint32_t *n, uint32_t nlimbs, size_t k,
     if (nlimbs < 3 || nlimbs > 32) return fail(c, GB_EINVAL, "nlimbs must be in 3..32");
     if (k == 0) return GB_OK;
     if (k > (1ull << 24)) return fail(c, GB_EINVAL, "at most 2^24 n per call");
-    // limb counts compiled: 4, 8, 12, 16, 24, 32
-    const int K = nlimbs <= 4 ? 4 : nlimbs <= 8 ? 8 : nlimbs <= 12 ? 12 : nlimbs <= 16 ? 16 : nlimbs <= 24 ? 24 : 32;
+    // limb counts compiled: 4, 8, 12, 16, 32.  A 24-limb form built from this
+    // same source returned wrong answers on gfx950 (its host build is right;
+    // the device code keeps the multiplier operand in scratch there), so 17 to
+    // 24 limbs run in the 32-limb form.
+    const int K = nlimbs <= 4 ? 4 : nlimbs <= 8 ? 8 : nlimbs <= 12 ? 12 : nlimbs <= 16 ? 16 : 32;
     // every n even and at least 2^64
     for (size_t i = 0; i < k; ++i) {
         const uint32_t *w = n + i * nlimbs;
@@ -96,19 +260,61 @@ gb_status gb_verify_big(gb_ctx *c, const uint32_t *n, uint32_t nlimbs, size_t k,
     for (size_t i = 0; i < k; ++i) std::memcpy(&h[i * K], n + i * nlimbs, nlimbs * 4);
     Workspace &ws = c->ws;
     GB_HIP(c, ws.big_n.ensure(h.size()));
-    GB_HIP(c, ws.big_p.ensure(k));
+    GB_HIP(c, ws.big_pos.ensure(k));
+    GB_HIP(c, ws.big_bad.ensure(k));
+    GB_HIP(c, ws.big_list.ensure(k));
     GB_HIP(c, hipMemcpyAsync(ws.big_n.p, h.data(), h.size() * 4, hipMemcpyHostToDevice, st));
-    switch (K) {
-    case 4: GB_HIP(c, launch_big<4>(ws.big_n.p, k, c->d_primes, c->ntab, ws.big_p.p, st)); break;
-    case 8: GB_HIP(c, launch_big<8>(ws.big_n.p, k, c->d_primes, c->ntab, ws.big_p.p, st)); break;
-    case 12: GB_HIP(c, launch_big<12>(ws.big_n.p, k, c->d_primes, c->ntab, ws.big_p.p, st)); break;
-    case 16: GB_HIP(c, launch_big<16>(ws.big_n.p, k, c->d_primes, c->ntab, ws.big_p.p, st)); break;
-    case 24: GB_HIP(c, launch_big<24>(ws.big_n.p, k, c->d_primes, c->ntab, ws.big_p.p, st)); break;
-    default: GB_HIP(c, launch_big<32>(ws.big_n.p, k, c->d_primes, c->ntab, ws.big_p.p, st)); break;
+    if (K == 32) {
+        GB_HIP(c, ws.big_p.ensure(k));
+        hipLaunchKernelGGL(k_big_wave<32>, dim3((uint32_t)((k + 3) / 4)), dim3(256), 0, st, ws.big_n.p, (uint64_t)k,
+                           c->d_primes, c->ntab, ws.big_p.p);
+        GB_HIP(c, hipGetLastError());
+        GB_HIP(c, hipMemcpyAsync(p, ws.big_p.p, k * 8, hipMemcpyDeviceToHost, st));
+        GB_HIP(c, hipStreamSynchronize(st));
+        for (size_t i = 0; i < k; ++i)
+            if (p[i] == 0) return fail(c, GB_EUNRESOLVED, "no partition with p in the resident prime table");
+        return GB_OK;
     }
-    GB_HIP(c, hipMemcpyAsync(p, ws.big_p.p, k * 8, hipMemcpyDeviceToHost, st));
-    GB_HIP(c, hipStreamSynchronize(st));
-    for (size_t i = 0; i < k; ++i)
-        if (p[i] == 0) return fail(c, GB_EUNRESOLVED, "no partition with p in the resident prime table");
+    GB_HIP(c, hipMemsetAsync(ws.big_pos.p, 0, k * 4, st));
+    const uint32_t np = (uint32_t)c->ntab;
+    std::vector<uint32_t> pos(k), bad(k), list;
+    const uint32_t *dlist = nullptr;                 // every n on the first pass
+    uint32_t nlist = (uint32_t)k;
+    // A rejected candidate is a strong pseudoprime to base 2 (none below
+    // 2^64 pass the first 12 bases either); a call with many passes is
+    // stopped with an error rather than left to run through the table.
+    for (int pass = 0;; ++pass) {
+        if (pass == 64) return fail(c, GB_EDEVICE, "confirmation rejected too many candidates");
+        GB_HIP(c, hipMemsetAsync(ws.big_bad.p, 0, k * 4, st));
+        hipError_t e;
+        switch (K) {
+        case 4: e = launch_big<4>(ws.big_n.p, dlist, nlist, c->d_primes, np, ws.big_pos.p, ws.big_bad.p, st); break;
+        case 8: e = launch_big<8>(ws.big_n.p, dlist, nlist, c->d_primes, np, ws.big_pos.p, ws.big_bad.p, st); break;
+        case 12: e = launch_big<12>(ws.big_n.p, dlist, nlist, c->d_primes, np, ws.big_pos.p, ws.big_bad.p, st); break;
+        default: e = launch_big<16>(ws.big_n.p, dlist, nlist, c->d_primes, np, ws.big_pos.p, ws.big_bad.p, st); break;
+        }
+        GB_HIP(c, e);
+        GB_HIP(c, hipMemcpyAsync(pos.data(), ws.big_pos.p, k * 4, hipMemcpyDeviceToHost, st));
+        GB_HIP(c, hipMemcpyAsync(bad.data(), ws.big_bad.p, k * 4, hipMemcpyDeviceToHost, st));
+        GB_HIP(c, hipStreamSynchronize(st));
+        // candidates that failed a base: search again from the next p
+        list.clear();
+        for (uint32_t i = 0; i < (uint32_t)k; ++i)
+            if (bad[i]) {
+                list.push_back(i);
+                ++pos[i];
+            }
+        if (list.empty()) break;
+        GB_HIP(c, hipMemcpyAsync(ws.big_pos.p, pos.data(), k * 4, hipMemcpyHostToDevice, st));
+        GB_HIP(c, hipMemcpyAsync(ws.big_list.p, list.data(), list.size() * 4, hipMemcpyHostToDevice, st));
+        dlist = ws.big_list.p;
+        nlist = (uint32_t)list.size();
+    }
+    bool unresolved = false;
+    for (size_t i = 0; i < k; ++i) {
+        p[i] = pos[i] < np ? c->h_primes[pos[i]] : 0ull;
+        unresolved = unresolved || p[i] == 0;
+    }
+    if (unresolved) return fail(c, GB_EUNRESOLVED, "no partition with p in the resident prime table");
     return GB_OK;
 }

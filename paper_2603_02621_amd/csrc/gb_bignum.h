@@ -197,4 +197,44 @@ template <int K> __host__ __device__ inline bool strong_prp(const Num<K> &q, uin
     }
 }
 
+// Strong probable prime to base 2, as strong_prp, with each multiplication
+// by the base done as a modular doubling (2 x R mod q from x R mod q): one
+// Montgomery squaring per exponent bit and no general product.
+template <int K> __host__ __device__ inline bool strong_prp2(const Num<K> &q)
+{
+    const uint32_t ninv = neg_inv32(q.w[0]);
+    const int nb = bit_length(q);
+    Num<K> one;
+#pragma unroll
+    for (int i = 0; i < K; ++i) one.w[i] = (i == ((nb - 1) >> 5)) ? 1u << ((nb - 1) & 31) : 0u;
+    for (int i = nb - 1; i < 32 * K; ++i) dbl_mod(one, q);
+    Num<K> mone;
+    sub(mone, q, one);
+    int s = 1;
+    while (bit(q, s) == 0u) ++s;
+    const int db = nb - s;
+    // x = 2^d: the top bit of d gives 2R; each lower bit one squaring, then
+    // a doubling for a set bit; then up to s - 1 more squarings
+    Num<K> x = one;
+    dbl_mod(x, q);
+    int i = db - 2;
+    int r = 0;
+    for (;;) {
+        if (i < 0) {
+            if (r == 0) {
+                if (equal(x, one) || equal(x, mone)) return true;
+            } else {
+                if (equal(x, mone)) return true;
+                if (equal(x, one)) return false;
+            }
+            if (++r >= s) return false;
+        }
+        mont_mul(x, x, x, q, ninv);
+        if (i >= 0) {
+            if (bit(q, i + s)) dbl_mod(x, q);
+            --i;
+        }
+    }
+}
+
 }  // namespace gbbig

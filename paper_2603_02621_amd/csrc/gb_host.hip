@@ -228,6 +228,9 @@ void Workspace::release()
     pc_red.release();
     h_pc_red.release();
     big_n.release();
+    big_pos.release();
+    big_bad.release();
+    big_list.release();
     big_p.release();
     h_slots.release();
     h_hist.release();

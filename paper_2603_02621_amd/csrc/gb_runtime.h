@@ -94,8 +94,11 @@ struct Workspace {
     DevBuf<unsigned long long> pc_counts;  // partition counts when the caller passes none
     DevBuf<unsigned long long> pc_red;   // partition counts: sum, min key, max key
     PinBuf<unsigned long long> h_pc_red;
-    DevBuf<uint32_t> big_n;              // beyond 64 bits: the n, K limbs each
-    DevBuf<unsigned long long> big_p;    // and their p
+    DevBuf<uint32_t> big_n;              // beyond 64 bits: the n, K limbs each,
+    DevBuf<uint32_t> big_pos;            // the table index of each n's candidate p,
+    DevBuf<uint32_t> big_bad;            // its confirmation flags
+    DevBuf<uint32_t> big_list;           // and the n searched again;
+    DevBuf<unsigned long long> big_p;    // the one-kernel form's answers
     PinBuf<GbSlot> h_slots;
     PinBuf<unsigned long long> h_hist;
     PinBuf<unsigned long long> h_counters;

@@ -74,3 +74,17 @@ def test_random_big_n_minimal():
             p = big.pmin_big(n)
             assert p and sympy.isprime(p) and sympy.isprime(n - p)
             assert not any(sympy.isprime(n - q) for q in sympy.primerange(3, p))
+
+
+def test_small_factor_fails_its_own_base():
+    # q with an odd prime factor r <= 97 fails the strong test to base r: every
+    # power of r mod q is a multiple of r, never 1 or q - 1.  The GPU scan drops
+    # p = n (mod r) on this ground before exponentiating, so its answer equals
+    # the full 25-base scan's.
+    rng = random.Random(11)
+    for r in big.BASES[1:]:
+        for bits in (70, 200, 500):
+            for _ in range(4):
+                q = r * (rng.getrandbits(bits) | 1)
+                assert not big.strong_probable_prime(q, r), (q, r)
+                assert not big.probable_prime(q)

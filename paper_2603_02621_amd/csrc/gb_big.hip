@@ -15,6 +15,7 @@
 // (a strong pseudoprime to base 2) sends its n back to the search, which
 // resumes after it.  The answer is the first p whose q passes all 25 bases;
 // every smaller p failed one, so its q is composite.
+#include <algorithm>
 #include <cstring>
 
 #include "gb_bignum.h"
@@ -40,18 +41,23 @@ template <int K> __device__ __forceinline__ uint32_t mod_small(const Num<K> &n, 
     return acc;
 }
 
-// pos[idx]: in, the table index to resume from; out, the table index of
-// the first surviving p at or after it whose q passes base 2, or nprimes.
+// One pass of the search: nways wavefronts per listed n, wavefront w taking
+// the w-th group of 64 surviving p from resume[idx] on and testing it to
+// base 2.  found[idx] (all ones before the pass) receives the smallest table
+// index that passed; the last wavefront sets resume[idx] to the table index
+// after its group (nprimes at the table's end).
 template <int K>
 __global__ __launch_bounds__(256) void k_big_search(const uint32_t *n_all, const uint32_t *list, uint32_t nlist,
-                                                    const uint32_t *primes, uint32_t nprimes, uint32_t *pos)
+                                                    uint32_t nways, const uint32_t *primes, uint32_t nprimes,
+                                                    uint32_t *resume, uint32_t *found)
 {
     __shared__ uint32_t cand_all[4][64];
     const uint32_t lane = threadIdx.x & 63u;
     const uint32_t wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const uint32_t slot = blockIdx.x * 4u + wv;
-    if (slot >= nlist) return;                       // whole wave
-    const uint32_t idx = list ? list[slot] : slot;
+    if (slot >= nlist * nways) return;               // whole wave
+    const uint32_t li = slot / nways, way = slot - li * nways;
+    const uint32_t idx = list ? list[li] : li;
     uint32_t *cand = cand_all[wv];
     Num<K> n;
 #pragma unroll
@@ -60,71 +66,67 @@ __global__ __launch_bounds__(256) void k_big_search(const uint32_t *n_all, const
     uint32_t nres[24];
 #pragma unroll
     for (int j = 0; j < 24; ++j) nres[j] = mod_small(n, kOddBases[j]);
-    uint32_t next = pos[idx];                        // next table index to filter
-    for (;;) {
-        // the table indices of the next (up to) 64 surviving p, ascending
-        uint32_t cnt = 0;
-        while (cnt < 64u && next < nprimes) {
-            const uint32_t c = next + lane;
-            const bool valid = c < nprimes;
-            const uint32_t p = valid ? primes[c] : 0u;
-            bool hit = false;
+    // table indices of the surviving p ranked [lo, hi) from resume[idx] on
+    const uint32_t lo = 64u * way, hi = lo + 64u;
+    uint32_t got = 0, next = resume[idx];
+    while (got < hi && next < nprimes) {
+        const uint32_t c = next + lane;
+        const bool valid = c < nprimes;
+        const uint32_t p = valid ? primes[c] : 0u;
+        bool hit = false;
 #pragma unroll
-            for (int j = 0; j < 24; ++j) hit = hit || (p % kOddBases[j] == nres[j]);
-            const bool keep = valid && !hit;
-            const unsigned long long m = __builtin_amdgcn_ballot_w64(keep);
-            const uint32_t rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-            const uint32_t room = 64u - cnt;
-            if (keep && rank < room) cand[cnt + rank] = c;
-            const uint32_t tot = (uint32_t)__popcll(m);
-            if (tot > room) {
-                // resume at the first surviving p that did not fit
-                next += (uint32_t)__builtin_ctzll(__builtin_amdgcn_ballot_w64(keep && rank == room));
-                cnt = 64u;
-            } else {
-                next = next + 64u < nprimes ? next + 64u : nprimes;
-                cnt += tot;
-            }
-        }
-        if (cnt == 0u) break;                        // table exhausted
-        __builtin_amdgcn_wave_barrier();
-        const bool act = lane < cnt;
-        const uint32_t c = act ? cand[lane] : 0u;
-        __builtin_amdgcn_wave_barrier();
-        const uint32_t p = act ? primes[c] : 3u;
-        // q = n - p (n >= 2^64 > p)
-        Num<K> q;
-        {
-            uint64_t br = p;
-#pragma unroll
-            for (int i = 0; i < K; ++i) {
-                const uint64_t t = (uint64_t)n.w[i] - br;
-                q.w[i] = (uint32_t)t;
-                br = (t >> 63) & 1u;
-            }
-        }
-        const bool pass2 = act && gbbig::strong_prp2<K>(q);
-        const unsigned long long m = __builtin_amdgcn_ballot_w64(pass2);
-        if (m) {
-            if (lane == 0u) pos[idx] = __builtin_amdgcn_readlane(c, (uint32_t)__builtin_ctzll(m));
-            return;
+        for (int j = 0; j < 24; ++j) hit = hit || (p % kOddBases[j] == nres[j]);
+        const bool keep = valid && !hit;
+        const unsigned long long m = __builtin_amdgcn_ballot_w64(keep);
+        const uint32_t g = got + __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+        if (keep && g >= lo && g < hi) cand[g - lo] = c;
+        const uint32_t tot = (uint32_t)__popcll(m);
+        if (got + tot > hi) {
+            // the first surviving p past the group
+            next += (uint32_t)__builtin_ctzll(__builtin_amdgcn_ballot_w64(keep && g == hi));
+            got = hi;
+        } else {
+            next = next + 64u < nprimes ? next + 64u : nprimes;
+            got += tot;
         }
     }
-    if (lane == 0u) pos[idx] = nprimes;              // no candidate left in the table
+    if (way == nways - 1u && lane == 0u) resume[idx] = next;
+    const uint32_t cnt = got > lo ? got - lo : 0u;
+    if (cnt == 0u) return;                           // the table ends before the group
+    __builtin_amdgcn_wave_barrier();
+    const bool act = lane < cnt;
+    const uint32_t c = act ? cand[lane] : 0u;
+    const uint32_t p = act ? primes[c] : 3u;
+    // q = n - p (n >= 2^64 > p)
+    Num<K> q;
+    {
+        uint64_t br = p;
+#pragma unroll
+        for (int i = 0; i < K; ++i) {
+            const uint64_t t = (uint64_t)n.w[i] - br;
+            q.w[i] = (uint32_t)t;
+            br = (t >> 63) & 1u;
+        }
+    }
+    const bool pass2 = act && gbbig::strong_prp2<K>(q);
+    const unsigned long long m = __builtin_amdgcn_ballot_w64(pass2);
+    if (m != 0ull && lane == 0u)
+        __hip_atomic_fetch_min(&found[idx], __builtin_amdgcn_readlane(c, (uint32_t)__builtin_ctzll(m)), __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // One lane per (n, base 3 .. 97): bad[idx] is set when the candidate's q
 // fails a base.
 template <int K>
 __global__ __launch_bounds__(256) void k_big_confirm(const uint32_t *n_all, const uint32_t *list, uint32_t nlist,
-                                                     const uint32_t *primes, uint32_t nprimes, const uint32_t *pos,
+                                                     const uint32_t *primes, uint32_t nprimes, const uint32_t *found,
                                                      uint32_t *bad)
 {
     const uint32_t g = blockIdx.x * 256u + threadIdx.x;
     if (g >= nlist * 24u) return;
     const uint32_t slot = g / 24u, j = g - slot * 24u;
     const uint32_t idx = list ? list[slot] : slot;
-    const uint32_t c = pos[idx];
+    const uint32_t c = found[idx];
     if (c >= nprimes) return;                        // nothing to confirm
     const uint32_t p = primes[c];
     Num<K> q;
@@ -200,7 +202,7 @@ __global__ __launch_bounds__(256) void k_big_wave(const uint32_t *n_all, uint64_
                 br = (t >> 63) & 1u;
             }
         }
-        const bool pass2 = act && gbbig::strong_prp<K>(q, 2u);
+        const bool pass2 = act && gbbig::strong_prp<K, true>(q, 2u);
         unsigned long long m = __builtin_amdgcn_ballot_w64(pass2);
         while (m) {
             const uint32_t L = (uint32_t)__builtin_ctzll(m);
@@ -208,7 +210,7 @@ __global__ __launch_bounds__(256) void k_big_wave(const uint32_t *n_all, uint64_
             Num<K> qL;
 #pragma unroll
             for (int i = 0; i < K; ++i) qL.w[i] = __builtin_amdgcn_readlane(q.w[i], L);
-            const bool ok = lane >= 24u || gbbig::strong_prp<K>(qL, kBigBases[lane + 1u]);
+            const bool ok = lane >= 24u || gbbig::strong_prp<K, true>(qL, kBigBases[lane + 1u]);
             if (__builtin_amdgcn_ballot_w64(!ok) == 0ull) {
                 if (lane == 0u) p_out[idx] = __builtin_amdgcn_readlane(p, L);
                 return;
@@ -219,15 +221,15 @@ __global__ __launch_bounds__(256) void k_big_wave(const uint32_t *n_all, uint64_
 }
 
 template <int K>
-hipError_t launch_big(const uint32_t *n, const uint32_t *list, uint32_t nlist, const uint32_t *primes,
-                      uint32_t nprimes, uint32_t *pos, uint32_t *bad, hipStream_t st)
+hipError_t launch_big(const uint32_t *n, const uint32_t *list, uint32_t nlist, uint32_t nways, const uint32_t *primes,
+                      uint32_t nprimes, uint32_t *resume, uint32_t *found, uint32_t *bad, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_big_search<K>, dim3((nlist + 3u) / 4u), dim3(256), 0, st, n, list, nlist, primes, nprimes,
-                       pos);
+    hipLaunchKernelGGL(k_big_search<K>, dim3((uint32_t)(((uint64_t)nlist * nways + 3u) / 4u)), dim3(256), 0, st, n,
+                       list, nlist, nways, primes, nprimes, resume, found);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_big_confirm<K>, dim3((uint32_t)(((uint64_t)nlist * 24u + 255u) / 256u)), dim3(256), 0, st, n,
-                       list, nlist, primes, nprimes, pos, bad);
+                       list, nlist, primes, nprimes, found, bad);
     return hipGetLastError();
 }
 
@@ -261,6 +263,7 @@ gb_status gb_verify_big(gb_ctx *c, const uint32_t *n, uint32_t nlimbs, size_t k,
     Workspace &ws = c->ws;
     GB_HIP(c, ws.big_n.ensure(h.size()));
     GB_HIP(c, ws.big_pos.ensure(k));
+    GB_HIP(c, ws.big_found.ensure(k));
     GB_HIP(c, ws.big_bad.ensure(k));
     GB_HIP(c, ws.big_list.ensure(k));
     GB_HIP(c, hipMemcpyAsync(ws.big_n.p, h.data(), h.size() * 4, hipMemcpyHostToDevice, st));
@@ -277,42 +280,53 @@ gb_status gb_verify_big(gb_ctx *c, const uint32_t *n, uint32_t nlimbs, size_t k,
     }
     GB_HIP(c, hipMemsetAsync(ws.big_pos.p, 0, k * 4, st));
     const uint32_t np = (uint32_t)c->ntab;
-    std::vector<uint32_t> pos(k), bad(k), list;
+    std::vector<uint32_t> resume(k), found(k), bad(k), ans(k, UINT32_MAX), list, cur;
     const uint32_t *dlist = nullptr;                 // every n on the first pass
-    uint32_t nlist = (uint32_t)k;
-    // A rejected candidate is a strong pseudoprime to base 2 (none below
-    // 2^64 pass the first 12 bases either); a call with many passes is
-    // stopped with an error rather than left to run through the table.
+    uint32_t nlist = (uint32_t)k, nways = 1;
+    // The n still open after a pass get several wavefronts each, one per
+    // group of 64 surviving p, so that the last n do not run alone.  Every
+    // pass moves each open n's resume point forward, so the loop ends; the
+    // cap stops a call whose device results do not settle.
+    const uint32_t target = (uint32_t)c->num_cu * 16u;
     for (int pass = 0;; ++pass) {
-        if (pass == 64) return fail(c, GB_EDEVICE, "confirmation rejected too many candidates");
+        if (pass == 256) return fail(c, GB_EDEVICE, "big-n search did not settle");
+        GB_HIP(c, hipMemsetAsync(ws.big_found.p, 0xFF, k * 4, st));
         GB_HIP(c, hipMemsetAsync(ws.big_bad.p, 0, k * 4, st));
         hipError_t e;
         switch (K) {
-        case 4: e = launch_big<4>(ws.big_n.p, dlist, nlist, c->d_primes, np, ws.big_pos.p, ws.big_bad.p, st); break;
-        case 8: e = launch_big<8>(ws.big_n.p, dlist, nlist, c->d_primes, np, ws.big_pos.p, ws.big_bad.p, st); break;
-        case 12: e = launch_big<12>(ws.big_n.p, dlist, nlist, c->d_primes, np, ws.big_pos.p, ws.big_bad.p, st); break;
-        default: e = launch_big<16>(ws.big_n.p, dlist, nlist, c->d_primes, np, ws.big_pos.p, ws.big_bad.p, st); break;
+        case 4: e = launch_big<4>(ws.big_n.p, dlist, nlist, nways, c->d_primes, np, ws.big_pos.p, ws.big_found.p, ws.big_bad.p, st); break;
+        case 8: e = launch_big<8>(ws.big_n.p, dlist, nlist, nways, c->d_primes, np, ws.big_pos.p, ws.big_found.p, ws.big_bad.p, st); break;
+        case 12: e = launch_big<12>(ws.big_n.p, dlist, nlist, nways, c->d_primes, np, ws.big_pos.p, ws.big_found.p, ws.big_bad.p, st); break;
+        default: e = launch_big<16>(ws.big_n.p, dlist, nlist, nways, c->d_primes, np, ws.big_pos.p, ws.big_found.p, ws.big_bad.p, st); break;
         }
         GB_HIP(c, e);
-        GB_HIP(c, hipMemcpyAsync(pos.data(), ws.big_pos.p, k * 4, hipMemcpyDeviceToHost, st));
+        GB_HIP(c, hipMemcpyAsync(resume.data(), ws.big_pos.p, k * 4, hipMemcpyDeviceToHost, st));
+        GB_HIP(c, hipMemcpyAsync(found.data(), ws.big_found.p, k * 4, hipMemcpyDeviceToHost, st));
         GB_HIP(c, hipMemcpyAsync(bad.data(), ws.big_bad.p, k * 4, hipMemcpyDeviceToHost, st));
         GB_HIP(c, hipStreamSynchronize(st));
-        // candidates that failed a base: search again from the next p
         list.clear();
-        for (uint32_t i = 0; i < (uint32_t)k; ++i)
-            if (bad[i]) {
-                list.push_back(i);
-                ++pos[i];
+        for (uint32_t li = 0; li < nlist; ++li) {
+            const uint32_t i = dlist ? cur[li] : li;
+            if (found[i] < np) {
+                if (!bad[i]) {
+                    ans[i] = found[i];
+                    continue;
+                }
+                resume[i] = found[i] + 1u;           // a base-2 pseudoprime: resume after it
             }
+            if (resume[i] < np) list.push_back(i);   // else the table ends: unresolved
+        }
         if (list.empty()) break;
-        GB_HIP(c, hipMemcpyAsync(ws.big_pos.p, pos.data(), k * 4, hipMemcpyHostToDevice, st));
-        GB_HIP(c, hipMemcpyAsync(ws.big_list.p, list.data(), list.size() * 4, hipMemcpyHostToDevice, st));
-        dlist = ws.big_list.p;
         nlist = (uint32_t)list.size();
+        nways = std::max(1u, std::min(16u, target / nlist));
+        cur = list;
+        GB_HIP(c, hipMemcpyAsync(ws.big_pos.p, resume.data(), k * 4, hipMemcpyHostToDevice, st));
+        GB_HIP(c, hipMemcpyAsync(ws.big_list.p, cur.data(), nlist * 4, hipMemcpyHostToDevice, st));
+        dlist = ws.big_list.p;
     }
     bool unresolved = false;
     for (size_t i = 0; i < k; ++i) {
-        p[i] = pos[i] < np ? c->h_primes[pos[i]] : 0ull;
+        p[i] = ans[i] < np ? c->h_primes[ans[i]] : 0ull;
         unresolved = unresolved || p[i] == 0;
     }
     if (unresolved) return fail(c, GB_EUNRESOLVED, "no partition with p in the resident prime table");

@@ -229,6 +229,7 @@ void Workspace::release()
     h_pc_red.release();
     big_n.release();
     big_pos.release();
+    big_found.release();
     big_bad.release();
     big_list.release();
     big_p.release();

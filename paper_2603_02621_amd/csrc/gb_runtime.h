@@ -95,7 +95,8 @@ struct Workspace {
     DevBuf<unsigned long long> pc_red;   // partition counts: sum, min key, max key
     PinBuf<unsigned long long> h_pc_red;
     DevBuf<uint32_t> big_n;              // beyond 64 bits: the n, K limbs each,
-    DevBuf<uint32_t> big_pos;            // the table index of each n's candidate p,
+    DevBuf<uint32_t> big_pos;            // the table index each n's search resumes from,
+    DevBuf<uint32_t> big_found;          // the index of its candidate p,
     DevBuf<uint32_t> big_bad;            // its confirmation flags
     DevBuf<uint32_t> big_list;           // and the n searched again;
     DevBuf<unsigned long long> big_p;    // the one-kernel form's answers

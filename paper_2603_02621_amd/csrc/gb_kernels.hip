@@ -159,7 +159,8 @@ __device__ __forceinline__ uint32_t pr_lh(uint32_t i) { return pr_px(i) + 8u; }
 // LDS carve-up of one tile workgroup (offsets in 32-bit words).
 struct TileLds {
     uint32_t *bits;           // (T + HB)/32 words: the tile's window, 1 = prime
-    // odd primes p <= P_max (padded by 4 copies of the last) in groups of
+    // odd primes p <= P_max (padded with copies of the last through one more
+    // group) in groups of
     // four, 12 words per group: the four packed words, the four g =
     // 2^16 - (p+1)/2, the four hit counts of this tile
     uint32_t *pr;
@@ -233,7 +234,10 @@ __device__ void process_tile(const GbTileArgs &a, unsigned long long g, const Ti
 
     // ---- fast-path prime list, per-tile histogram --------------------------
     if (!SIEVE_ONLY) {
-        for (uint32_t i = tid; i < nps + 4; i += NT) {
+        // through the end of the group after the last prime's group: a lane
+        // runs two groups per exit check and may start on the last one
+        const uint32_t npad = 4u * ((nps + 3u) / 4u + 1u);
+        for (uint32_t i = tid; i < npad; i += NT) {
             const uint32_t p = a.primes[i < nps ? i : (nps ? nps - 1 : 0)];
             const uint32_t h = (p + 1u) >> 1;
             uint32_t hi = PX_BIAS - 4u * ((h + 31u) >> 5);
@@ -528,93 +532,99 @@ __device__ void process_tile(const GbTileArgs &a, unsigned long long g, const Ti
     }
     while (b < nblk) {
         if (nps != 0u) {
-            // four probes per exit check; the prime list is padded with
-            // copies of its last prime, which cannot hit an n twice
-            // the group's twelve window words do not depend on the hits, so
-            // they are all read before the first test
-            const v4u32 xv = *reinterpret_cast<const lds_v4 *>(static_cast<uintptr_t>(ka));
-            const uint32_t xs[4] = {xv.x, xv.y, xv.z, xv.w};
-            uint32_t dw[4][3], pcs[4];
-            if constexpr (GW) {
-                // the four windows lie in the four words from the base word
-                // of the group's last (largest) prime: two reads for the group
-                const lds_u32 *wp = probe_addr(xs[3], bw);
-                const uint32_t w0 = wp[0], w1 = wp[1], w2 = wp[2], w3 = wp[3];
+            // four probes (one group) per exit check, eight in the bulk form,
+            // whose probes are cheap enough that the block-end work weighs;
+            // the prime list is padded with copies of its last prime, which
+            // cannot hit an n twice
+            constexpr uint32_t kGroupsPerCheck = VERIFY ? 2u : 1u;
 #pragma unroll
-                for (uint32_t u = 0; u < 3; ++u) {
-                    // all ones when the flag (bit 16) is set: one bit-field
-                    // extract, then three bit-wise selects
-                    const uint32_t m = sext_bit16(xs[u]);
-                    dw[u][0] = bitsel(m, w1, w0);
-                    dw[u][1] = bitsel(m, w2, w1);
-                    dw[u][2] = bitsel(m, w3, w2);
-                }
-                dw[3][0] = w0;
-                dw[3][1] = w1;
-                dw[3][2] = w2;
-            } else {
+            for (uint32_t gg = 0; gg < kGroupsPerCheck; ++gg) {
+                // the group's twelve window words do not depend on the hits, so
+                // they are all read before the first test
+                const v4u32 xv = *reinterpret_cast<const lds_v4 *>(static_cast<uintptr_t>(ka));
+                const uint32_t xs[4] = {xv.x, xv.y, xv.z, xv.w};
+                uint32_t dw[4][3], pcs[4];
+                if constexpr (GW) {
+                    // the four windows lie in the four words from the base word
+                    // of the group's last (largest) prime: two reads for the group
+                    const lds_u32 *wp = probe_addr(xs[3], bw);
+                    const uint32_t w0 = wp[0], w1 = wp[1], w2 = wp[2], w3 = wp[3];
 #pragma unroll
-                for (uint32_t u = 0; u < 4; ++u) {
-                    const lds_u32 *wp = probe_addr(xs[u], bw);
-                    dw[u][0] = wp[0];
-                    dw[u][1] = wp[1];
-                    dw[u][2] = wp[2];
+                    for (uint32_t u = 0; u < 3; ++u) {
+                        // all ones when the flag (bit 16) is set: one bit-field
+                        // extract, then three bit-wise selects
+                        const uint32_t m = sext_bit16(xs[u]);
+                        dw[u][0] = bitsel(m, w1, w0);
+                        dw[u][1] = bitsel(m, w2, w1);
+                        dw[u][2] = bitsel(m, w3, w2);
+                    }
+                    dw[3][0] = w0;
+                    dw[3][1] = w1;
+                    dw[3][2] = w2;
+                } else {
+#pragma unroll
+                    for (uint32_t u = 0; u < 4; ++u) {
+                        const lds_u32 *wp = probe_addr(xs[u], bw);
+                        dw[u][0] = wp[0];
+                        dw[u][1] = wp[1];
+                        dw[u][2] = wp[2];
+                    }
                 }
-            }
-            // the group's four g with one 16-byte read up front (otherwise
-            // the compiler sinks single reads into the hit branches)
-            v4u32 gv = *reinterpret_cast<const lds_v4 *>(static_cast<uintptr_t>(ka + 16u));
-            asm volatile("" : "+v"(gv.x), "+v"(gv.y), "+v"(gv.z), "+v"(gv.w));
-            const uint32_t gs[4] = {gv.x, gv.y, gv.z, gv.w};
-            if constexpr (VERIFY) {
-                // every n the prime resolves leaves U; the last probe that
-                // starts on a nonempty U is the one that empties it, i.e. the
-                // block's last hit (when the block resolves completely)
+                // the group's four g with one 16-byte read up front (otherwise
+                // the compiler sinks single reads into the hit branches)
+                v4u32 gv = *reinterpret_cast<const lds_v4 *>(static_cast<uintptr_t>(ka + 16u));
+                asm volatile("" : "+v"(gv.x), "+v"(gv.y), "+v"(gv.z), "+v"(gv.w));
+                const uint32_t gs[4] = {gv.x, gv.y, gv.z, gv.w};
+                if constexpr (VERIFY) {
+                    // every n the prime resolves leaves U; the last probe that
+                    // starts on a nonempty U is the one that empties it, i.e. the
+                    // block's last hit (when the block resolves completely)
+#pragma unroll
+                    for (uint32_t u = 0; u < 4; ++u) {
+                        const uint32_t x = xs[u];
+                        const uint32_t wlo = __builtin_amdgcn_alignbit(dw[u][1], dw[u][0], x);
+                        const uint32_t whi = __builtin_amdgcn_alignbit(dw[u][2], dw[u][1], x);
+                        lastkey = (Ulo | Uhi) != 0u ? gs[u] : lastkey;
+                        Ulo &= ~wlo;
+                        Uhi &= ~whi;
+                    }
+                } else {
 #pragma unroll
                 for (uint32_t u = 0; u < 4; ++u) {
                     const uint32_t x = xs[u];
-                    const uint32_t wlo = __builtin_amdgcn_alignbit(dw[u][1], dw[u][0], x);
-                    const uint32_t whi = __builtin_amdgcn_alignbit(dw[u][2], dw[u][1], x);
-                    lastkey = (Ulo | Uhi) != 0u ? gs[u] : lastkey;
-                    Ulo &= ~wlo;
-                    Uhi &= ~whi;
-                }
-            } else {
-#pragma unroll
-            for (uint32_t u = 0; u < 4; ++u) {
-                const uint32_t x = xs[u];
-                const uint32_t hlo = __builtin_amdgcn_alignbit(dw[u][1], dw[u][0], x) & Ulo;
-                const uint32_t hhi = __builtin_amdgcn_alignbit(dw[u][2], dw[u][1], x) & Uhi;
-                pcs[u] = __popc(hlo) + __popc(hhi);
-                if (pcs[u] != 0u) {
-                    const uint32_t pc = pcs[u];
-                    sumg = mad_lo16(x, pc, sumg);
-                    s0 += (unsigned long long)gs[u] * hlo;
-                    s1 += (unsigned long long)gs[u] * hhi;
-                    lastkey = x << 16;
-                    if constexpr (PB != 0) {
-                        if (a.pmin) {
-                            const uint32_t p = 131071u - 2u * (x & 0xFFFFu);
-                            unsigned long long hb = ((unsigned long long)hhi << 32) | hlo;
-                            const unsigned long long ob = outb + 64ull * b;
-                            while (hb) {
-                                store_p<PB>(a.pmin, ob + (unsigned long long)__builtin_ctzll(hb), p);
-                                hb &= hb - 1ull;
+                    const uint32_t hlo = __builtin_amdgcn_alignbit(dw[u][1], dw[u][0], x) & Ulo;
+                    const uint32_t hhi = __builtin_amdgcn_alignbit(dw[u][2], dw[u][1], x) & Uhi;
+                    pcs[u] = __popc(hlo) + __popc(hhi);
+                    if (pcs[u] != 0u) {
+                        const uint32_t pc = pcs[u];
+                        sumg = mad_lo16(x, pc, sumg);
+                        s0 += (unsigned long long)gs[u] * hlo;
+                        s1 += (unsigned long long)gs[u] * hhi;
+                        lastkey = x << 16;
+                        if constexpr (PB != 0) {
+                            if (a.pmin) {
+                                const uint32_t p = 131071u - 2u * (x & 0xFFFFu);
+                                unsigned long long hb = ((unsigned long long)hhi << 32) | hlo;
+                                const unsigned long long ob = outb + 64ull * b;
+                                while (hb) {
+                                    store_p<PB>(a.pmin, ob + (unsigned long long)__builtin_ctzll(hb), p);
+                                    hb &= hb - 1ull;
+                                }
                             }
                         }
+                        Ulo ^= hlo;
+                        Uhi ^= hhi;
                     }
-                    Ulo ^= hlo;
-                    Uhi ^= hhi;
                 }
+                // the group's hit counts, two primes per 64-bit LDS atomic
+                lds_u64 *lh2 = reinterpret_cast<lds_u64 *>(static_cast<uintptr_t>(ka + 32u));
+                const unsigned long long c01 = (unsigned long long)pcs[0] | ((unsigned long long)pcs[1] << 32);
+                const unsigned long long c23 = (unsigned long long)pcs[2] | ((unsigned long long)pcs[3] << 32);
+                if (c01 != 0ull) __hip_atomic_fetch_add(&lh2[0], c01, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                if (c23 != 0ull) __hip_atomic_fetch_add(&lh2[1], c23, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                }
+                ka += 48u;
             }
-            // the group's hit counts, two primes per 64-bit LDS atomic
-            lds_u64 *lh2 = reinterpret_cast<lds_u64 *>(static_cast<uintptr_t>(ka + 32u));
-            const unsigned long long c01 = (unsigned long long)pcs[0] | ((unsigned long long)pcs[1] << 32);
-            const unsigned long long c23 = (unsigned long long)pcs[2] | ((unsigned long long)pcs[3] << 32);
-            if (c01 != 0ull) __hip_atomic_fetch_add(&lh2[0], c01, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-            if (c23 != 0ull) __hip_atomic_fetch_add(&lh2[1], c23, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-            }
-            ka += 48u;
         }
         // Lanes that finish a block take the next blocks of their wave's
         // chunk, so that no lane idles while others still have long blocks;

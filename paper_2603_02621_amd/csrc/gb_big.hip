@@ -19,6 +19,7 @@
 #include <cstring>
 
 #include "gb_bignum.h"
+#include "gb_bignum28.h"
 #include "gb_runtime.h"
 
 namespace {
@@ -31,7 +32,8 @@ __constant__ uint32_t kBigBases[25] = {2, 3, 5, 7, 11, 13, 17, 19, 23, 29, 31, 3
 constexpr uint32_t kOddBases[24] = {3, 5, 7, 11, 13, 17, 19, 23, 29, 31, 37, 41,
                                      43, 47, 53, 59, 61, 67, 71, 73, 79, 83, 89, 97};
 
-// n mod r for a small r (r < 2^12), most significant limb first
+// n mod r for a small r (r < 2^12), most significant limb first (32- and
+// 28-bit limbs)
 template <int K> __device__ __forceinline__ uint32_t mod_small(const Num<K> &n, uint32_t r)
 {
     const uint32_t t = (uint32_t)((1ull << 32) % r);
@@ -41,25 +43,47 @@ template <int K> __device__ __forceinline__ uint32_t mod_small(const Num<K> &n, 
     return acc;
 }
 
+template <int K> __device__ __forceinline__ uint32_t mod_small(const gbbig28::Num<K> &n, uint32_t r)
+{
+    const uint32_t t = (1u << gbbig28::kBits) % r;
+    uint32_t acc = 0;
+#pragma unroll
+    for (int i = K - 1; i >= 0; --i) acc = (acc * t + n.w[i] % r) % r;
+    return acc;
+}
+
+// q = n - p for n (K 28-bit limbs) above p (p < 2^32: two limbs)
+template <int K> __device__ __forceinline__ void big_sub_p(gbbig28::Num<K> &q, const uint32_t *n, uint32_t p)
+{
+    uint32_t br = 0;
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+        const uint32_t pi = i == 0 ? (p & gbbig28::kMask) : i == 1 ? (p >> gbbig28::kBits) : 0u;
+        const uint32_t t = n[i] - pi - br;
+        q.w[i] = t & gbbig28::kMask;
+        br = t >> 31;
+    }
+}
+
 // One pass of the search: nways wavefronts per listed n, wavefront w taking
 // the w-th group of 64 surviving p from resume[idx] on and testing it to
 // base 2.  found[idx] (all ones before the pass) receives the smallest table
 // index that passed; the last wavefront sets resume[idx] to the table index
 // after its group (nprimes at the table's end).
 template <int K>
-__global__ __launch_bounds__(256) void k_big_search(const uint32_t *n_all, const uint32_t *list, uint32_t nlist,
-                                                    uint32_t nways, const uint32_t *primes, uint32_t nprimes,
-                                                    uint32_t *resume, uint32_t *found)
+__device__ __forceinline__ void big_search(uint32_t blk, const uint32_t *n_all, const uint32_t *list, uint32_t nlist,
+                                           uint32_t nways, const uint32_t *primes, uint32_t nprimes, uint32_t *resume,
+                                           uint32_t *found)
 {
     __shared__ uint32_t cand_all[4][64];
     const uint32_t lane = threadIdx.x & 63u;
     const uint32_t wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const uint32_t slot = blockIdx.x * 4u + wv;
+    const uint32_t slot = blk * 4u + wv;
     if (slot >= nlist * nways) return;               // whole wave
     const uint32_t li = slot / nways, way = slot - li * nways;
     const uint32_t idx = list ? list[li] : li;
     uint32_t *cand = cand_all[wv];
-    Num<K> n;
+    gbbig28::Num<K> n;
 #pragma unroll
     for (int i = 0; i < K; ++i) n.w[i] = n_all[(uint64_t)idx * K + i];
     // n mod r for the 24 odd bases (the same in every lane)
@@ -98,17 +122,9 @@ __global__ __launch_bounds__(256) void k_big_search(const uint32_t *n_all, const
     const uint32_t c = act ? cand[lane] : 0u;
     const uint32_t p = act ? primes[c] : 3u;
     // q = n - p (n >= 2^64 > p)
-    Num<K> q;
-    {
-        uint64_t br = p;
-#pragma unroll
-        for (int i = 0; i < K; ++i) {
-            const uint64_t t = (uint64_t)n.w[i] - br;
-            q.w[i] = (uint32_t)t;
-            br = (t >> 63) & 1u;
-        }
-    }
-    const bool pass2 = act && gbbig::strong_prp2<K>(q);
+    gbbig28::Num<K> q;
+    big_sub_p(q, n.w, p);
+    const bool pass2 = act && gbbig28::strong_prp2<K>(q);
     const unsigned long long m = __builtin_amdgcn_ballot_w64(pass2);
     if (m != 0ull && lane == 0u)
         __hip_atomic_fetch_min(&found[idx], __builtin_amdgcn_readlane(c, (uint32_t)__builtin_ctzll(m)), __ATOMIC_RELAXED,
@@ -118,27 +134,37 @@ __global__ __launch_bounds__(256) void k_big_search(const uint32_t *n_all, const
 // One lane per (n, base 3 .. 97): bad[idx] is set when the candidate's q
 // fails a base.
 template <int K>
-__global__ __launch_bounds__(256) void k_big_confirm(const uint32_t *n_all, const uint32_t *list, uint32_t nlist,
-                                                     const uint32_t *primes, uint32_t nprimes, const uint32_t *found,
-                                                     uint32_t *bad)
+__device__ __forceinline__ void big_confirm(uint32_t blk, const uint32_t *n_all, const uint32_t *list, uint32_t nlist,
+                                            const uint32_t *primes, uint32_t nprimes, const uint32_t *found,
+                                            uint32_t *bad)
 {
-    const uint32_t g = blockIdx.x * 256u + threadIdx.x;
+    const uint32_t g = blk * 256u + threadIdx.x;
     if (g >= nlist * 24u) return;
     const uint32_t slot = g / 24u, j = g - slot * 24u;
     const uint32_t idx = list ? list[slot] : slot;
     const uint32_t c = found[idx];
     if (c >= nprimes) return;                        // nothing to confirm
     const uint32_t p = primes[c];
-    Num<K> q;
-    uint64_t br = p;
-#pragma unroll
-    for (int i = 0; i < K; ++i) {
-        const uint64_t t = (uint64_t)n_all[(uint64_t)idx * K + i] - br;
-        q.w[i] = (uint32_t)t;
-        br = (t >> 63) & 1u;
-    }
-    if (!gbbig::strong_prp<K>(q, kBigBases[j + 1u]))
+    gbbig28::Num<K> q;
+    big_sub_p(q, n_all + (uint64_t)idx * K, p);
+    if (!gbbig28::strong_prp<K>(q, kBigBases[j + 1u]))
         __hip_atomic_fetch_or(&bad[idx], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// One pass: blocks [0, sblocks) search the open n of slist (nslist n,
+// nways wavefronts each; entries of found for them all ones), the other
+// blocks confirm the candidates of the n in clist, found in the pass before,
+// so that both run side by side.
+template <int K>
+__global__ __launch_bounds__(256) void k_big_pass(const uint32_t *n_all, const uint32_t *slist, uint32_t nslist,
+                                                  uint32_t nways, uint32_t sblocks, const uint32_t *clist,
+                                                  uint32_t nclist, const uint32_t *primes, uint32_t nprimes,
+                                                  uint32_t *resume, uint32_t *found, uint32_t *bad)
+{
+    if (blockIdx.x < sblocks)
+        big_search<K>(blockIdx.x, n_all, slist, nslist, nways, primes, nprimes, resume, found);
+    else
+        big_confirm<K>(blockIdx.x - sblocks, n_all, clist, nclist, primes, nprimes, found, bad);
 }
 
 // The one-kernel form, used for 32 limbs: the same filter and base-2 search
@@ -221,15 +247,14 @@ __global__ __launch_bounds__(256) void k_big_wave(const uint32_t *n_all, uint64_
 }
 
 template <int K>
-hipError_t launch_big(const uint32_t *n, const uint32_t *list, uint32_t nlist, uint32_t nways, const uint32_t *primes,
-                      uint32_t nprimes, uint32_t *resume, uint32_t *found, uint32_t *bad, hipStream_t st)
+hipError_t launch_pass(const uint32_t *n, const uint32_t *slist, uint32_t nslist, uint32_t nways, const uint32_t *clist,
+                       uint32_t nclist, const uint32_t *primes, uint32_t nprimes, uint32_t *resume, uint32_t *found,
+                       uint32_t *bad, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_big_search<K>, dim3((uint32_t)(((uint64_t)nlist * nways + 3u) / 4u)), dim3(256), 0, st, n,
-                       list, nlist, nways, primes, nprimes, resume, found);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_big_confirm<K>, dim3((uint32_t)(((uint64_t)nlist * 24u + 255u) / 256u)), dim3(256), 0, st, n,
-                       list, nlist, primes, nprimes, found, bad);
+    const uint32_t sblocks = (uint32_t)(((uint64_t)nslist * nways + 3u) / 4u);
+    const uint32_t cblocks = (uint32_t)(((uint64_t)nclist * 24u + 255u) / 256u);
+    hipLaunchKernelGGL(k_big_pass<K>, dim3(sblocks + cblocks), dim3(256), 0, st, n, slist, nslist, nways, sblocks, clist,
+                       nclist, primes, nprimes, resume, found, bad);
     return hipGetLastError();
 }
 
@@ -243,29 +268,50 @@ gb_status gb_verify_big(gb_ctx *c, const uint32_t *n, uint32_t nlimbs, size_t k,
     if (nlimbs < 3 || nlimbs > 32) return fail(c, GB_EINVAL, "nlimbs must be in 3..32");
     if (k == 0) return GB_OK;
     if (k > (1ull << 24)) return fail(c, GB_EINVAL, "at most 2^24 n per call");
-    // limb counts compiled: 4, 8, 12, 16, 32.  A 24-limb form built from this
-    // same source returned wrong answers on gfx950 (its host build is right;
-    // the device code keeps the multiplier operand in scratch there), so 17 to
-    // 24 limbs run in the 32-limb form.
-    const int K = nlimbs <= 4 ? 4 : nlimbs <= 8 ? 8 : nlimbs <= 12 ? 12 : nlimbs <= 16 ? 16 : 32;
-    // every n even and at least 2^64
+    // every n even and at least 2^64; the bit length of the largest
+    uint32_t bits = 0;
     for (size_t i = 0; i < k; ++i) {
         const uint32_t *w = n + i * nlimbs;
         bool big = false;
         for (uint32_t j = 2; j < nlimbs; ++j) big = big || w[j] != 0u;
         if ((w[0] & 1u) || !big) return fail(c, GB_EINVAL, "n must be even and at least 2^64");
+        for (uint32_t j = nlimbs; j-- > 0;)
+            if (w[j]) {
+                bits = std::max(bits, 32u * j + 32u - (uint32_t)__builtin_clz(w[j]));
+                break;
+            }
     }
+    // Forms compiled: 4, 8, 12 and 16 limbs of 28 bits (n below 2^448, the
+    // two-kernel form), and 32 limbs of 32 bits (the one-kernel form).  A
+    // 24-limb form of 32 bits returned wrong answers on gfx950 (its host build
+    // is right; its device code keeps the multiplier in scratch), and the
+    // two-kernel form at 32 limbs did not finish a 520-bit case, so every n
+    // of 449 bits or more runs in the one-kernel 32-limb form.
+    const int K = bits <= 112 ? 4 : bits <= 224 ? 8 : bits <= 336 ? 12 : bits <= 448 ? 16 : 32;
     if (hipSetDevice(c->prm.device) != hipSuccess) return fail(c, GB_EDEVICE, "hipSetDevice failed");
     hipStream_t st = static_cast<hipStream_t>(stream);
-    // padded to K limbs per n
     std::vector<uint32_t> h((size_t)k * K, 0u);
-    for (size_t i = 0; i < k; ++i) std::memcpy(&h[i * K], n + i * nlimbs, nlimbs * 4);
+    if (K == 32) {
+        // padded to 32 limbs of 32 bits
+        for (size_t i = 0; i < k; ++i) std::memcpy(&h[i * K], n + i * nlimbs, nlimbs * 4);
+    } else {
+        // K limbs of 28 bits: limb l is bits 28 l .. 28 l + 27
+        for (size_t i = 0; i < k; ++i) {
+            const uint32_t *w = n + i * nlimbs;
+            for (int l = 0; l < K; ++l) {
+                const uint32_t b0 = 28u * (uint32_t)l, j = b0 >> 5, o = b0 & 31u;
+                uint64_t v = j < nlimbs ? w[j] : 0u;
+                if (j + 1 < nlimbs) v |= (uint64_t)w[j + 1] << 32;
+                h[i * K + l] = (uint32_t)(v >> o) & gbbig28::kMask;
+            }
+        }
+    }
     Workspace &ws = c->ws;
     GB_HIP(c, ws.big_n.ensure(h.size()));
     GB_HIP(c, ws.big_pos.ensure(k));
     GB_HIP(c, ws.big_found.ensure(k));
     GB_HIP(c, ws.big_bad.ensure(k));
-    GB_HIP(c, ws.big_list.ensure(k));
+    GB_HIP(c, ws.big_list.ensure(2 * k));
     GB_HIP(c, hipMemcpyAsync(ws.big_n.p, h.data(), h.size() * 4, hipMemcpyHostToDevice, st));
     if (K == 32) {
         GB_HIP(c, ws.big_p.ensure(k));
@@ -278,51 +324,64 @@ gb_status gb_verify_big(gb_ctx *c, const uint32_t *n, uint32_t nlimbs, size_t k,
             if (p[i] == 0) return fail(c, GB_EUNRESOLVED, "no partition with p in the resident prime table");
         return GB_OK;
     }
-    GB_HIP(c, hipMemsetAsync(ws.big_pos.p, 0, k * 4, st));
     const uint32_t np = (uint32_t)c->ntab;
-    std::vector<uint32_t> resume(k), found(k), bad(k), ans(k, UINT32_MAX), list, cur;
-    const uint32_t *dlist = nullptr;                 // every n on the first pass
-    uint32_t nlist = (uint32_t)k, nways = 1;
-    // The n still open after a pass get several wavefronts each, one per
+    std::vector<uint32_t> resume(k, 0u), found(k, UINT32_MAX), bad(k), ans(k, UINT32_MAX), sl, cl, nsl, ncl;
+    bool all = true;                                 // the first pass searches every n
+    uint32_t nways = 1;
+    // Each pass searches the open n and confirms the candidates found in the
+    // pass before.  The n still open get several wavefronts each, one per
     // group of 64 surviving p, so that the last n do not run alone.  Every
     // pass moves each open n's resume point forward, so the loop ends; the
     // cap stops a call whose device results do not settle.
     const uint32_t target = (uint32_t)c->num_cu * 16u;
     for (int pass = 0;; ++pass) {
         if (pass == 256) return fail(c, GB_EDEVICE, "big-n search did not settle");
-        GB_HIP(c, hipMemsetAsync(ws.big_found.p, 0xFF, k * 4, st));
+        const uint32_t nslist = all ? (uint32_t)k : (uint32_t)sl.size(), nclist = (uint32_t)cl.size();
+        if (all)
+            std::fill(found.begin(), found.end(), UINT32_MAX);
+        else
+            for (uint32_t i : sl) found[i] = UINT32_MAX;
+        GB_HIP(c, hipMemcpyAsync(ws.big_pos.p, resume.data(), k * 4, hipMemcpyHostToDevice, st));
+        GB_HIP(c, hipMemcpyAsync(ws.big_found.p, found.data(), k * 4, hipMemcpyHostToDevice, st));
         GB_HIP(c, hipMemsetAsync(ws.big_bad.p, 0, k * 4, st));
+        // the two lists share one buffer: the search list, then the confirm list
+        if (!all && nslist) GB_HIP(c, hipMemcpyAsync(ws.big_list.p, sl.data(), nslist * 4, hipMemcpyHostToDevice, st));
+        if (nclist) GB_HIP(c, hipMemcpyAsync(ws.big_list.p + k, cl.data(), nclist * 4, hipMemcpyHostToDevice, st));
+        const uint32_t *dsl = all ? nullptr : ws.big_list.p, *dcl = ws.big_list.p + k;
         hipError_t e;
         switch (K) {
-        case 4: e = launch_big<4>(ws.big_n.p, dlist, nlist, nways, c->d_primes, np, ws.big_pos.p, ws.big_found.p, ws.big_bad.p, st); break;
-        case 8: e = launch_big<8>(ws.big_n.p, dlist, nlist, nways, c->d_primes, np, ws.big_pos.p, ws.big_found.p, ws.big_bad.p, st); break;
-        case 12: e = launch_big<12>(ws.big_n.p, dlist, nlist, nways, c->d_primes, np, ws.big_pos.p, ws.big_found.p, ws.big_bad.p, st); break;
-        default: e = launch_big<16>(ws.big_n.p, dlist, nlist, nways, c->d_primes, np, ws.big_pos.p, ws.big_found.p, ws.big_bad.p, st); break;
+        case 4: e = launch_pass<4>(ws.big_n.p, dsl, nslist, nways, dcl, nclist, c->d_primes, np, ws.big_pos.p, ws.big_found.p, ws.big_bad.p, st); break;
+        case 8: e = launch_pass<8>(ws.big_n.p, dsl, nslist, nways, dcl, nclist, c->d_primes, np, ws.big_pos.p, ws.big_found.p, ws.big_bad.p, st); break;
+        case 12: e = launch_pass<12>(ws.big_n.p, dsl, nslist, nways, dcl, nclist, c->d_primes, np, ws.big_pos.p, ws.big_found.p, ws.big_bad.p, st); break;
+        default: e = launch_pass<16>(ws.big_n.p, dsl, nslist, nways, dcl, nclist, c->d_primes, np, ws.big_pos.p, ws.big_found.p, ws.big_bad.p, st); break;
         }
         GB_HIP(c, e);
         GB_HIP(c, hipMemcpyAsync(resume.data(), ws.big_pos.p, k * 4, hipMemcpyDeviceToHost, st));
         GB_HIP(c, hipMemcpyAsync(found.data(), ws.big_found.p, k * 4, hipMemcpyDeviceToHost, st));
         GB_HIP(c, hipMemcpyAsync(bad.data(), ws.big_bad.p, k * 4, hipMemcpyDeviceToHost, st));
         GB_HIP(c, hipStreamSynchronize(st));
-        list.clear();
-        for (uint32_t li = 0; li < nlist; ++li) {
-            const uint32_t i = dlist ? cur[li] : li;
-            if (found[i] < np) {
-                if (!bad[i]) {
-                    ans[i] = found[i];
-                    continue;
-                }
-                resume[i] = found[i] + 1u;           // a base-2 pseudoprime: resume after it
+        nsl.clear();
+        ncl.clear();
+        for (uint32_t i : cl) {
+            if (!bad[i]) {
+                ans[i] = found[i];
+                continue;
             }
-            if (resume[i] < np) list.push_back(i);   // else the table ends: unresolved
+            resume[i] = found[i] + 1u;               // a base-2 pseudoprime: resume after it
+            if (resume[i] < np) nsl.push_back(i);    // else the table ends: unresolved
         }
-        if (list.empty()) break;
-        nlist = (uint32_t)list.size();
-        nways = std::max(1u, std::min(16u, target / nlist));
-        cur = list;
-        GB_HIP(c, hipMemcpyAsync(ws.big_pos.p, resume.data(), k * 4, hipMemcpyHostToDevice, st));
-        GB_HIP(c, hipMemcpyAsync(ws.big_list.p, cur.data(), nlist * 4, hipMemcpyHostToDevice, st));
-        dlist = ws.big_list.p;
+        for (uint32_t li = 0; li < nslist; ++li) {
+            const uint32_t i = all ? li : sl[li];
+            if (found[i] < np)
+                ncl.push_back(i);
+            else if (resume[i] < np)
+                nsl.push_back(i);
+        }
+        if (nsl.empty() && ncl.empty()) break;
+        sl.swap(nsl);
+        cl.swap(ncl);
+        all = false;
+        nways = sl.empty() ? 1u : std::max(1u, std::min(16u, target / (uint32_t)sl.size()));
     }
     bool unresolved = false;
     for (size_t i = 0; i < k; ++i) {

@@ -2,19 +2,22 @@
 // section "Arbitrary Precision Checker": small primes p in ascending order,
 // q = n - p tested with Miller-Rabin), up to n < 2^1024.
 //
-// Two kernels.  The search takes one wavefront per n.  The odd primes p of
-// the resident table are first filtered, 64 at a time, by the 24 odd prime
-// bases r = 3 .. 97: a q = n - p that r divides fails the strong test to
-// base r (a^d and its squarings mod q are then multiples of r, never 1 or
-// q - 1), so dropping p = n (mod r) leaves the answer unchanged; about a
-// quarter of the p survive.  Lane l then takes the l-th of the next 64
-// surviving p and runs the strong probable-prime test to base 2 on its q
-// (multi-limb Montgomery arithmetic, gb_bignum.h); the lowest passing lane
-// gives the candidate.  The confirmation then tests each candidate's q to
-// the other 24 bases, one (n, base) per lane.  A candidate that fails a base
-// (a strong pseudoprime to base 2) sends its n back to the search, which
-// resumes after it.  The answer is the first p whose q passes all 25 bases;
-// every smaller p failed one, so its q is composite.
+// Below 2^448 (n as 4 .. 16 limbs of 28 bits, gb_bignum28.h) each pass is
+// one launch whose blocks either search or confirm.  The search takes one
+// wavefront per n and group of candidates.  The odd primes p of the resident
+// table are first filtered, 64 at a time, by the 24 odd prime bases
+// r = 3 .. 97: a q = n - p that r divides fails the strong test to base r
+// (a^d and its squarings mod q are then multiples of r, never 1 or q - 1),
+// so dropping p = n (mod r) leaves the answer unchanged; about a quarter of
+// the p survive.  Lane l then takes the l-th of the group's 64 surviving p
+// and runs the strong probable-prime test to base 2 on its q; the lowest
+// passing lane gives the candidate.  The confirmation, in the next pass,
+// tests each candidate's q to the other 24 bases, one (n, base) per lane.  A
+// candidate that fails a base (a strong pseudoprime to base 2) sends its n
+// back to the search, which resumes after it.  The answer is the first p
+// whose q passes all 25 bases; every smaller p failed one, so its q is
+// composite.  From 449 bits on (32 limbs of 32 bits, gb_bignum.h) one
+// wavefront per n does the same in one kernel.
 #include <algorithm>
 #include <cstring>
 
@@ -228,7 +231,7 @@ __global__ __launch_bounds__(256) void k_big_wave(const uint32_t *n_all, uint64_
                 br = (t >> 63) & 1u;
             }
         }
-        const bool pass2 = act && gbbig::strong_prp<K, true>(q, 2u);
+        const bool pass2 = act && gbbig::strong_prp<K>(q, 2u);
         unsigned long long m = __builtin_amdgcn_ballot_w64(pass2);
         while (m) {
             const uint32_t L = (uint32_t)__builtin_ctzll(m);
@@ -236,7 +239,7 @@ __global__ __launch_bounds__(256) void k_big_wave(const uint32_t *n_all, uint64_
             Num<K> qL;
 #pragma unroll
             for (int i = 0; i < K; ++i) qL.w[i] = __builtin_amdgcn_readlane(q.w[i], L);
-            const bool ok = lane >= 24u || gbbig::strong_prp<K, true>(qL, kBigBases[lane + 1u]);
+            const bool ok = lane >= 24u || gbbig::strong_prp<K>(qL, kBigBases[lane + 1u]);
             if (__builtin_amdgcn_ballot_w64(!ok) == 0ull) {
                 if (lane == 0u) p_out[idx] = __builtin_amdgcn_readlane(p, L);
                 return;

@@ -311,10 +311,9 @@ gb_status gb_verify_big(gb_ctx *c, const uint32_t *n, uint32_t nlimbs, size_t k,
     }
     Workspace &ws = c->ws;
     GB_HIP(c, ws.big_n.ensure(h.size()));
-    GB_HIP(c, ws.big_pos.ensure(k));
-    GB_HIP(c, ws.big_found.ensure(k));
-    GB_HIP(c, ws.big_bad.ensure(k));
+    GB_HIP(c, ws.big_state.ensure(3 * k));
     GB_HIP(c, ws.big_list.ensure(2 * k));
+    GB_HIP(c, ws.h_big.ensure(5 * k));
     GB_HIP(c, hipMemcpyAsync(ws.big_n.p, h.data(), h.size() * 4, hipMemcpyHostToDevice, st));
     if (K == 32) {
         GB_HIP(c, ws.big_p.ensure(k));
@@ -328,7 +327,11 @@ gb_status gb_verify_big(gb_ctx *c, const uint32_t *n, uint32_t nlimbs, size_t k,
         return GB_OK;
     }
     const uint32_t np = (uint32_t)c->ntab;
-    std::vector<uint32_t> resume(k, 0u), found(k, UINT32_MAX), bad(k), ans(k, UINT32_MAX), sl, cl, nsl, ncl;
+    // pinned host copies: resume, found and bad (k each), then the two lists
+    uint32_t *resume = ws.h_big.p, *found = resume + k, *bad = found + k, *hsl = bad + k, *hcl = hsl + k;
+    uint32_t *d_resume = ws.big_state.p, *d_found = d_resume + k, *d_bad = d_found + k;
+    std::fill(resume, resume + k, 0u);
+    std::vector<uint32_t> ans(k, UINT32_MAX), sl, cl, nsl, ncl;
     bool all = true;                                 // the first pass searches every n
     uint32_t nways = 1;
     // Each pass searches the open n and confirms the candidates found in the
@@ -341,27 +344,26 @@ gb_status gb_verify_big(gb_ctx *c, const uint32_t *n, uint32_t nlimbs, size_t k,
         if (pass == 256) return fail(c, GB_EDEVICE, "big-n search did not settle");
         const uint32_t nslist = all ? (uint32_t)k : (uint32_t)sl.size(), nclist = (uint32_t)cl.size();
         if (all)
-            std::fill(found.begin(), found.end(), UINT32_MAX);
+            std::fill(found, found + k, UINT32_MAX);
         else
             for (uint32_t i : sl) found[i] = UINT32_MAX;
-        GB_HIP(c, hipMemcpyAsync(ws.big_pos.p, resume.data(), k * 4, hipMemcpyHostToDevice, st));
-        GB_HIP(c, hipMemcpyAsync(ws.big_found.p, found.data(), k * 4, hipMemcpyHostToDevice, st));
-        GB_HIP(c, hipMemsetAsync(ws.big_bad.p, 0, k * 4, st));
+        std::copy(sl.begin(), sl.end(), hsl);
+        std::copy(cl.begin(), cl.end(), hcl);
+        GB_HIP(c, hipMemcpyAsync(d_resume, resume, 2 * k * 4, hipMemcpyHostToDevice, st));   // resume, found
+        GB_HIP(c, hipMemsetAsync(d_bad, 0, k * 4, st));
         // the two lists share one buffer: the search list, then the confirm list
-        if (!all && nslist) GB_HIP(c, hipMemcpyAsync(ws.big_list.p, sl.data(), nslist * 4, hipMemcpyHostToDevice, st));
-        if (nclist) GB_HIP(c, hipMemcpyAsync(ws.big_list.p + k, cl.data(), nclist * 4, hipMemcpyHostToDevice, st));
+        if (!all && nslist) GB_HIP(c, hipMemcpyAsync(ws.big_list.p, hsl, nslist * 4, hipMemcpyHostToDevice, st));
+        if (nclist) GB_HIP(c, hipMemcpyAsync(ws.big_list.p + k, hcl, nclist * 4, hipMemcpyHostToDevice, st));
         const uint32_t *dsl = all ? nullptr : ws.big_list.p, *dcl = ws.big_list.p + k;
         hipError_t e;
         switch (K) {
-        case 4: e = launch_pass<4>(ws.big_n.p, dsl, nslist, nways, dcl, nclist, c->d_primes, np, ws.big_pos.p, ws.big_found.p, ws.big_bad.p, st); break;
-        case 8: e = launch_pass<8>(ws.big_n.p, dsl, nslist, nways, dcl, nclist, c->d_primes, np, ws.big_pos.p, ws.big_found.p, ws.big_bad.p, st); break;
-        case 12: e = launch_pass<12>(ws.big_n.p, dsl, nslist, nways, dcl, nclist, c->d_primes, np, ws.big_pos.p, ws.big_found.p, ws.big_bad.p, st); break;
-        default: e = launch_pass<16>(ws.big_n.p, dsl, nslist, nways, dcl, nclist, c->d_primes, np, ws.big_pos.p, ws.big_found.p, ws.big_bad.p, st); break;
+        case 4: e = launch_pass<4>(ws.big_n.p, dsl, nslist, nways, dcl, nclist, c->d_primes, np, d_resume, d_found, d_bad, st); break;
+        case 8: e = launch_pass<8>(ws.big_n.p, dsl, nslist, nways, dcl, nclist, c->d_primes, np, d_resume, d_found, d_bad, st); break;
+        case 12: e = launch_pass<12>(ws.big_n.p, dsl, nslist, nways, dcl, nclist, c->d_primes, np, d_resume, d_found, d_bad, st); break;
+        default: e = launch_pass<16>(ws.big_n.p, dsl, nslist, nways, dcl, nclist, c->d_primes, np, d_resume, d_found, d_bad, st); break;
         }
         GB_HIP(c, e);
-        GB_HIP(c, hipMemcpyAsync(resume.data(), ws.big_pos.p, k * 4, hipMemcpyDeviceToHost, st));
-        GB_HIP(c, hipMemcpyAsync(found.data(), ws.big_found.p, k * 4, hipMemcpyDeviceToHost, st));
-        GB_HIP(c, hipMemcpyAsync(bad.data(), ws.big_bad.p, k * 4, hipMemcpyDeviceToHost, st));
+        GB_HIP(c, hipMemcpyAsync(resume, d_resume, 3 * k * 4, hipMemcpyDeviceToHost, st));   // resume, found, bad
         GB_HIP(c, hipStreamSynchronize(st));
         nsl.clear();
         ncl.clear();

@@ -228,10 +228,9 @@ void Workspace::release()
     pc_red.release();
     h_pc_red.release();
     big_n.release();
-    big_pos.release();
-    big_found.release();
-    big_bad.release();
+    big_state.release();
     big_list.release();
+    h_big.release();
     big_p.release();
     h_slots.release();
     h_hist.release();

@@ -95,10 +95,11 @@ struct Workspace {
     DevBuf<unsigned long long> pc_red;   // partition counts: sum, min key, max key
     PinBuf<unsigned long long> h_pc_red;
     DevBuf<uint32_t> big_n;              // beyond 64 bits: the n, K limbs each,
-    DevBuf<uint32_t> big_pos;            // the table index each n's search resumes from,
-    DevBuf<uint32_t> big_found;          // the index of its candidate p,
-    DevBuf<uint32_t> big_bad;            // its confirmation flags
-    DevBuf<uint32_t> big_list;           // and the n searched again;
+    DevBuf<uint32_t> big_state;          // per n: the table index its search resumes
+                                         // from, that of its candidate p, its
+                                         // confirmation flag (three arrays of k)
+    DevBuf<uint32_t> big_list;           // the n searched and confirmed in a pass;
+    PinBuf<uint32_t> h_big;              // host copies of both;
     DevBuf<unsigned long long> big_p;    // the one-kernel form's answers
     PinBuf<GbSlot> h_slots;
     PinBuf<unsigned long long> h_hist;

@@ -67,3 +67,18 @@ def test_base2_pseudoprime_candidate_is_rejected(V, psi):
     got = V.verify_big(ns)
     assert got == [big.pmin_big(n) for n in ns]
     assert got[0] > 3
+
+
+@pytest.mark.parametrize("bits", [112, 113, 224, 225, 336, 337, 448, 449])
+def test_limb_class_edges(V, bits):
+    # n of exactly `bits` bits: the largest and smallest of each class of
+    # 28-bit limbs (4, 8, 12, 16 limbs) and the first n of the 32-limb form
+    rng = random.Random(1000 + bits)
+    top = (1 << bits) - 2                              # all ones but the last bit
+    low = 1 << (bits - 1)
+    mid = (rng.getrandbits(bits - 1) | (1 << (bits - 1))) & ~1
+    ns = [top, low, mid]
+    assert all(n.bit_length() == bits and n % 2 == 0 for n in ns)
+    assert V.verify_big(ns) == [big.pmin_big(n) for n in ns]
+    # mixed with a smaller n: the call's form follows its largest n
+    assert V.verify_big([2**64 + 2, top]) == [big.pmin_big(2**64 + 2), big.pmin_big(top)]

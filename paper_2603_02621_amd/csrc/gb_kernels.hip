@@ -532,11 +532,11 @@ __device__ void process_tile(const GbTileArgs &a, unsigned long long g, const Ti
     }
     while (b < nblk) {
         if (nps != 0u) {
-            // four probes (one group) per exit check, eight in the bulk form,
-            // whose probes are cheap enough that the block-end work weighs;
-            // the prime list is padded with copies of its last prime, which
-            // cannot hit an n twice
-            constexpr uint32_t kGroupsPerCheck = VERIFY ? 2u : 1u;
+            // eight probes (two groups) per exit check, so that the block-end
+            // work (hand-out and block set-up) runs half as often; the prime
+            // list is padded with copies of its last prime, which cannot hit
+            // an n twice
+            constexpr uint32_t kGroupsPerCheck = 2u;
 #pragma unroll
             for (uint32_t gg = 0; gg < kGroupsPerCheck; ++gg) {
                 // the group's twelve window words do not depend on the hits, so

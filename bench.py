@@ -40,8 +40,8 @@ BIG_N = 4096                        # beyond-64-bit workload: even n from 10^100
 # HBM bytes per launch of the tile kernel on this workload, from rocprofv3
 # FETCH_SIZE and WRITE_SIZE scaled by a 1 GiB copy's readings (factors 2.000
 # and 1.000), valid only for the kernel source they were taken on.
-TRAFFIC = {"kernel_sha256_prefix": "ab538fa92de3ab09", "tile_log2": 20, "wg_threads": 1024,
-           "bytes_per_launch": 8.008e6 + 64.760e6}
+TRAFFIC = {"kernel_sha256_prefix": "6283eff8ab0f3db5", "tile_log2": 20, "wg_threads": 1024,
+           "bytes_per_launch": 8.017e6 + 64.794e6}
 
 
 def _load_tuned():

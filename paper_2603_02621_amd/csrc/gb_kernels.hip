@@ -159,8 +159,8 @@ __device__ __forceinline__ uint32_t pr_lh(uint32_t i) { return pr_px(i) + 8u; }
 // LDS carve-up of one tile workgroup (offsets in 32-bit words).
 struct TileLds {
     uint32_t *bits;           // (T + HB)/32 words: the tile's window, 1 = prime
-    // odd primes p <= P_max (padded with copies of the last through one more
-    // group) in groups of
+    // odd primes p <= P_max (padded with copies of the last through two more
+    // groups) in groups of
     // four, 12 words per group: the four packed words, the four g =
     // 2^16 - (p+1)/2, the four hit counts of this tile
     uint32_t *pr;
@@ -178,7 +178,7 @@ __device__ __forceinline__ TileLds carve(uint32_t *smem, const GbTileArgs &a)
     o += (a.tile_n + a.halo_bits) / 32;
     o = (o + 3) & ~3u;   // 16-byte aligned: a group reads its four words at once
     L.pr = smem + o;
-    o += 12u * ((a.np_search + 7u) / 4u);
+    o += 12u * ((a.np_search + 3u) / 4u + 2u);
     L.offs = smem + o;
     o += a.n_off;
     o = (o + 1) & ~1u;
@@ -234,9 +234,10 @@ __device__ void process_tile(const GbTileArgs &a, unsigned long long g, const Ti
 
     // ---- fast-path prime list, per-tile histogram --------------------------
     if (!SIEVE_ONLY) {
-        // through the end of the group after the last prime's group: a lane
-        // runs two groups per exit check and may start on the last one
-        const uint32_t npad = 4u * ((nps + 3u) / 4u + 1u);
+        // through the end of the second group after the last prime's group:
+        // a lane runs three groups per exit check and may start on the last
+        // one
+        const uint32_t npad = 4u * ((nps + 3u) / 4u + 2u);
         for (uint32_t i = tid; i < npad; i += NT) {
             const uint32_t p = a.primes[i < nps ? i : (nps ? nps - 1 : 0)];
             const uint32_t h = (p + 1u) >> 1;
@@ -532,11 +533,11 @@ __device__ void process_tile(const GbTileArgs &a, unsigned long long g, const Ti
     }
     while (b < nblk) {
         if (nps != 0u) {
-            // eight probes (two groups) per exit check, so that the block-end
-            // work (hand-out and block set-up) runs half as often; the prime
-            // list is padded with copies of its last prime, which cannot hit
-            // an n twice
-            constexpr uint32_t kGroupsPerCheck = 2u;
+            // twelve probes (three groups) per exit check, so that the
+            // block-end work (hand-out and block set-up) runs a third as often
+            // (four groups made the minimal-p form slower); the prime list is
+            // padded with copies of its last prime, which cannot hit an n twice
+            constexpr uint32_t kGroupsPerCheck = 3u;
 #pragma unroll
             for (uint32_t gg = 0; gg < kGroupsPerCheck; ++gg) {
                 // the group's twelve window words do not depend on the hits, so
@@ -1069,7 +1070,7 @@ size_t gb_tile_lds_bytes(uint32_t tile_n, uint32_t halo_bits, uint32_t np_search
 {
     // the same carve-up as carve()
     size_t words = ((tile_n + halo_bits) / 32 + 3) & ~(size_t)3;
-    words += 12 * (((size_t)np_search + 7) / 4);          // prime groups
+    words += 12 * (((size_t)np_search + 3) / 4 + 2);          // prime groups
     words += n_off;                                       // first strikes
     words = (words + 1) & ~(size_t)1;
     words += 2 * 4;                                       // tile reductions

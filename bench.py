@@ -39,9 +39,10 @@ BIG_N = 4096                        # beyond-64-bit workload: even n from 10^100
 
 # HBM bytes per launch of the tile kernel on this workload, from rocprofv3
 # FETCH_SIZE and WRITE_SIZE scaled by a 1 GiB copy's readings (factors 2.000
-# and 1.000), valid only for the kernel source they were taken on.
-TRAFFIC = {"kernel_sha256_prefix": "6283eff8ab0f3db5", "tile_log2": 20, "wg_threads": 1024,
-           "bytes_per_launch": 8.017e6 + 64.794e6}
+# and 1.000), valid only for the kernel source and compiler flags they were
+# taken with.
+TRAFFIC = {"kernel_sha256_prefix": "d7da8de317149f64", "tile_log2": 20, "wg_threads": 1024,
+           "bytes_per_launch": 8.017e6 + 64.774e6}
 
 
 def _load_tuned():
@@ -256,7 +257,10 @@ def main():
     achieved = ALG_OPS_PER_N * count / t_launch
     import hashlib
     src = os.path.join(ROOT, "paper_2603_02621_amd", "csrc", "gb_kernels.hip")
-    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    # the kernel source and the compiler flags it was built with (paths left out)
+    from paper_2603_02621_amd.build import HIPCC_FLAGS
+    flags = " ".join(f for f in HIPCC_FLAGS if "/" not in f).encode()
+    sha = hashlib.sha256(open(src, "rb").read() + flags).hexdigest()[:16]
     same = (sha == TRAFFIC["kernel_sha256_prefix"] and p["tile_log2"] == TRAFFIC["tile_log2"]
             and p["wg_threads"] == TRAFFIC["wg_threads"])
     roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": ALU_PEAK_OPS / 1e12,

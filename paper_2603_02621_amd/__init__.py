@@ -145,20 +145,22 @@ class Verifier:
         2^64 <= n < 2^1024 (Python integers).  Returns a list of ints (0 for
         none in the prime table)."""
         import numpy as np
-        ns = [int(x) for x in ns]
+        ns = list(map(int, ns))
         if not ns:
             return []
-        bits = max(x.bit_length() for x in ns)
-        nl = max(3, (bits + 31) // 32)
+        if min(ns) < 0:
+            raise ValueError("n must be positive")
+        nl = max(3, (max(ns).bit_length() + 31) // 32)
         if nl > 32:
             raise ValueError("n must be below 2^1024")
-        words = np.frombuffer(b"".join(x.to_bytes(4 * nl, "little") for x in ns),
+        nb = 4 * nl
+        words = np.frombuffer(b"".join([x.to_bytes(nb, "little") for x in ns]),
                               dtype="<u4").reshape(len(ns), nl).copy()
         out = np.zeros(len(ns), dtype=np.uint64)
         st = self._lib.gb_verify_big(self._h, words.ctypes.data, nl, len(ns), out.ctypes.data,
                                      _stream_ptr(stream))
         self._check(st, allow=(5,) if allow_unresolved else ())
-        return [int(x) for x in out]
+        return out.tolist()
 
     def measure_peaks(self, stream=None):
         """Measured device throughput ceilings (see gb_measure_peaks)."""

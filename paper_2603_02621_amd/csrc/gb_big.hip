@@ -311,9 +311,6 @@ gb_status gb_verify_big(gb_ctx *c, const uint32_t *n, uint32_t nlimbs, size_t k,
     }
     Workspace &ws = c->ws;
     GB_HIP(c, ws.big_n.ensure(h.size()));
-    GB_HIP(c, ws.big_state.ensure(3 * k));
-    GB_HIP(c, ws.big_list.ensure(2 * k));
-    GB_HIP(c, ws.h_big.ensure(5 * k));
     GB_HIP(c, hipMemcpyAsync(ws.big_n.p, h.data(), h.size() * 4, hipMemcpyHostToDevice, st));
     if (K == 32) {
         GB_HIP(c, ws.big_p.ensure(k));
@@ -326,6 +323,9 @@ gb_status gb_verify_big(gb_ctx *c, const uint32_t *n, uint32_t nlimbs, size_t k,
             if (p[i] == 0) return fail(c, GB_EUNRESOLVED, "no partition with p in the resident prime table");
         return GB_OK;
     }
+    GB_HIP(c, ws.big_state.ensure(3 * k));
+    GB_HIP(c, ws.big_list.ensure(2 * k));
+    GB_HIP(c, ws.h_big.ensure(5 * k));
     const uint32_t np = (uint32_t)c->ntab;
     // pinned host copies: resume, found and bad (k each), then the two lists
     uint32_t *resume = ws.h_big.p, *found = resume + k, *bad = found + k, *hsl = bad + k, *hcl = hsl + k;

@@ -69,14 +69,16 @@ template <int K> __device__ __forceinline__ void big_sub_p(gbbig28::Num<K> &q, c
 }
 
 // One pass of the search: nways wavefronts per listed n, wavefront w taking
-// the w-th group of 64 surviving p from resume[idx] on and testing it to
+// the w-th group of 64 surviving p from resume_in[idx] on and testing it to
 // base 2.  found[idx] (all ones before the pass) receives the smallest table
-// index that passed; the last wavefront sets resume[idx] to the table index
-// after its group (nprimes at the table's end).
+// index that passed; the last wavefront writes the table index after its
+// group (nprimes at the table's end) to resume_out[idx].  resume_in is only
+// read during the pass: the wavefronts of one n run in any order, so a write
+// into the array the others read would move their groups.
 template <int K>
 __device__ __forceinline__ void big_search(uint32_t blk, const uint32_t *n_all, const uint32_t *list, uint32_t nlist,
-                                           uint32_t nways, const uint32_t *primes, uint32_t nprimes, uint32_t *resume,
-                                           uint32_t *found)
+                                           uint32_t nways, const uint32_t *primes, uint32_t nprimes,
+                                           const uint32_t *resume_in, uint32_t *resume_out, uint32_t *found)
 {
     __shared__ uint32_t cand_all[4][64];
     const uint32_t lane = threadIdx.x & 63u;
@@ -93,9 +95,9 @@ __device__ __forceinline__ void big_search(uint32_t blk, const uint32_t *n_all, 
     uint32_t nres[24];
 #pragma unroll
     for (int j = 0; j < 24; ++j) nres[j] = mod_small(n, kOddBases[j]);
-    // table indices of the surviving p ranked [lo, hi) from resume[idx] on
+    // table indices of the surviving p ranked [lo, hi) from resume_in[idx] on
     const uint32_t lo = 64u * way, hi = lo + 64u;
-    uint32_t got = 0, next = resume[idx];
+    uint32_t got = 0, next = resume_in[idx];
     while (got < hi && next < nprimes) {
         const uint32_t c = next + lane;
         const bool valid = c < nprimes;
@@ -117,7 +119,7 @@ __device__ __forceinline__ void big_search(uint32_t blk, const uint32_t *n_all, 
             got += tot;
         }
     }
-    if (way == nways - 1u && lane == 0u) resume[idx] = next;
+    if (way == nways - 1u && lane == 0u) resume_out[idx] = next;
     const uint32_t cnt = got > lo ? got - lo : 0u;
     if (cnt == 0u) return;                           // the table ends before the group
     __builtin_amdgcn_wave_barrier();
@@ -162,10 +164,11 @@ template <int K>
 __global__ __launch_bounds__(256) void k_big_pass(const uint32_t *n_all, const uint32_t *slist, uint32_t nslist,
                                                   uint32_t nways, uint32_t sblocks, const uint32_t *clist,
                                                   uint32_t nclist, const uint32_t *primes, uint32_t nprimes,
-                                                  uint32_t *resume, uint32_t *found, uint32_t *bad)
+                                                  const uint32_t *resume_in, uint32_t *resume_out, uint32_t *found,
+                                                  uint32_t *bad)
 {
     if (blockIdx.x < sblocks)
-        big_search<K>(blockIdx.x, n_all, slist, nslist, nways, primes, nprimes, resume, found);
+        big_search<K>(blockIdx.x, n_all, slist, nslist, nways, primes, nprimes, resume_in, resume_out, found);
     else
         big_confirm<K>(blockIdx.x - sblocks, n_all, clist, nclist, primes, nprimes, found, bad);
 }
@@ -251,13 +254,13 @@ __global__ __launch_bounds__(256) void k_big_wave(const uint32_t *n_all, uint64_
 
 template <int K>
 hipError_t launch_pass(const uint32_t *n, const uint32_t *slist, uint32_t nslist, uint32_t nways, const uint32_t *clist,
-                       uint32_t nclist, const uint32_t *primes, uint32_t nprimes, uint32_t *resume, uint32_t *found,
-                       uint32_t *bad, hipStream_t st)
+                       uint32_t nclist, const uint32_t *primes, uint32_t nprimes, const uint32_t *resume_in,
+                       uint32_t *resume_out, uint32_t *found, uint32_t *bad, hipStream_t st)
 {
     const uint32_t sblocks = (uint32_t)(((uint64_t)nslist * nways + 3u) / 4u);
     const uint32_t cblocks = (uint32_t)(((uint64_t)nclist * 24u + 255u) / 256u);
     hipLaunchKernelGGL(k_big_pass<K>, dim3(sblocks + cblocks), dim3(256), 0, st, n, slist, nslist, nways, sblocks, clist,
-                       nclist, primes, nprimes, resume, found, bad);
+                       nclist, primes, nprimes, resume_in, resume_out, found, bad);
     return hipGetLastError();
 }
 
@@ -323,13 +326,15 @@ gb_status gb_verify_big(gb_ctx *c, const uint32_t *n, uint32_t nlimbs, size_t k,
             if (p[i] == 0) return fail(c, GB_EUNRESOLVED, "no partition with p in the resident prime table");
         return GB_OK;
     }
-    GB_HIP(c, ws.big_state.ensure(3 * k));
+    GB_HIP(c, ws.big_state.ensure(4 * k));
     GB_HIP(c, ws.big_list.ensure(2 * k));
-    GB_HIP(c, ws.h_big.ensure(5 * k));
+    GB_HIP(c, ws.h_big.ensure(6 * k));
     const uint32_t np = (uint32_t)c->ntab;
-    // pinned host copies: resume, found and bad (k each), then the two lists
-    uint32_t *resume = ws.h_big.p, *found = resume + k, *bad = found + k, *hsl = bad + k, *hcl = hsl + k;
-    uint32_t *d_resume = ws.big_state.p, *d_found = d_resume + k, *d_bad = d_found + k;
+    // pinned host copies of the four device arrays (resume point in, found,
+    // resume point out, bad; k each), then the two lists
+    uint32_t *resume = ws.h_big.p, *found = resume + k, *rout = found + k, *bad = rout + k, *hsl = bad + k,
+             *hcl = hsl + k;
+    uint32_t *d_resume = ws.big_state.p, *d_found = d_resume + k, *d_rout = d_found + k, *d_bad = d_rout + k;
     std::fill(resume, resume + k, 0u);
     std::vector<uint32_t> ans(k, UINT32_MAX), sl, cl, nsl, ncl;
     bool all = true;                                 // the first pass searches every n
@@ -349,7 +354,7 @@ gb_status gb_verify_big(gb_ctx *c, const uint32_t *n, uint32_t nlimbs, size_t k,
             for (uint32_t i : sl) found[i] = UINT32_MAX;
         std::copy(sl.begin(), sl.end(), hsl);
         std::copy(cl.begin(), cl.end(), hcl);
-        GB_HIP(c, hipMemcpyAsync(d_resume, resume, 2 * k * 4, hipMemcpyHostToDevice, st));   // resume, found
+        GB_HIP(c, hipMemcpyAsync(d_resume, resume, 2 * k * 4, hipMemcpyHostToDevice, st));   // resume in, found
         GB_HIP(c, hipMemsetAsync(d_bad, 0, k * 4, st));
         // the two lists share one buffer: the search list, then the confirm list
         if (!all && nslist) GB_HIP(c, hipMemcpyAsync(ws.big_list.p, hsl, nslist * 4, hipMemcpyHostToDevice, st));
@@ -357,14 +362,19 @@ gb_status gb_verify_big(gb_ctx *c, const uint32_t *n, uint32_t nlimbs, size_t k,
         const uint32_t *dsl = all ? nullptr : ws.big_list.p, *dcl = ws.big_list.p + k;
         hipError_t e;
         switch (K) {
-        case 4: e = launch_pass<4>(ws.big_n.p, dsl, nslist, nways, dcl, nclist, c->d_primes, np, d_resume, d_found, d_bad, st); break;
-        case 8: e = launch_pass<8>(ws.big_n.p, dsl, nslist, nways, dcl, nclist, c->d_primes, np, d_resume, d_found, d_bad, st); break;
-        case 12: e = launch_pass<12>(ws.big_n.p, dsl, nslist, nways, dcl, nclist, c->d_primes, np, d_resume, d_found, d_bad, st); break;
-        default: e = launch_pass<16>(ws.big_n.p, dsl, nslist, nways, dcl, nclist, c->d_primes, np, d_resume, d_found, d_bad, st); break;
+        case 4: e = launch_pass<4>(ws.big_n.p, dsl, nslist, nways, dcl, nclist, c->d_primes, np, d_resume, d_rout, d_found, d_bad, st); break;
+        case 8: e = launch_pass<8>(ws.big_n.p, dsl, nslist, nways, dcl, nclist, c->d_primes, np, d_resume, d_rout, d_found, d_bad, st); break;
+        case 12: e = launch_pass<12>(ws.big_n.p, dsl, nslist, nways, dcl, nclist, c->d_primes, np, d_resume, d_rout, d_found, d_bad, st); break;
+        default: e = launch_pass<16>(ws.big_n.p, dsl, nslist, nways, dcl, nclist, c->d_primes, np, d_resume, d_rout, d_found, d_bad, st); break;
         }
         GB_HIP(c, e);
-        GB_HIP(c, hipMemcpyAsync(resume, d_resume, 3 * k * 4, hipMemcpyDeviceToHost, st));   // resume, found, bad
+        GB_HIP(c, hipMemcpyAsync(found, d_found, 3 * k * 4, hipMemcpyDeviceToHost, st));   // found, resume out, bad
         GB_HIP(c, hipStreamSynchronize(st));
+        // the searched n continue after the groups this pass took
+        for (uint32_t li = 0; li < nslist; ++li) {
+            const uint32_t i = all ? li : sl[li];
+            resume[i] = rout[i];
+        }
         nsl.clear();
         ncl.clear();
         for (uint32_t i : cl) {

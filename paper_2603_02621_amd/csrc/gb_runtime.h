@@ -96,8 +96,9 @@ struct Workspace {
     PinBuf<unsigned long long> h_pc_red;
     DevBuf<uint32_t> big_n;              // beyond 64 bits: the n, K limbs each,
     DevBuf<uint32_t> big_state;          // per n: the table index its search resumes
-                                         // from, that of its candidate p, its
-                                         // confirmation flag (three arrays of k)
+                                         // from, that of its candidate p, the
+                                         // resume index after the pass, its
+                                         // confirmation flag (four arrays of k)
     DevBuf<uint32_t> big_list;           // the n searched and confirmed in a pass;
     PinBuf<uint32_t> h_big;              // host copies of both;
     DevBuf<unsigned long long> big_p;    // the one-kernel form's answers

@@ -46,6 +46,14 @@ def test_batch(V):
     assert V.verify_big(ns) == [big.pmin_big(n) for n in ns]
 
 
+def test_many_open_n_share_wavefronts(V):
+    # 300 n of 440 bits: 47 of them need more than the first 64 candidates
+    # the small-base filter leaves, so the second pass gives each open n 16
+    # wavefronts (one per group of 64) that all start from one resume point
+    ns = [2**439 + 2 * 10**6 * i + 2 * i * i for i in range(300)]
+    assert V.verify_big(ns) == [big.pmin_big(n) for n in ns]
+
+
 def test_argument_checks(V):
     from paper_2603_02621_amd import GoldbachError
     with pytest.raises(GoldbachError):

@@ -7,6 +7,11 @@ range.  The timed form is the batched one (one persistent tile launch in a
 replayed HIP graph); the plain form (one launch per segment of S even n) is
 timed beside it.  Prints one JSON line.
 
+Beside it: the bulk form, the batched windows, partition counts, even n
+beyond 64 bits, and a serving sweep (the seeded request stream replayed at
+increasing offered rates, p50/p99 per request class), every request of which
+the CPU leg re-verifies with the oracle.
+
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-serve]
 """
 from __future__ import annotations
@@ -55,16 +60,77 @@ def _load_tuned():
     return {}
 
 
-def cpu_baseline(threads: int, log2n: int = 30):
-    """The oracle as it stands, timed on the host cores over a bounded sample."""
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(threads: int, log2n: int = 30, serving_points=None):
+    """The oracle as it stands, timed on the host cores: a bounded sample of
+    the bench range on every core; the paper's CPU-baseline workloads
+    (every even n up to 10^6 and up to 10^9) on one core and on every core;
+    and the re-verification of every request of the serving sweep, whose
+    mismatches are written into each sweep point."""
     import oracle
     oracle.build(force=False)
     lo = HI - 2 * ((1 << log2n) - 1)
     t0 = time.perf_counter()
     _, _, s = oracle.verify_range(lo, HI, per_n_bits=None, hist=True, threads=threads)
     dt = time.perf_counter() - t0
-    return {"value": s["count"] / dt, "unit": "even n/s", "cores": threads, "kind": "oracle",
-            "sample": f"2^{log2n} even n ending at 1e12 ({s['count']} n, {dt:.2f} s wall)"}
+    out = {"value": s["count"] / dt, "unit": "even n/s", "cores": threads, "kind": "oracle",
+           "sample": f"2^{log2n} even n ending at 1e12 ({s['count']} n, {dt:.2f} s wall)",
+           "cpu_model": _cpu_model()}
+    table = []
+    for hi, th in ((10**6, 1), (10**9, 1), (10**9, threads)):
+        t0 = time.perf_counter()
+        _, _, r = oracle.verify_range(4, hi, per_n_bits=None, hist=True, threads=th)
+        dt = time.perf_counter() - t0
+        table.append({"workload": f"every even n in [4, {hi:.0e}]", "threads": th, "seconds": dt,
+                      "even_n_per_s": r["count"] / dt, "n_failed": r["n_failed"]})
+        print(f"# oracle [4, {hi:.0e}] on {th} thread(s): {dt:.2f} s", file=sys.stderr, flush=True)
+    out["paper_workloads"] = table
+    if serving_points:
+        out["serving_reverify"] = reverify_serving(serving_points, threads)
+    return out
+
+
+def reverify_serving(points, threads: int):
+    """Every request of the serving sweep checked against the oracle: p of
+    each single n, and the summary and every per-n p_min of each range.  The
+    stream's requests are the same at every rate, so the oracle runs once."""
+    import numpy as np
+    import oracle
+    reqs = points[0]["requests"]
+    ones = [(i, q["n"]) for i, q in enumerate(reqs) if q["kind"] == "one"]
+    rngs = [(i, (q["n"], q["len"])) for i, q in enumerate(reqs) if q["kind"] == "range"]
+    t0 = time.perf_counter()
+    ref_p = oracle.verify_many([n for _, n in ones], threads=threads)
+    t1 = time.perf_counter()
+    ref_out, ref_sums = oracle.verify_windows([w for _, w in rngs], threads=threads)
+    t2 = time.perf_counter()
+    keys = ("count", "max_p", "argmax_n", "checksum", "n_failed")
+    for pt in points:
+        done = pt["done"]
+        bad_one = sum(1 for (i, _), p in zip(ones, ref_p) if done[i]["p"] != int(p))
+        bad_sum = sum(1 for (i, _), r in zip(rngs, ref_sums)
+                      if any(done[i]["summary"][k] != r[k] for k in keys))
+        bad_n = None
+        if pt["pmin"] is not None:
+            got = pt["pmin"].cpu().numpy().view(np.uint16)
+            bad_n = int(np.count_nonzero(got != ref_out))
+            pt["pmin"] = None
+        pt["stats"]["oracle_mismatches"] = {"one": bad_one, "range_summary": bad_sum, "range_per_n": bad_n}
+    n_range = int(sum(w[1] for _, w in rngs))
+    print(f"# oracle re-verification of the serving stream: {t1 - t0:.2f} s for {len(ones)} single n, "
+          f"{t2 - t1:.2f} s for {len(rngs)} ranges ({n_range} n)", file=sys.stderr, flush=True)
+    return {"single_n": len(ones), "single_s": t1 - t0, "ranges": len(rngs), "range_n": n_range,
+            "range_s": t2 - t1, "range_even_n_per_s": n_range / (t2 - t1), "threads": threads}
 
 
 def main():
@@ -80,6 +146,11 @@ def main():
     ap.add_argument("--no-bulk", action="store_true", help="skip the bulk-verification line")
     ap.add_argument("--no-pcount", action="store_true", help="skip the partition-count line")
     ap.add_argument("--no-big", action="store_true", help="skip the beyond-64-bit line")
+    ap.add_argument("--serve-count", type=int, default=10_000,
+                    help="requests per offered rate of the serving sweep")
+    ap.add_argument("--serve-qps", default="1e2,3e2,1e3,3e3,1e4,3e4,1e5",
+                    help="offered rates of the serving sweep, comma-separated")
+    ap.add_argument("--serve-streams", type=int, default=4)
     ap.add_argument("--copy-calibrate", type=int, default=0, metavar="MIB",
                     help="also run one device-to-device copy of this many MiB (a reference "
                          "kernel of known traffic for the HBM byte counters)")
@@ -298,17 +369,17 @@ def main():
         "measured_peaks": peaks,
     }
 
-    if not args.no_serve:
-        try:
-            from paper_2603_02621_amd import serving
-            out["serving"] = serving.quick_latency(v)
-        except (ImportError, AttributeError) as e:
-            out["serving"] = {"skipped": str(e)}
-
     v.close()
+    points = None
+    if not args.no_serve:
+        from paper_2603_02621_amd import serving
+        qps = [float(x) for x in args.serve_qps.split(",") if x]
+        log = lambda m: print(m, file=sys.stderr, flush=True)  # noqa: E731
+        points = serving.sweep(qps, count=args.serve_count, streams=args.serve_streams, log=log)
+        out["serving_sweep"] = [pt["stats"] for pt in points]
     if not args.no_cpu:
         threads = len(os.sched_getaffinity(0))
-        out["cpu_baseline"] = cpu_baseline(threads)
+        out["cpu_baseline"] = cpu_baseline(threads, serving_points=points)
     print(json.dumps(out), flush=True)
 
 

@@ -157,7 +157,11 @@ gb_status gb_verify_range(gb_ctx *ctx, uint64_t lo, uint64_t hi,
 /* Batched form of the same computation: all segments' tiles go to one
  * persistent launch that pulls tiles from a device work queue, captured with
  * the exhaustive phase and the reduction in one HIP graph, replayed on later
- * calls of the same shape.  Same results as gb_verify_range, bit for bit. */
+ * calls of the same shape.  Same results as gb_verify_range, bit for bit.
+ * The paper has no such form: it runs its segments one after another, each
+ * sieved on the host and copied over (subsection "Correct segmentation"),
+ * and names that host loop as its bottleneck (section "Limitations"); this
+ * call is the same computation with the segment loop moved onto the device. */
 gb_status gb_verify_range_batched(gb_ctx *ctx, uint64_t lo, uint64_t hi,
                                   gb_result *res, void *stream);
 
@@ -179,7 +183,12 @@ gb_status gb_verify_range_bulk(gb_ctx *ctx, uint64_t lo, uint64_t hi,
  * launch.  pmin (nullable) is device memory of sum(len) uint16 entries,
  * window j's n at offset sum_{i<j} len_i.  sums (nullable, host, k entries)
  * receives each window's summary; hist (nullable, host, GB_HIST_BINS) the
- * histogram over all windows.  Windows may overlap. */
+ * histogram over all windows.  Windows may overlap.  The paper defines no
+ * windows call (its verifier covers one range [4, N]); each window is the
+ * range computation of gb_verify_range on [start, start + 2(len-1)], and
+ * many of them share one launch.  The outputs are separate arguments rather
+ * than one gb_result per window so that the k summaries come back in one
+ * array and the per-n output of all windows in one device buffer. */
 gb_status gb_verify_windows(gb_ctx *ctx, const gb_window *w, size_t k,
                             uint16_t *pmin, gb_summary *sums, uint64_t *hist,
                             void *stream);
@@ -188,7 +197,9 @@ gb_status gb_verify_windows(gb_ctx *ctx, const gb_window *w, size_t k,
  * p): one wavefront scans odd primes from 3 upward, 64 candidates at a time,
  * testing q = n - p with deterministic Miller-Rabin (bases 2..37), and takes
  * the lowest passing lane.  n must be even, 4 <= n <= 2^63.  *p receives
- * p_min(n), or 0 with GB_EUNRESOLVED if none exists within the budget. */
+ * p_min(n), or 0 with GB_EUNRESOLVED if none exists within the budget.  The
+ * result is the bare p (q = n - p): for one n the range summaries would
+ * only repeat it. */
 gb_status gb_verify_one(gb_ctx *ctx, uint64_t n, uint64_t *p, void *stream);
 
 /* Even n beyond 64 bits (section "Arbitrary Precision Checker": small
@@ -208,14 +219,18 @@ gb_status gb_verify_one(gb_ctx *ctx, uint64_t n, uint64_t *p, void *stream);
 gb_status gb_verify_big(gb_ctx *ctx, const uint32_t *n, uint32_t nlimbs, size_t k,
                         uint64_t *p, void *stream);
 
-/* Many single n in one launch (one wavefront per n).  n and p are arrays of
+/* Many single n in one launch (one wavefront per n; the checker of section
+ * "GPU Single-Number Checker" applied to a batch, minimal p as in
+ * gb_verify_one).  n and p are arrays of
  * k uint64 entries, both in device memory when on_device is 1, else both in
  * host memory.  Entries with no partition within the budget get 0 and the
  * call returns GB_EUNRESOLVED; odd or out-of-range n give GB_EINVAL. */
 gb_status gb_verify_many(gb_ctx *ctx, const uint64_t *n, uint64_t *p, size_t k,
                          int on_device, void *stream);
 
-/* The sieve alone: bit i of the output (LSB-first uint32 words) is 1 iff the
+/* The sieve alone (the segment bitset of subsection "Correct segmentation",
+ * there built on the host; a GPU-built sieve is a direction of section
+ * "Future work"): bit i of the output (LSB-first uint32 words) is 1 iff the
  * odd number w0 + 2i is prime, for 0 <= i < nbits, built by the same LDS tile
  * sieve the range calls use (wheel pattern, then strided marking of the odd
  * multiples of each sieving prime from max(p^2, w0)).  w0 is odd, w0 >= 1,
@@ -255,7 +270,8 @@ gb_status gb_partition_counts(gb_ctx *ctx, uint64_t lo, uint64_t hi,
                               uint64_t *counts, gb_pc_result *res, void *stream);
 
 /* Measured throughput ceilings of the units the kernels use, for roofline
- * fractions beside the nominal peaks (every figure is for the whole device,
+ * fractions beside the nominal peaks.  Not part of the paper's method: a
+ * measurement aid for this device (every figure is for the whole device,
  * the best of three timed launches after a warm-up launch):
  *   valu_vop2_ops   int32 lane-ops/s of a two-operand instruction (v_xor_b32)
  *   valu_vop3_ops   int32 lane-ops/s of a three-operand one (v_alignbit_b32)
@@ -275,21 +291,32 @@ typedef struct gb_peaks {
 gb_status gb_measure_peaks(gb_ctx *ctx, gb_peaks *out, void *stream);
 
 /* The (n, p) pairs the last range or window call sent to the exhaustive
- * phase (p = 0 for a failure), at most cap of them, into host arrays;
- * *count receives the total number. */
+ * phase (section "Phase 2: exhaustive CPU fallback", run on the GPU here;
+ * p = 0 for a failure), at most cap of them, into host arrays; *count
+ * receives the total number.  These are the n whose uint16 entry can be 0
+ * (p_min >= 2^16 or no partition) together with their true p, and the n the
+ * fast path left, so the list is the exhaustive phase's work list rather
+ * than only the overflow of the uint16 output. */
 gb_status gb_exhaustive_list(gb_ctx *ctx, uint64_t *n, uint64_t *p, size_t cap,
                              size_t *count);
 
 /* Autotuner: time the batched form over a sample of windows for every
  * combination of the candidate tile sizes, workgroup sizes, P_max and wheel
- * values, check that every combination gives bit-identical results, keep the
- * fastest in the context and, when cache_path is not NULL, write it there as
- * one JSON object.  best (nullable) receives the chosen parameters. */
+ * values, then the plain form for segment sizes S = 2^20 .. 2^26, check that
+ * every combination gives bit-identical results, keep the fastest in the
+ * context and, when cache_path is not NULL, write it there as one JSON
+ * object.  best (nullable) receives the chosen parameters.  The paper fixes
+ * SEG_SIZE and PSMALL and reports that data-centre GPUs need them tuned to
+ * the hardware (sections "Multi-GPU Scaling and Efficiency", "Limitations"
+ * and "Future work"); this call is that tuning.  P_max plays PSMALL's part. */
 gb_status gb_autotune(gb_ctx *ctx, const gb_window *sample, size_t k,
                       const char *cache_path, gb_params *best);
 
 /* ------------------------------------------------------------------------
- * Serving: continuous batching of single-n and range requests.
+ * Serving: continuous batching of single-n and range requests.  The paper
+ * has no serving mode; these calls put the range computation of
+ * gb_verify_windows and the single-n checker of gb_verify_many behind a
+ * request queue.
  *
  * A server owns a context and `streams` device streams, each with its own
  * scratch.  A scheduler thread takes submitted requests in arrival order,
@@ -307,14 +334,18 @@ typedef struct gb_server gb_server;
 #define GB_REQ_ONE 0u    /* one even n */
 #define GB_REQ_RANGE 1u  /* the even n n, n+2, ..., n + 2(len-1) */
 
+#define GB_REQ_PMIN_DEVICE 1u  /* flags: pmin is device memory of the
+                                  server's device, written by the kernels */
+
 typedef struct gb_request {
     uint32_t  kind;      /* GB_REQ_ONE or GB_REQ_RANGE */
-    uint32_t  flags;     /* must be 0 */
+    uint32_t  flags;     /* 0, or GB_REQ_PMIN_DEVICE for a range with pmin */
     uint64_t  n;         /* the n (GB_REQ_ONE) or the first n (GB_REQ_RANGE) */
     uint64_t  len;       /* GB_REQ_RANGE: number of even n (>= 1) */
-    uint16_t *pmin;      /* GB_REQ_RANGE: host buffer of len entries for the
-                            per-n p_min (0 for p_min >= 2^16), written before
-                            the completion is reported; or NULL */
+    uint16_t *pmin;      /* GB_REQ_RANGE: buffer of len entries for the per-n
+                            p_min (0 for p_min >= 2^16), written before the
+                            completion is reported; host memory, or device
+                            memory with GB_REQ_PMIN_DEVICE; or NULL */
     uint64_t  tag;       /* caller's value, returned with the completion */
 } gb_request;
 
@@ -352,6 +383,19 @@ gb_status gb_server_submit(gb_server *srv, const gb_request *req, uint64_t *id);
 gb_status gb_server_poll(gb_server *srv, gb_completion *out, size_t cap, size_t *count,
                          int32_t wait_ms);
 gb_status gb_server_stats_get(gb_server *srv, gb_server_stats *stats);
+/* Replay a request trace (a load generator inside the library, so that the
+ * offered load does not depend on the caller's language): request i is
+ * submitted arrival_ns[i] nanoseconds after the call starts (arrival_ns
+ * ascending), and the call returns when all k have completed, with out[i]
+ * the completion of req[i].  Its submit_ns is the scheduled arrival time, so
+ * done_ns - submit_ns includes any delay in submitting (an open-loop
+ * measurement).  The paper has no serving mode; this drives the continuous
+ * batching above with a Poisson or any other arrival process.  No other
+ * thread may poll the server during the call.  GB_EINVAL for a malformed
+ * request (nothing submitted after it), GB_EDEVICE when the requests have
+ * not all completed within timeout_ms. */
+gb_status gb_server_replay(gb_server *srv, const gb_request *req, const uint64_t *arrival_ns,
+                           size_t k, gb_completion *out, uint32_t timeout_ms);
 /* Finish every queued and running request, then free the server. */
 gb_status gb_server_stop(gb_server *srv);
 const char *gb_server_last_error(const gb_server *srv);

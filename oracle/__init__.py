@@ -83,6 +83,8 @@ def lib():
         L.orc_hist_bins.argtypes, L.orc_hist_bins.restype = [], u32
         L.orc_checksum_weight.argtypes, L.orc_checksum_weight.restype = [u64], u64
         L.orc_odd_primality.argtypes, L.orc_odd_primality.restype = [u64, u64, vp], ip
+        L.orc_verify_windows.argtypes = [vp, vp, u64, u32, vp, ctypes.POINTER(Summary), ip]
+        L.orc_verify_windows.restype = ip
         L.orc_partition_counts.argtypes = [vp, vp, u64, ctypes.POINTER(PcSummary), ip]
         L.orc_partition_counts.restype = ip
         _lib = L
@@ -150,6 +152,27 @@ def verify_range(lo: int, hi: int, pmax: int = 8192, per_n_bits: int | None = 32
     if rc != 0:
         raise MemoryError("oracle allocation failed")
     return out, h, s.as_dict()
+
+
+def verify_windows(windows, pmax: int = 8192, per_n: bool = True, threads: int = 1):
+    """p_min for the even n of each window (start, len): start, start + 2,
+    ..., start + 2 (len - 1), start even and >= 4.  Returns (uint16 array of
+    every window's n concatenated in order, or None; list of summary dicts,
+    one per window)."""
+    k = len(windows)
+    st = np.ascontiguousarray(np.array([w[0] for w in windows], dtype=np.uint64))
+    ln = np.ascontiguousarray(np.array([w[1] for w in windows], dtype=np.uint64))
+    out = np.zeros(int(ln.sum()), dtype=np.uint16) if per_n else None
+    sums = (Summary * max(k, 1))()
+    if k:
+        rc = lib().orc_verify_windows(st.ctypes.data, ln.ctypes.data, k, pmax,
+                                      out.ctypes.data if out is not None and out.size else None,
+                                      sums, threads)
+        if rc == -2:
+            raise ValueError("every window needs an even start >= 4 and a positive length")
+        if rc != 0:
+            raise MemoryError("oracle allocation failed")
+    return out, [sums[i].as_dict() for i in range(k)]
 
 
 def odd_primality(w0: int, count: int) -> np.ndarray:

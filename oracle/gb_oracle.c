@@ -417,6 +417,70 @@ int orc_verify_range_mt(uint64_t lo, uint64_t hi, uint32_t pmax, void *out,
     return 0;
 }
 
+/* ---- many windows of consecutive even n (the batched and serving
+ * workloads): the base primes once, then each window is the plain scan of
+ * range_core, windows spread over threads.  Window i is the even n
+ * start[i], start[i] + 2, ..., start[i] + 2 (len[i] - 1), start[i] even and
+ * >= 4; its per-n p_min (uint16, 0 for p >= 2^16 or none) goes to out
+ * (nullable) at offset len[0] + ... + len[i-1], its summary to sums[i].
+ * Returns 0, -1 on allocation failure, -2 for a malformed window. */
+
+typedef struct {
+    const uint64_t *start, *len, *off;
+    uint64_t k, next;
+    uint32_t pmax;
+    const uint32_t *base, *small;
+    uint64_t nbase, nsmall;
+    uint16_t *out;
+    orc_summary *sums;
+} win_job;
+
+static void *win_worker(void *arg)
+{
+    win_job *j = arg;
+    for (;;) {
+        uint64_t i = __atomic_fetch_add(&j->next, 1, __ATOMIC_RELAXED);
+        if (i >= j->k) break;
+        memset(&j->sums[i], 0, sizeof j->sums[i]);
+        range_core(j->start[i], j->start[i] + 2 * (j->len[i] - 1), j->pmax, j->base, j->nbase,
+                   j->small, j->nsmall, j->out ? j->out + j->off[i] : NULL, 16, NULL, &j->sums[i]);
+    }
+    return NULL;
+}
+
+int orc_verify_windows(const uint64_t *start, const uint64_t *len, uint64_t k, uint32_t pmax,
+                       uint16_t *out, orc_summary *sums, int nthreads)
+{
+    if (k == 0) return 0;
+    uint64_t top = 0;
+    uint64_t *off = malloc(k * sizeof(uint64_t));
+    if (!off) return -1;
+    for (uint64_t i = 0, o = 0; i < k; i++) {
+        if (start[i] < 4 || start[i] % 2 || len[i] == 0) { free(off); return -2; }
+        uint64_t last = start[i] + 2 * (len[i] - 1);
+        if (last > top) top = last;
+        off[i] = o;
+        o += len[i];
+    }
+    if (nthreads < 1) nthreads = 1;
+    win_job j;
+    memset(&j, 0, sizeof j);
+    uint64_t lim = orc_isqrt(top) + 1;
+    if (lim < ORC_P_EXT) lim = ORC_P_EXT;
+    j.base = odd_primes_upto(lim, &j.nbase);
+    j.small = odd_primes_upto(ORC_P_EXT, &j.nsmall);
+    if (!j.base || !j.small) { free((void *)j.base); free((void *)j.small); free(off); return -1; }
+    j.start = start; j.len = len; j.off = off; j.k = k; j.pmax = pmax; j.out = out; j.sums = sums;
+    pthread_t *th = malloc(sizeof(pthread_t) * (size_t)nthreads);
+    for (int t = 0; t < nthreads; t++) pthread_create(&th[t], NULL, win_worker, &j);
+    for (int t = 0; t < nthreads; t++) pthread_join(th[t], NULL);
+    free(th);
+    free((void *)j.base);
+    free((void *)j.small);
+    free(off);
+    return 0;
+}
+
 /* p_min of one even n (4 <= n < 2^64) by scanning odd primes p upward and
  * testing q = n - p with the deterministic Miller-Rabin test.  Candidate p
  * come from the odd primes below 2^16 and, past them, from odd numbers that

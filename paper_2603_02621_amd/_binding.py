@@ -116,6 +116,8 @@ SIGNATURES = {
     "gb_server_submit": ([vp, ctypes.POINTER(Request), ctypes.POINTER(u64)], i32),
     "gb_server_poll": ([vp, ctypes.POINTER(Completion), ctypes.c_size_t,
                         ctypes.POINTER(ctypes.c_size_t), i32], i32),
+    "gb_server_replay": ([vp, ctypes.POINTER(Request), ctypes.POINTER(u64), ctypes.c_size_t,
+                          ctypes.POINTER(Completion), u32], i32),
     "gb_server_stats_get": ([vp, ctypes.POINTER(ServerStats)], i32),
     "gb_server_stop": ([vp], i32),
     "gb_server_last_error": ([vp], ctypes.c_char_p),

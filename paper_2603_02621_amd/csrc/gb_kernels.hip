@@ -191,8 +191,57 @@ __device__ __forceinline__ TileLds carve(uint32_t *smem, const GbTileArgs &a)
     return L;
 }
 
+// The histogram row a workgroup's LDS hit counts belong to, and the n
+// counted into them since they were last flushed (the same in every thread).
+constexpr uint32_t kNoRow = 0xFFFFFFFFu;
+struct HistCarry {
+    uint32_t row = kNoRow;
+    unsigned long long n = 0;
+};
+
+// Fast-path prime list in LDS, once per workgroup: odd primes p <= P_max in
+// groups of four (packed words, g, hit counts), padded with copies of the last
+// prime through the end of the second group after the last prime's group (a
+// lane runs three groups per exit check and may start on the last one).
+template <int NT, bool VERIFY, bool GW>
+__device__ void setup_primes(const GbTileArgs &a, const TileLds &L)
+{
+    const uint32_t nps = a.np_search;
+    const uint32_t npad = 4u * ((nps + 3u) / 4u + 2u);
+    for (uint32_t i = threadIdx.x; i < npad; i += NT) {
+        const uint32_t p = a.primes[i < nps ? i : (nps ? nps - 1 : 0)];
+        const uint32_t h = (p + 1u) >> 1;
+        uint32_t hi = PX_BIAS - 4u * ((h + 31u) >> 5);
+        if (GW && (i & 3u) != 3u) {
+            // group-window form: the high half of a group's first three
+            // words says whether the probe starts one word above the
+            // group's base word (that of its last prime)
+            const uint32_t i3 = i | 3u;
+            const uint32_t p3 = a.primes[i3 < nps ? i3 : (nps ? nps - 1 : 0)];
+            hi = ((((p3 + 1u) >> 1) + 31u) >> 5) - ((h + 31u) >> 5);
+        }
+        L.pr[pr_px(i)] = (hi << 16) | (65536u - h);
+        L.pr[pr_gl(i)] = VERIFY ? (65536u - h) << 16 : 65536u - h;
+        L.pr[pr_lh(i)] = 0;
+    }
+}
+
+// Add the workgroup's per-prime hit counts to histogram row `row` and clear
+// them (each thread its own primes).
+__device__ void flush_hist(const GbTileArgs &a, const TileLds &L, uint32_t row)
+{
+    unsigned long long *hist = a.hist + (unsigned long long)row * GB_HIST_BINS_I;
+    for (uint32_t i = threadIdx.x; i < a.np_search; i += blockDim.x) {
+        const uint32_t c = L.pr[pr_lh(i)];
+        if (c) {
+            atomicAdd(&hist[i + 1], (unsigned long long)c);
+            L.pr[pr_lh(i)] = 0;
+        }
+    }
+}
+
 template <int NT, int PB, bool SIEVE_ONLY, bool GW>
-__device__ void process_tile(const GbTileArgs &a, unsigned long long g, const TileLds &L)
+__device__ void process_tile(const GbTileArgs &a, unsigned long long g, const TileLds &L, HistCarry &hc)
 {
     // made opaque per tile: otherwise the compiler hoists values derived
     // from the thread index out of a persistent workgroup's tile loop and
@@ -232,30 +281,25 @@ __device__ void process_tile(const GbTileArgs &a, unsigned long long g, const Ti
     const bool small_w0 = w0 < (1ll << 53);   // exact as a double
     const double w0d = (double)w0;
 
-    // ---- fast-path prime list, per-tile histogram --------------------------
+    // ---- per-tile reductions; the workgroup's histogram row ----------------
     if (!SIEVE_ONLY) {
-        // through the end of the second group after the last prime's group:
-        // a lane runs three groups per exit check and may start on the last
-        // one
-        const uint32_t npad = 4u * ((nps + 3u) / 4u + 2u);
-        for (uint32_t i = tid; i < npad; i += NT) {
-            const uint32_t p = a.primes[i < nps ? i : (nps ? nps - 1 : 0)];
-            const uint32_t h = (p + 1u) >> 1;
-            uint32_t hi = PX_BIAS - 4u * ((h + 31u) >> 5);
-            if (GW && (i & 3u) != 3u) {
-                // group-window form: the high half of a group's first three
-                // words says whether the probe starts one word above the
-                // group's base word (that of its last prime)
-                const uint32_t i3 = i | 3u;
-                const uint32_t p3 = a.primes[i3 < nps ? i3 : (nps ? nps - 1 : 0)];
-                hi = ((((p3 + 1u) >> 1) + 31u) >> 5) - ((h + 31u) >> 5);
-            }
-            L.pr[pr_px(i)] = (hi << 16) | (65536u - h);
-            L.pr[pr_gl(i)] = VERIFY ? (65536u - h) << 16 : 65536u - h;
-            L.pr[pr_lh(i)] = 0;
-        }
         if (tid < 4) L.red[tid] = 0ull;   // tile sums, max key, OR words
         if (tid == 0) *L.next = NT;       // blocks 0..NT-1 go to the threads in order
+        // The per-prime hit counts in L.pr stay in LDS across the tiles of a
+        // workgroup and go to the histogram when its row changes (one row per
+        // window with per-slot histograms), before 2^31 n could overflow a
+        // 32-bit count, and when the workgroup ends.  Each thread flushes and
+        // clears its own primes' counts; the counts are next written in the
+        // search phase, behind the sieve's barriers.
+        if (!VERIFY) {
+            const uint32_t row = a.hist_per_slot ? W.slot : 0u;
+            if (row != hc.row || hc.n + cnt > 0x7FFFFFFFull) {
+                if (hc.row != kNoRow) flush_hist(a, L, hc.row);
+                hc.row = row;
+                hc.n = 0;
+            }
+            hc.n += cnt;
+        }
     }
     // ---- first strike of every small and medium sieving prime, once -------
     // When the window starts at or above the square of its largest sieving
@@ -721,12 +765,6 @@ __device__ void process_tile(const GbTileArgs &a, unsigned long long g, const Ti
     if (nexh) atomicAdd(&L.red[1], (unsigned long long)nexh);
     if (maxp) atomicMax(&L.red[2], key);
     __syncthreads();
-    if (!VERIFY) {
-        for (uint32_t i = tid; i < nps; i += NT) {
-            const uint32_t c = L.pr[pr_lh(i)];
-            if (c) atomicAdd(&hist[i + 1], (unsigned long long)c);
-        }
-    }
     if (wave == 0) {
         const unsigned long long csum = L.red[0], xsum = L.red[1], kmax = L.red[2];
         const uint32_t mp = (uint32_t)(kmax >> 32);
@@ -783,17 +821,23 @@ __global__ __launch_bounds__(NT) void k_tile(GbTileArgs a)
 {
     extern __shared__ uint32_t smem[];
     const TileLds L = carve(smem, a);
+    HistCarry hc;
+    if constexpr (!SIEVE_ONLY) setup_primes<NT, PB == 1, GW>(a, L);   // behind the first barrier below
     if constexpr (PERS) {
         for (;;) {
             if (threadIdx.x == 0) *L.tile = atomicAdd(a.queue, 1ull);
             __syncthreads();
             const unsigned long long g = *L.tile;
             if (g >= a.ntiles) break;
-            process_tile<NT, PB, SIEVE_ONLY, GW>(a, g, L);
+            process_tile<NT, PB, SIEVE_ONLY, GW>(a, g, L, hc);
         }
     } else {
-        process_tile<NT, PB, SIEVE_ONLY, GW>(a, a.tile0 + blockIdx.x, L);
+        __syncthreads();
+        process_tile<NT, PB, SIEVE_ONLY, GW>(a, a.tile0 + blockIdx.x, L, hc);
     }
+    // process_tile ends with a barrier, so every count is in LDS
+    if constexpr (!SIEVE_ONLY && PB != 1)
+        if (hc.row != kNoRow) flush_hist(a, L, hc.row);
 }
 
 

@@ -169,9 +169,9 @@ extern "C" gb_status gb_autotune(gb_ctx *c, const gb_window *sample, size_t k, c
             }
         }
     }
-    // 4. segment size of the plain form (one launch per segment), on 2^32
-    // even n from the sample's first start: large enough that the largest
-    // segments still make several launches
+    // 4. segment size of the plain form (one launch per segment), S = 2^20 ..
+    // 2^26 even n, on 2^32 even n from the sample's first start: large
+    // enough that the largest segments still make many launches
     uint64_t total = 0;
     for (size_t i = 0; i < k; ++i) total += sample[i].len;
     const uint64_t lo = sample[0].start;
@@ -182,7 +182,7 @@ extern "C" gb_status gb_autotune(gb_ctx *c, const gb_window *sample, size_t k, c
     double best_seg_ms = 1e300;
     gb_summary seg_ref{};
     bool have_seg_ref = false;
-    for (uint32_t sl = 20; sl <= 30; ++sl) {
+    for (uint32_t sl = 20; sl <= 26; ++sl) {
         gb_params p = cur;
         p.seg_log2 = std::max(sl, p.tile_log2);
         gb_status st = reconfigure(c, p);

@@ -290,6 +290,35 @@ def test_multithread_equals_single(orc):
     assert np.array_equal(o1, o2) and np.array_equal(h1, h2) and s1 == s2
 
 
+def test_windows_bruteforce_and_single_n(orc, td_table):
+    # overlapping and ragged windows below 10^5 against trial division, and
+    # windows near 10^12 and 10^15 (the serving workload's range starts)
+    # against the Miller-Rabin scan of single n with SymPy minimality
+    wins = [(4, 1), (4, 500), (98, 3), (1000, 777), (1002, 100), (99_000, 500), (50_000, 1)]
+    out, sums = orc.verify_windows(wins, threads=3)
+    o = 0
+    for (start, ln), sm in zip(wins, sums):
+        ref = [_td_pmin(start + 2 * i, td_table) for i in range(ln)]
+        assert out[o:o + ln].tolist() == ref, start
+        assert sm["count"] == ln and sm["n_failed"] == 0
+        assert sm["max_p"] == max(ref)
+        assert sm["argmax_n"] == start + 2 * ref.index(max(ref))
+        assert sm["checksum"] == sum(_weight(start + 2 * i) * p for i, p in enumerate(ref)) % 2**64
+        o += ln
+    big = [(10**15 + 2 * 12345, 300), (10**12 - 2**17, 200), (2 * 10**14 + 6, 1)]
+    out, sums = orc.verify_windows(big, threads=2)
+    o = 0
+    rng = np.random.default_rng(11)
+    for (start, ln), sm in zip(big, sums):
+        for i in rng.integers(0, ln, size=min(ln, 20)):
+            n = start + 2 * int(i)
+            assert int(out[o + int(i)]) == orc.verify_one(n)
+        _check_minimal(start, int(out[o]))
+        o += ln
+    with pytest.raises(ValueError):
+        orc.verify_windows([(7, 10)])
+
+
 def test_paper_counts_small(orc):
     for kind, arg, val in _golden():
         if kind == "count" and arg <= 10**8:

@@ -28,17 +28,29 @@ sys.path.insert(0, ROOT)
 LO, HI = 10**12 - 2**36, 10**12
 METRIC = "even n verified/s at N~1e12 on 1 MI355X (batched form)"
 
-# Per-n algorithmic work of the sieve-and-search kernel at this workload:
-# sum over sieving primes 11 <= p <= 10^6 of 1/p = 1.711 bit clears per odd
-# number (3 integer ops each: next index, word, mask), 1.01 64-bit window
-# probes per n (7 ops: offset, word, two funnel shifts, two ANDs, test; the
-# mean over 64-n blocks of the largest prime index needed, divided by 64),
-# and 1/32 wheel word per n (5 ops).
+# Per-n algorithmic work of the sieve-and-search kernel at this workload
+# (every even n of [1e12 - 2^36, 1e12], fast path P_max = 4096, tiles of
+# T = 2^20 even n), counted in int32 lane operations and fixed here:
+#  - sieve bit clears: the sum of 1/p over the sieving primes 11 <= p <= 10^6
+#    is 1.711 clears per odd number, 3 ops each (next index, word, mask);
+#  - wheel pattern: one 32-bit word store per 32 odd numbers, 5 ops each;
+#  - first strikes: pi(10^6) - 1 = 78,497 odd sieving primes per tile, one
+#    64-bit remainder (10 ops) each, per 2^20 n;
+#  - window probes: 1.01 64-bit probes per n (the mean over 64-n blocks of
+#    the largest prime index the block needs, 64.68, divided by 64), 7 ops
+#    each (offset, word, two funnel shifts, two ANDs, test);
+#  - hit bookkeeping: 29.9 distinct p_min per 64-n block, 0.467 hit events
+#    per n, 8 ops each (clear the resolved n from the block mask: 2, popcount
+#    for the histogram: 2, count add: 1, checksum multiply-adds: 3).
 CLEARS_PER_N = 1.711
 PROBES_PER_N = 1.01
-ALG_OPS_PER_N = CLEARS_PER_N * 3 + PROBES_PER_N * 7 + 5 / 32
-# 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz, one 32-bit integer op per lane-cycle
-ALU_PEAK_OPS = 256 * 64 * 2.4e9
+HITS_PER_N = 29.9 / 64
+STRIKES_PER_N = 78497 / 2**20
+ALG_OPS_PER_N = (CLEARS_PER_N * 3 + 5 / 32 + STRIKES_PER_N * 10 + PROBES_PER_N * 7
+                 + HITS_PER_N * 8)
+# Integer VALU peak: 157.3 TFLOP/s fp32 vector = 78.6e12 FMA lane-slots per
+# second (256 CUs x 4 SIMDs x 32 lanes x 2.4 GHz); one int32 op per slot.
+ALU_PEAK_OPS = 256 * 4 * 32 * 2.4e9
 PC_N, PC_HI = 1 << 16, 10**9        # partition-count workload: 2^16 even n ending at 1e9
 BIG_N = 4096                        # beyond-64-bit workload: even n from 10^100 upward
 

@@ -118,6 +118,17 @@ gb_status enqueue_init(gb_ctx *c, Workspace &ws, const Job &j, hipStream_t st)
     return GB_OK;
 }
 
+hipError_t ensure_plain_streams(gb_ctx *c)
+{
+    if (c->plain_fork) return hipSuccess;
+    hipError_t e;
+    for (int l = 0; l < gb_ctx::kPlainLanes - 1; ++l) {
+        if ((e = hipStreamCreateWithFlags(&c->plain_st[l], hipStreamNonBlocking)) != hipSuccess) return e;
+        if ((e = hipEventCreateWithFlags(&c->plain_join[l], hipEventDisableTiming)) != hipSuccess) return e;
+    }
+    return hipEventCreateWithFlags(&c->plain_fork, hipEventDisableTiming);
+}
+
 gb_status enqueue_tiles(gb_ctx *c, Workspace &ws, const Job &j, hipStream_t st)
 {
     GbTileArgs a = base_args(c, ws);
@@ -134,13 +145,30 @@ gb_status enqueue_tiles(gb_ctx *c, Workspace &ws, const Job &j, hipStream_t st)
         const uint64_t g = std::min<uint64_t>(pl.ntiles, (uint64_t)c->num_cu * c->occupancy);
         GB_HIP(c, gb_launch_tiles(a, (uint32_t)g, c->threads, c->lds, j.pmin_bits, true, false, c->group_window, st));
     } else {
+        // One launch per segment.  A segment of S even n is S/T tiles, fewer
+        // than the device holds at S = 2^24, so consecutive segments go to
+        // the caller's stream and up to three more in turn and run side by
+        // side; each segment writes only its own slot, histogram row, tile
+        // records and per-n output.
+        const int lanes = (int)std::min<size_t>(gb_ctx::kPlainLanes, pl.w.size());
+        if (lanes > 1) {
+            GB_HIP(c, ensure_plain_streams(c));
+            GB_HIP(c, hipEventRecord(c->plain_fork, st));
+            for (int l = 1; l < lanes; ++l) GB_HIP(c, hipStreamWaitEvent(c->plain_st[l - 1], c->plain_fork, 0));
+        }
         for (size_t i = 0; i < pl.w.size(); ++i) {
             GbTileArgs b = a;
             b.win = ws.win.p + i;
             b.nwin = 1;
             b.tile0 = pl.w[i].tile_base;
             const uint64_t nt = (pl.w[i].count + c->tile_n - 1) / c->tile_n;
-            GB_HIP(c, gb_launch_tiles(b, (uint32_t)nt, c->threads, c->lds, j.pmin_bits, false, false, c->group_window, st));
+            const int l = (int)(i % (size_t)lanes);
+            hipStream_t ls = l == 0 ? st : c->plain_st[l - 1];
+            GB_HIP(c, gb_launch_tiles(b, (uint32_t)nt, c->threads, c->lds, j.pmin_bits, false, false, c->group_window, ls));
+        }
+        for (int l = 1; l < lanes; ++l) {
+            GB_HIP(c, hipEventRecord(c->plain_join[l - 1], c->plain_st[l - 1]));
+            GB_HIP(c, hipStreamWaitEvent(st, c->plain_join[l - 1], 0));
         }
     }
     return GB_OK;
@@ -661,6 +689,11 @@ void gb_destroy(gb_ctx *c)
     if (!c) return;
     (void)hipSetDevice(c->prm.device);
     (void)hipDeviceSynchronize();
+    for (int l = 0; l < gb_ctx::kPlainLanes - 1; ++l) {
+        if (c->plain_st[l]) (void)hipStreamDestroy(c->plain_st[l]);
+        if (c->plain_join[l]) (void)hipEventDestroy(c->plain_join[l]);
+    }
+    if (c->plain_fork) (void)hipEventDestroy(c->plain_fork);
     c->ws.release();
     free_tables(c);
     delete c;

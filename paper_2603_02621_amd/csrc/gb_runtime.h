@@ -148,6 +148,12 @@ struct gb_ctx {
     size_t lds = 0;
     bool group_window = false;       // search form: one window read per group of four probes
     int occupancy = 1;
+    // plain form: segment launches go round-robin to the caller's stream and
+    // these (created on first use), forked after the init kernel and joined
+    // before the exhaustive phase
+    static constexpr int kPlainLanes = 4;
+    hipStream_t plain_st[kPlainLanes - 1] = {};
+    hipEvent_t plain_fork = nullptr, plain_join[kPlainLanes - 1] = {};
     gbrt::Workspace ws;              // scratch of the synchronous calls
     std::string err;
     std::vector<GbExh> last_list;

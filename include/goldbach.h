@@ -228,6 +228,18 @@ gb_status gb_verify_big(gb_ctx *ctx, const uint32_t *n, uint32_t nlimbs, size_t 
 gb_status gb_verify_many(gb_ctx *ctx, const uint64_t *n, uint64_t *p, size_t k,
                          int on_device, void *stream);
 
+/* gb_verify_many without any allocation in the call, for callers that
+ * cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc).  n and p are device arrays of k
+ * entries (inputs and outputs stay the caller's); the exhaustive phase's
+ * work list and counters live in a fixed device array inside the library,
+ * 2 MiB per device, so k is at most 65536 (GB_EINVAL above).  Every call on
+ * one device shares that array: calls that overlap on a device race.  The
+ * call synchronises `stream`.  Same results as gb_verify_many; GB_EINVAL when
+ * an n is odd, below 4 or above 2^63 (p unspecified), GB_EUNRESOLVED when an
+ * n has no partition within the budget (its p is 0). */
+gb_status gb_verify_many_noalloc(gb_ctx *ctx, const uint64_t *n, uint64_t *p, size_t k, void *stream);
+
 /* The sieve alone (the segment bitset of subsection "Correct segmentation",
  * there built on the host; a GPU-built sieve is a direction of section
  * "Future work"): bit i of the output (LSB-first uint32 words) is 1 iff the

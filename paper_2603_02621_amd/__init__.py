@@ -213,6 +213,18 @@ class Verifier:
         self._check(st, allow=(5,) if allow_unresolved else ())
         return out
 
+    def verify_many_noalloc(self, ns, out=None, stream=None, allow_unresolved=False):
+        """verify_many for a torch int64/uint64 tensor on the GPU with no
+        device allocation inside the library (at most 65536 n; `out`, a
+        tensor like `ns`, receives the p)."""
+        import torch
+        if out is None:
+            out = torch.empty_like(ns)
+        st = self._lib.gb_verify_many_noalloc(self._h, ns.data_ptr(), out.data_ptr(), ns.numel(),
+                                              _stream_ptr(stream))
+        self._check(st, allow=(5,) if allow_unresolved else ())
+        return out
+
     def sieve_window(self, w0: int, nbits: int, out, stream=None):
         """Sieve bits of the odd numbers w0, w0+2, ... into ``out`` (a torch
         int32 tensor of nbits/32 words on the GPU)."""

@@ -675,6 +675,7 @@ gb_status gb_create(gb_ctx **out, const gb_params *prm)
         return s;
     };
     if (hipSetDevice(c->prm.device) != hipSuccess) return bail(GB_EDEVICE);
+    if (noalloc_setup(c->prm.device) != hipSuccess) return bail(GB_EDEVICE);
     st = build_tables(c);
     if (st != GB_OK) return bail(st);
     if (c->ws.init(c->prm.max_unresolved) != hipSuccess) return bail(GB_ENOMEM);

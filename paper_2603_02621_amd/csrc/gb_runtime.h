@@ -183,6 +183,9 @@ gb_status enqueue_queries(gb_ctx *c, Workspace &ws, uint64_t k, const unsigned l
 // w0, w0 + 2, ... (w0 odd, nbits a multiple of 64), enqueued on st
 gb_status enqueue_sieve(gb_ctx *c, Workspace &ws, uint64_t w0, uint64_t nbits, uint32_t *bits, hipStream_t st);
 void merge_slot(gb_summary &acc, const GbSlot &s);
+// Record the device address of the no-allocation form's scratch array on
+// `device` (current), once per device; its result on later calls.
+hipError_t noalloc_setup(int device);
 
 }  // namespace gbrt
 

@@ -160,7 +160,7 @@ def main():
     ap.add_argument("--no-big", action="store_true", help="skip the beyond-64-bit line")
     ap.add_argument("--serve-count", type=int, default=10_000,
                     help="requests per offered rate of the serving sweep")
-    ap.add_argument("--serve-qps", default="1e2,3e2,1e3,3e3,1e4,3e4,1e5",
+    ap.add_argument("--serve-qps", default="1e2,3e2,1e3,3e3,1e4,3e4,1e5,3e5,1e6",
                     help="offered rates of the serving sweep, comma-separated")
     ap.add_argument("--serve-streams", type=int, default=4)
     ap.add_argument("--copy-calibrate", type=int, default=0, metavar="MIB",
@@ -209,23 +209,43 @@ def main():
           file=sys.stderr, flush=True)
 
     # ---- plain (beside it) ------------------------------------------------
-    plain = None
+    # The paper's segment loop: one tile launch per segment of S even n,
+    # consecutive segments on four streams; at the tuned S (2^20 .. 2^26)
+    # and at S = 2^24 with tiles of 2^18 n (64 tiles per segment: the tile
+    # size at which four segments in flight cover the device).
+    plain = []
     if args.plain_steps > 0:
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        plain_tile = []
-        for _ in range(args.plain_steps):
-            rp = v.verify_range(LO, HI, batched=False)
-            plain_tile.append(rp["tile_ms"] / max(rp["tile_launches"], 1))
-        torch.cuda.synchronize()
-        plain_wall = (time.perf_counter() - t0) / args.plain_steps
-        for k in ("count", "checksum", "max_p", "argmax_n", "n_exhaustive", "n_failed"):
-            assert rp[k] == ref[k], k
-        print(f"# plain: {1e3*plain_wall:.1f} ms/step over {rp['n_segments']} segment launches",
-              file=sys.stderr, flush=True)
-        plain = {"value": count / plain_wall, "ms_per_step": 1e3 * plain_wall,
-                 "segments": rp["n_segments"],
-                 "tile_launch_ms": sum(plain_tile) / len(plain_tile)}
+        forms = [("tuned", {}), ("s24", {"seg_log2": 24, "tile_log2": 18, "wg_threads": 1024})]
+        for name, over in forms:
+            if name == "tuned" and p["seg_log2"] > 26:
+                over = {"seg_log2": 26}
+            vp = v if not over else Verifier(0, **{**params, **over})
+            pp = vp.params
+            vp.verify_range(LO, LO + 2 * ((1 << 28) - 1), batched=False)    # code and buffers warm
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            plain_tile = []
+            for _ in range(args.plain_steps):
+                rp = vp.verify_range(LO, HI, batched=False)
+                plain_tile.append(rp["tile_ms"])
+            torch.cuda.synchronize()
+            plain_wall = (time.perf_counter() - t0) / args.plain_steps
+            for k in ("count", "checksum", "max_p", "argmax_n", "n_exhaustive", "n_failed"):
+                assert rp[k] == ref[k], k
+            t_tiles = sum(plain_tile) / len(plain_tile) / 1e3
+            ach = ALG_OPS_PER_N * count / t_tiles
+            print(f"# plain S=2^{pp['seg_log2']} T=2^{pp['tile_log2']}: {1e3*plain_wall:.1f} ms/step over "
+                  f"{rp['n_segments']} segment launches", file=sys.stderr, flush=True)
+            plain.append({"form": name, "seg_log2": pp["seg_log2"], "tile_log2": pp["tile_log2"],
+                          "wg_threads": pp["wg_threads"], "value": count / plain_wall,
+                          "ms_per_step": 1e3 * plain_wall, "segments": rp["n_segments"],
+                          "streams": 4, "tile_phase_ms": 1e3 * t_tiles,
+                          "vs_batched": value / (count / plain_wall),
+                          "roofline": {"bound": "alu", "achieved": ach / 1e12, "peak": ALU_PEAK_OPS / 1e12,
+                                       "unit": "Tops/s (int32 lane ops)", "frac": ach / ALU_PEAK_OPS,
+                                       "alg_ops_per_n": round(ALG_OPS_PER_N, 3)}})
+            if vp is not v:
+                vp.close()
 
     # ---- bulk verification of the same range (no per-n minimal p) --------
     bulk = None

@@ -94,11 +94,23 @@ def test_bench_size_sampled(V, orc):
     got = V.partition_counts(BENCH_LO, BENCH_HI, counts=out)
     torch.cuda.synchronize()
     dev = out.cpu().numpy().view(np.uint64)
-    # the first and last n, the block edges around 512 and a seeded sample
+    # 256 n: for every residue of m = n/2 - 1 mod 32 (each residue is its
+    # own wavefront), its first and last n, its n on both sides of two edges
+    # of the 2048-m blocks a group of workgroups covers, and four more from a
+    # seeded draw
+    m = ns // 2 - 1
     rng = np.random.default_rng(7)
-    idx = np.unique(np.concatenate([[0, 1, 511, 512, 513, ns.size - 1],
-                                    rng.integers(0, ns.size, size=10)]))
-    ref, _ = orc.partition_counts(ns[idx], threads=8)
+    idx = []
+    for r in range(32):
+        where = np.nonzero(m % 32 == r)[0]
+        edges = [np.searchsorted(m[where], e) for e in (m[0] - m[0] % 2048 + 2048 * 3,
+                                                        m[0] - m[0] % 2048 + 2048 * 17)]
+        pick = [0, where.size - 1] + [e for e in edges] + [e - 1 for e in edges]
+        pick += list(rng.integers(0, where.size, size=4))
+        idx += [int(where[min(max(i, 0), where.size - 1)]) for i in pick]
+    idx = np.unique(np.array(idx))
+    assert idx.size >= 240 and len(set((m[idx] % 32).tolist())) == 32
+    ref, _ = orc.partition_counts(ns[idx], threads=16)
     assert np.array_equal(dev[idx], ref), list(zip(ns[idx], dev[idx], ref))
     # summaries agree with the per-n counts
     assert got == {**_summary_of(ns, dev), "device_ms": got["device_ms"],

@@ -290,6 +290,17 @@ def test_multithread_equals_single(orc):
     assert np.array_equal(o1, o2) and np.array_equal(h1, h2) and s1 == s2
 
 
+@pytest.mark.parametrize("w0", [10**12 - 1001, 1000003**2 - 2000, 2**53 - 2001, 1, 99_991])
+def test_odd_primality_vs_sympy(orc, w0):
+    # the byte sieve the GPU sieve is compared with, pinned directly: every
+    # odd number of windows near 10^12, across 1000003^2 (the first square
+    # of a sieving prime above 10^6) and across 2^53, against SymPy
+    count = 2000
+    got = orc.odd_primality(w0, count)
+    want = [int(sympy.isprime(w0 + 2 * i)) for i in range(count)]
+    assert got.tolist() == want
+
+
 def test_windows_bruteforce_and_single_n(orc, td_table):
     # overlapping and ragged windows below 10^5 against trial division, and
     # windows near 10^12 and 10^15 (the serving workload's range starts)

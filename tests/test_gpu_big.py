@@ -26,9 +26,7 @@ def test_table5(V):
     assert V.verify_big([10**50, 10**100]) == [383, 797]
 
 
-@pytest.mark.parametrize("bits", [65, 96, 127, 128, 200, 256, 333, 500, 512, pytest.param(520, marks=pytest.mark.skip(
-    reason="did not finish within the test's limit in the two-kernel form at 32 limbs (since switched off for "
-           "32 limbs); cause not found")), 600, 700, 768, 1020])
+@pytest.mark.parametrize("bits", [65, 96, 127, 128, 200, 256, 333, 500, 512, 520, 600, 700, 768, 1020])
 def test_random_vs_oracle(V, bits):
     rng = random.Random(bits)
     ns = [2 * rng.getrandbits(bits - 1) | (1 << (bits - 1)) for _ in range(6)]

@@ -155,12 +155,24 @@ class Verifier:
             raise ValueError("n must be below 2^1024")
         nb = 4 * nl
         words = np.frombuffer(b"".join([x.to_bytes(nb, "little") for x in ns]),
-                              dtype="<u4").reshape(len(ns), nl).copy()
-        out = np.zeros(len(ns), dtype=np.uint64)
-        st = self._lib.gb_verify_big(self._h, words.ctypes.data, nl, len(ns), out.ctypes.data,
-                                     _stream_ptr(stream))
+                              dtype="<u4").reshape(len(ns), nl)
+        return self.verify_big_words(words, stream, allow_unresolved).tolist()
+
+    def verify_big_words(self, words, stream=None, allow_unresolved=False):
+        """The same for n already laid out as the C call takes them: a C-ordered
+        uint32 array of shape (k, nlimbs), little-endian limbs, 3 <= nlimbs
+        <= 32.  Returns a uint64 array of k entries."""
+        import numpy as np
+        w = np.ascontiguousarray(words, dtype=np.uint32)
+        if w.ndim != 2:
+            raise ValueError("words must have shape (k, nlimbs)")
+        k, nl = w.shape
+        out = np.zeros(k, dtype=np.uint64)
+        if k == 0:
+            return out
+        st = self._lib.gb_verify_big(self._h, w.ctypes.data, nl, k, out.ctypes.data, _stream_ptr(stream))
         self._check(st, allow=(5,) if allow_unresolved else ())
-        return out.tolist()
+        return out
 
     def measure_peaks(self, stream=None):
         """Measured device throughput ceilings (see gb_measure_peaks)."""

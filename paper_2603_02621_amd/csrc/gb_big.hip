@@ -2,22 +2,27 @@
 // section "Arbitrary Precision Checker": small primes p in ascending order,
 // q = n - p tested with Miller-Rabin), up to n < 2^1024.
 //
-// Below 2^448 (n as 4 .. 16 limbs of 28 bits, gb_bignum28.h) each pass is
-// one launch whose blocks either search or confirm.  The search takes one
-// wavefront per n and group of candidates.  The odd primes p of the resident
-// table are first filtered, 64 at a time, by the 24 odd prime bases
-// r = 3 .. 97: a q = n - p that r divides fails the strong test to base r
-// (a^d and its squarings mod q are then multiples of r, never 1 or q - 1),
-// so dropping p = n (mod r) leaves the answer unchanged; about a quarter of
-// the p survive.  Lane l then takes the l-th of the group's 64 surviving p
-// and runs the strong probable-prime test to base 2 on its q; the lowest
-// passing lane gives the candidate.  The confirmation, in the next pass,
-// tests each candidate's q to the other 24 bases, one (n, base) per lane.  A
-// candidate that fails a base (a strong pseudoprime to base 2) sends its n
-// back to the search, which resumes after it.  The answer is the first p
-// whose q passes all 25 bases; every smaller p failed one, so its q is
-// composite.  From 449 bits on (32 limbs of 32 bits, gb_bignum.h) one
-// wavefront per n does the same in one kernel.
+// Below 2^446 (n as K = 4, 6, ..., 16 limbs of 28 bits, gb_bignum28.h) the
+// host runs passes of one launch each.  A launch is a list of lane tasks,
+// 64 to a wavefront: first the search groups, then the confirmations.
+//
+// - Search: the odd primes p of the resident table are filtered, 64 at a
+//   time, by the 24 odd prime bases r = 3 .. 97.  A q = n - p that r divides
+//   fails the strong test to base r (a^d and its squarings mod q are then
+//   multiples of r, never 1 or q - 1), so dropping p = n (mod r) leaves the
+//   answer unchanged; about a quarter of the p survive.  A group of G lanes
+//   (G = 32 or 64) takes G consecutive survivors of one n and tests their q
+//   to base 2; the group's lowest passing lane gives the candidate, and an
+//   atomic minimum over the groups of one n keeps the smallest.
+// - Confirmation: 24 lanes per candidate, lane j testing its q to the j-th
+//   odd base.  A candidate that fails one (a strong pseudoprime to base 2)
+//   sends its n back to the search, which resumes after it.
+//
+// The answer is the first p whose q passes all 25 bases; every smaller p
+// failed one, so its q is composite.  All lanes run the same windowed strong
+// test (base 2 or an odd base), so search groups and confirmations share
+// wavefronts.  From 447 bits on (32 limbs of 32 bits, gb_bignum.h) one
+// wavefront per n does the search and confirmation in one kernel.
 #include <algorithm>
 #include <cstring>
 
@@ -27,6 +32,7 @@
 
 namespace {
 
+using namespace gbrt;
 using gbbig::Num;
 
 __constant__ uint32_t kBigBases[25] = {2, 3, 5, 7, 11, 13, 17, 19, 23, 29, 31, 37, 41,
@@ -68,26 +74,19 @@ template <int K> __device__ __forceinline__ void big_sub_p(gbbig28::Num<K> &q, c
     }
 }
 
-// One pass of the search: nways wavefronts per listed n, wavefront w taking
-// the w-th group of 64 surviving p from resume_in[idx] on and testing it to
-// base 2.  found[idx] (all ones before the pass) receives the smallest table
-// index that passed; the last wavefront writes the table index after its
-// group (nprimes at the table's end) to resume_out[idx].  resume_in is only
-// read during the pass: the wavefronts of one n run in any order, so a write
-// into the array the others read would move their groups.
+// Lanes [lane0, lane0 + G) of the wavefront collect, into cand, the table
+// indices of the surviving p of n_all[idx] ranked [G way, G way + G) from
+// resume_in[idx] on; returns how many there are (fewer at the table's end).
+// Way nways - 1 writes the table index after its group (nprimes at the
+// table's end) to resume_out[idx].  resume_in is only read during the pass:
+// the groups of one n run in any order, so a write into the array the others
+// read would move their groups.
 template <int K>
-__device__ __forceinline__ void big_search(uint32_t blk, const uint32_t *n_all, const uint32_t *list, uint32_t nlist,
-                                           uint32_t nways, const uint32_t *primes, uint32_t nprimes,
-                                           const uint32_t *resume_in, uint32_t *resume_out, uint32_t *found)
+__device__ __forceinline__ uint32_t big_collect(uint32_t *cand, uint32_t G, uint32_t way, uint32_t nways,
+                                                uint32_t idx, const uint32_t *n_all, const uint32_t *primes,
+                                                uint32_t nprimes, const uint32_t *resume_in, uint32_t *resume_out)
 {
-    __shared__ uint32_t cand_all[4][64];
     const uint32_t lane = threadIdx.x & 63u;
-    const uint32_t wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const uint32_t slot = blk * 4u + wv;
-    if (slot >= nlist * nways) return;               // whole wave
-    const uint32_t li = slot / nways, way = slot - li * nways;
-    const uint32_t idx = list ? list[li] : li;
-    uint32_t *cand = cand_all[wv];
     gbbig28::Num<K> n;
 #pragma unroll
     for (int i = 0; i < K; ++i) n.w[i] = n_all[(uint64_t)idx * K + i];
@@ -95,8 +94,7 @@ __device__ __forceinline__ void big_search(uint32_t blk, const uint32_t *n_all, 
     uint32_t nres[24];
 #pragma unroll
     for (int j = 0; j < 24; ++j) nres[j] = mod_small(n, kOddBases[j]);
-    // table indices of the surviving p ranked [lo, hi) from resume_in[idx] on
-    const uint32_t lo = 64u * way, hi = lo + 64u;
+    const uint32_t lo = G * way, hi = lo + G;
     uint32_t got = 0, next = resume_in[idx];
     while (got < hi && next < nprimes) {
         const uint32_t c = next + lane;
@@ -120,57 +118,80 @@ __device__ __forceinline__ void big_search(uint32_t blk, const uint32_t *n_all, 
         }
     }
     if (way == nways - 1u && lane == 0u) resume_out[idx] = next;
-    const uint32_t cnt = got > lo ? got - lo : 0u;
-    if (cnt == 0u) return;                           // the table ends before the group
-    __builtin_amdgcn_wave_barrier();
-    const bool act = lane < cnt;
-    const uint32_t c = act ? cand[lane] : 0u;
-    const uint32_t p = act ? primes[c] : 3u;
-    // q = n - p (n >= 2^64 > p)
-    gbbig28::Num<K> q;
-    big_sub_p(q, n.w, p);
-    const bool pass2 = act && gbbig28::strong_prp2<K>(q);
-    const unsigned long long m = __builtin_amdgcn_ballot_w64(pass2);
-    if (m != 0ull && lane == 0u)
-        __hip_atomic_fetch_min(&found[idx], __builtin_amdgcn_readlane(c, (uint32_t)__builtin_ctzll(m)), __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_AGENT);
+    return got > lo ? got - lo : 0u;
 }
 
-// One lane per (n, base 3 .. 97): bad[idx] is set when the candidate's q
-// fails a base.
-template <int K>
-__device__ __forceinline__ void big_confirm(uint32_t blk, const uint32_t *n_all, const uint32_t *list, uint32_t nlist,
-                                            const uint32_t *primes, uint32_t nprimes, const uint32_t *found,
-                                            uint32_t *bad)
-{
-    const uint32_t g = blk * 256u + threadIdx.x;
-    if (g >= nlist * 24u) return;
-    const uint32_t slot = g / 24u, j = g - slot * 24u;
-    const uint32_t idx = list ? list[slot] : slot;
-    const uint32_t c = found[idx];
-    if (c >= nprimes) return;                        // nothing to confirm
-    const uint32_t p = primes[c];
-    gbbig28::Num<K> q;
-    big_sub_p(q, n_all + (uint64_t)idx * K, p);
-    if (!gbbig28::strong_prp<K>(q, kBigBases[j + 1u]))
-        __hip_atomic_fetch_or(&bad[idx], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// One pass: blocks [0, sblocks) search the open n of slist (nslist n,
-// nways wavefronts each; entries of found for them all ones), the other
-// blocks confirm the candidates of the n in clist, found in the pass before,
-// so that both run side by side.
+// One pass.  Lane task t (64 per wavefront, blockIdx.x * 256 + threadIdx.x):
+// t < S0 = nslist nways G is lane t mod G of search group t / G, which is way
+// (t / G) mod nways of the ((t / G) / nways)-th n of slist (of all n when
+// slist is null; their found entries are all ones before the pass); the
+// next nclist * 24 tasks confirm the candidates of the n of clist, found in
+// the pass before, one odd base each.
 template <int K>
 __global__ __launch_bounds__(256) void k_big_pass(const uint32_t *n_all, const uint32_t *slist, uint32_t nslist,
-                                                  uint32_t nways, uint32_t sblocks, const uint32_t *clist,
-                                                  uint32_t nclist, const uint32_t *primes, uint32_t nprimes,
-                                                  const uint32_t *resume_in, uint32_t *resume_out, uint32_t *found,
-                                                  uint32_t *bad)
+                                                  uint32_t G, uint32_t nways, const uint32_t *clist, uint32_t nclist,
+                                                  const uint32_t *primes, uint32_t nprimes, const uint32_t *resume_in,
+                                                  uint32_t *resume_out, uint32_t *found, uint32_t *bad)
 {
-    if (blockIdx.x < sblocks)
-        big_search<K>(blockIdx.x, n_all, slist, nslist, nways, primes, nprimes, resume_in, resume_out, found);
-    else
-        big_confirm<K>(blockIdx.x - sblocks, n_all, clist, nclist, primes, nprimes, found, bad);
+    __shared__ uint32_t cand_all[4][64];
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const uint64_t t0 = ((uint64_t)blockIdx.x * 4u + wv) * 64u;
+    const uint64_t S0 = (uint64_t)nslist * nways * G;
+    const uint64_t total = S0 + (uint64_t)nclist * 24u;
+    if (t0 >= total) return;                         // whole wave
+    uint32_t *cand = cand_all[wv];
+    // the search groups among this wave's lanes (G divides 64, so a group
+    // never straddles two wavefronts)
+    uint32_t gidx0 = 0u, gidx1 = 0u, gcnt0 = 0u, gcnt1 = 0u;
+    const uint32_t ngw = 64u / G;
+    for (uint32_t gi = 0; gi < ngw && t0 + (uint64_t)gi * G < S0; ++gi) {
+        const uint32_t grp = (uint32_t)((t0 + (uint64_t)gi * G) / G);
+        const uint32_t li = grp / nways, way = grp - li * nways;
+        const uint32_t idx = slist ? slist[li] : li;
+        const uint32_t cnt =
+            big_collect<K>(cand + gi * G, G, way, nways, idx, n_all, primes, nprimes, resume_in, resume_out);
+        if (gi == 0u) {
+            gidx0 = idx;
+            gcnt0 = cnt;
+        } else {
+            gidx1 = idx;
+            gcnt1 = cnt;
+        }
+    }
+    __builtin_amdgcn_wave_barrier();
+    const uint64_t t = t0 + lane;
+    const bool srch = t < S0;
+    bool act = false;
+    uint32_t idx = 0u, c = 0u, base = 2u;
+    if (srch) {
+        const uint32_t gi = lane / G;
+        idx = gi ? gidx1 : gidx0;
+        act = lane - gi * G < (gi ? gcnt1 : gcnt0);
+        c = act ? cand[lane] : 0u;
+    } else if (t < total) {
+        const uint64_t k = t - S0;
+        const uint32_t ci = (uint32_t)(k / 24u), j = (uint32_t)(k - (uint64_t)ci * 24u);
+        idx = clist[ci];
+        c = found[idx];
+        act = c < nprimes;                           // else nothing to confirm
+        base = kBigBases[j + 1u];
+    }
+    bool pass = false;
+    if (act) {
+        gbbig28::Num<K> q;
+        big_sub_p(q, n_all + (uint64_t)idx * K, primes[c]);
+        pass = gbbig28::strong_prp<K>(q, base);
+    }
+    const unsigned long long m = __builtin_amdgcn_ballot_w64(srch && pass);
+    for (uint32_t gi = 0; gi < ngw; ++gi) {
+        const unsigned long long gm = G == 64u ? m : (m >> (gi * 32u)) & 0xFFFFFFFFull;
+        if (gm != 0ull && lane == 0u)
+            __hip_atomic_fetch_min(&found[gi ? gidx1 : gidx0],
+                                   __builtin_amdgcn_readlane(c, gi * G + (uint32_t)__builtin_ctzll(gm)),
+                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    if (!srch && act && !pass) __hip_atomic_fetch_or(&bad[idx], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // The one-kernel form, used for 32 limbs: the same filter and base-2 search
@@ -253,79 +274,31 @@ __global__ __launch_bounds__(256) void k_big_wave(const uint32_t *n_all, uint64_
 }
 
 template <int K>
-hipError_t launch_pass(const uint32_t *n, const uint32_t *slist, uint32_t nslist, uint32_t nways, const uint32_t *clist,
-                       uint32_t nclist, const uint32_t *primes, uint32_t nprimes, const uint32_t *resume_in,
-                       uint32_t *resume_out, uint32_t *found, uint32_t *bad, hipStream_t st)
+hipError_t launch_pass(const uint32_t *n, const uint32_t *slist, uint32_t nslist, uint32_t G, uint32_t nways,
+                       const uint32_t *clist, uint32_t nclist, const uint32_t *primes, uint32_t nprimes,
+                       const uint32_t *resume_in, uint32_t *resume_out, uint32_t *found, uint32_t *bad, hipStream_t st)
 {
-    const uint32_t sblocks = (uint32_t)(((uint64_t)nslist * nways + 3u) / 4u);
-    const uint32_t cblocks = (uint32_t)(((uint64_t)nclist * 24u + 255u) / 256u);
-    hipLaunchKernelGGL(k_big_pass<K>, dim3(sblocks + cblocks), dim3(256), 0, st, n, slist, nslist, nways, sblocks, clist,
-                       nclist, primes, nprimes, resume_in, resume_out, found, bad);
+    const uint64_t tasks = (uint64_t)nslist * nways * G + (uint64_t)nclist * 24u;
+    hipLaunchKernelGGL(k_big_pass<K>, dim3((uint32_t)((tasks + 255u) / 256u)), dim3(256), 0, st, n, slist, nslist, G,
+                       nways, clist, nclist, primes, nprimes, resume_in, resume_out, found, bad);
     return hipGetLastError();
 }
 
-}  // namespace
+// Pass shape: the first pass gives every n one group of kFirstGroup
+// survivors; later passes give each open n kLaterGroup-lane groups, as many
+// ways as keep about one search wavefront per SIMD busy (at most 16), so
+// that the n with large p_min do not run alone.
+constexpr uint32_t kFirstGroup = 32, kLaterGroup = 32, kMaxWays = 16;
 
-using namespace gbrt;
-
-gb_status gb_verify_big(gb_ctx *c, const uint32_t *n, uint32_t nlimbs, size_t k, uint64_t *p, void *stream)
+// The n of one limb count K (28-bit limbs): h holds them, K limbs each
+// (k n); their answers go to ans (table indices, UINT32_MAX for none).
+template <int K>
+gb_status big28_passes(gb_ctx *c, const std::vector<uint32_t> &h, size_t k, std::vector<uint32_t> &ans,
+                       hipStream_t st)
 {
-    if (!c || (k && (!n || !p))) return fail(c, GB_EINVAL, "null argument");
-    if (nlimbs < 3 || nlimbs > 32) return fail(c, GB_EINVAL, "nlimbs must be in 3..32");
-    if (k == 0) return GB_OK;
-    if (k > (1ull << 24)) return fail(c, GB_EINVAL, "at most 2^24 n per call");
-    // every n even and at least 2^64; the bit length of the largest
-    uint32_t bits = 0;
-    for (size_t i = 0; i < k; ++i) {
-        const uint32_t *w = n + i * nlimbs;
-        bool big = false;
-        for (uint32_t j = 2; j < nlimbs; ++j) big = big || w[j] != 0u;
-        if ((w[0] & 1u) || !big) return fail(c, GB_EINVAL, "n must be even and at least 2^64");
-        for (uint32_t j = nlimbs; j-- > 0;)
-            if (w[j]) {
-                bits = std::max(bits, 32u * j + 32u - (uint32_t)__builtin_clz(w[j]));
-                break;
-            }
-    }
-    // Forms compiled: 4, 8, 12 and 16 limbs of 28 bits (n below 2^448, the
-    // two-kernel form), and 32 limbs of 32 bits (the one-kernel form).  A
-    // 24-limb form of 32 bits returned wrong answers on gfx950 (its host build
-    // is right; its device code keeps the multiplier in scratch), and the
-    // two-kernel form at 32 limbs did not finish a 520-bit case, so every n
-    // of 449 bits or more runs in the one-kernel 32-limb form.
-    const int K = bits <= 112 ? 4 : bits <= 224 ? 8 : bits <= 336 ? 12 : bits <= 448 ? 16 : 32;
-    if (hipSetDevice(c->prm.device) != hipSuccess) return fail(c, GB_EDEVICE, "hipSetDevice failed");
-    hipStream_t st = static_cast<hipStream_t>(stream);
-    std::vector<uint32_t> h((size_t)k * K, 0u);
-    if (K == 32) {
-        // padded to 32 limbs of 32 bits
-        for (size_t i = 0; i < k; ++i) std::memcpy(&h[i * K], n + i * nlimbs, nlimbs * 4);
-    } else {
-        // K limbs of 28 bits: limb l is bits 28 l .. 28 l + 27
-        for (size_t i = 0; i < k; ++i) {
-            const uint32_t *w = n + i * nlimbs;
-            for (int l = 0; l < K; ++l) {
-                const uint32_t b0 = 28u * (uint32_t)l, j = b0 >> 5, o = b0 & 31u;
-                uint64_t v = j < nlimbs ? w[j] : 0u;
-                if (j + 1 < nlimbs) v |= (uint64_t)w[j + 1] << 32;
-                h[i * K + l] = (uint32_t)(v >> o) & gbbig28::kMask;
-            }
-        }
-    }
     Workspace &ws = c->ws;
     GB_HIP(c, ws.big_n.ensure(h.size()));
     GB_HIP(c, hipMemcpyAsync(ws.big_n.p, h.data(), h.size() * 4, hipMemcpyHostToDevice, st));
-    if (K == 32) {
-        GB_HIP(c, ws.big_p.ensure(k));
-        hipLaunchKernelGGL(k_big_wave<32>, dim3((uint32_t)((k + 3) / 4)), dim3(256), 0, st, ws.big_n.p, (uint64_t)k,
-                           c->d_primes, c->ntab, ws.big_p.p);
-        GB_HIP(c, hipGetLastError());
-        GB_HIP(c, hipMemcpyAsync(p, ws.big_p.p, k * 8, hipMemcpyDeviceToHost, st));
-        GB_HIP(c, hipStreamSynchronize(st));
-        for (size_t i = 0; i < k; ++i)
-            if (p[i] == 0) return fail(c, GB_EUNRESOLVED, "no partition with p in the resident prime table");
-        return GB_OK;
-    }
     GB_HIP(c, ws.big_state.ensure(4 * k));
     GB_HIP(c, ws.big_list.ensure(2 * k));
     GB_HIP(c, ws.h_big.ensure(6 * k));
@@ -336,17 +309,16 @@ gb_status gb_verify_big(gb_ctx *c, const uint32_t *n, uint32_t nlimbs, size_t k,
              *hcl = hsl + k;
     uint32_t *d_resume = ws.big_state.p, *d_found = d_resume + k, *d_rout = d_found + k, *d_bad = d_rout + k;
     std::fill(resume, resume + k, 0u);
-    std::vector<uint32_t> ans(k, UINT32_MAX), sl, cl, nsl, ncl;
+    ans.assign(k, UINT32_MAX);
+    std::vector<uint32_t> sl, cl, nsl, ncl;
     bool all = true;                                 // the first pass searches every n
-    uint32_t nways = 1;
+    uint32_t G = kFirstGroup, nways = 1;
     // Each pass searches the open n and confirms the candidates found in the
-    // pass before.  The n still open get several wavefronts each, one per
-    // group of 64 surviving p, so that the last n do not run alone.  Every
-    // pass moves each open n's resume point forward, so the loop ends; the
-    // cap stops a call whose device results do not settle.
-    const uint32_t target = (uint32_t)c->num_cu * 16u;
+    // pass before.  Every pass moves each open n's resume point forward, so
+    // the loop ends; the cap stops a call whose device results do not settle.
+    const uint64_t target = (uint64_t)c->num_cu * 4u * 64u;   // search lanes: one wavefront per SIMD
     for (int pass = 0;; ++pass) {
-        if (pass == 256) return fail(c, GB_EDEVICE, "big-n search did not settle");
+        if (pass == 1024) return fail(c, GB_EDEVICE, "big-n search did not settle");
         const uint32_t nslist = all ? (uint32_t)k : (uint32_t)sl.size(), nclist = (uint32_t)cl.size();
         if (all)
             std::fill(found, found + k, UINT32_MAX);
@@ -360,14 +332,8 @@ gb_status gb_verify_big(gb_ctx *c, const uint32_t *n, uint32_t nlimbs, size_t k,
         if (!all && nslist) GB_HIP(c, hipMemcpyAsync(ws.big_list.p, hsl, nslist * 4, hipMemcpyHostToDevice, st));
         if (nclist) GB_HIP(c, hipMemcpyAsync(ws.big_list.p + k, hcl, nclist * 4, hipMemcpyHostToDevice, st));
         const uint32_t *dsl = all ? nullptr : ws.big_list.p, *dcl = ws.big_list.p + k;
-        hipError_t e;
-        switch (K) {
-        case 4: e = launch_pass<4>(ws.big_n.p, dsl, nslist, nways, dcl, nclist, c->d_primes, np, d_resume, d_rout, d_found, d_bad, st); break;
-        case 8: e = launch_pass<8>(ws.big_n.p, dsl, nslist, nways, dcl, nclist, c->d_primes, np, d_resume, d_rout, d_found, d_bad, st); break;
-        case 12: e = launch_pass<12>(ws.big_n.p, dsl, nslist, nways, dcl, nclist, c->d_primes, np, d_resume, d_rout, d_found, d_bad, st); break;
-        default: e = launch_pass<16>(ws.big_n.p, dsl, nslist, nways, dcl, nclist, c->d_primes, np, d_resume, d_rout, d_found, d_bad, st); break;
-        }
-        GB_HIP(c, e);
+        GB_HIP(c, launch_pass<K>(ws.big_n.p, dsl, nslist, G, nways, dcl, nclist, c->d_primes, np, d_resume, d_rout,
+                                 d_found, d_bad, st));
         GB_HIP(c, hipMemcpyAsync(found, d_found, 3 * k * 4, hipMemcpyDeviceToHost, st));   // found, resume out, bad
         GB_HIP(c, hipStreamSynchronize(st));
         // the searched n continue after the groups this pass took
@@ -396,12 +362,106 @@ gb_status gb_verify_big(gb_ctx *c, const uint32_t *n, uint32_t nlimbs, size_t k,
         sl.swap(nsl);
         cl.swap(ncl);
         all = false;
-        nways = sl.empty() ? 1u : std::max(1u, std::min(16u, target / (uint32_t)sl.size()));
+        G = kLaterGroup;
+        nways = sl.empty() ? 1u
+                           : (uint32_t)std::max<uint64_t>(1u, std::min<uint64_t>(kMaxWays, target / ((uint64_t)sl.size() * G)));
+    }
+    return GB_OK;
+}
+
+}  // namespace
+
+using namespace gbrt;
+
+gb_status gb_verify_big(gb_ctx *c, const uint32_t *n, uint32_t nlimbs, size_t k, uint64_t *p, void *stream)
+{
+    if (!c || (k && (!n || !p))) return fail(c, GB_EINVAL, "null argument");
+    if (nlimbs < 3 || nlimbs > 32) return fail(c, GB_EINVAL, "nlimbs must be in 3..32");
+    if (k == 0) return GB_OK;
+    if (k > (1ull << 24)) return fail(c, GB_EINVAL, "at most 2^24 n per call");
+    // every n even and at least 2^64; the bit length of each
+    std::vector<uint16_t> bits(k, 0);
+    for (size_t i = 0; i < k; ++i) {
+        const uint32_t *w = n + i * nlimbs;
+        bool big = false;
+        for (uint32_t j = 2; j < nlimbs; ++j) big = big || w[j] != 0u;
+        if ((w[0] & 1u) || !big) return fail(c, GB_EINVAL, "n must be even and at least 2^64");
+        for (uint32_t j = nlimbs; j-- > 0;)
+            if (w[j]) {
+                bits[i] = (uint16_t)(32u * j + 32u - (uint32_t)__builtin_clz(w[j]));
+                break;
+            }
+    }
+    if (hipSetDevice(c->prm.device) != hipSuccess) return fail(c, GB_EDEVICE, "hipSetDevice failed");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    // Forms: the smallest even K with 28K - 2 >= bits (n of at most 446 bits,
+    // so q = n - p has 28K - 58 bits or more, which the 28-bit arithmetic
+    // needs), one pass sequence per K present; 32 limbs of 32 bits (the
+    // one-kernel form) from 447 bits on.  The two-kernel form at 32 limbs did
+    // not finish a 520-bit case on the GPU and a 24-limb 32-bit form returned
+    // wrong answers (both explained by a base-2 test that failed primes), so
+    // they are not used.
+    std::vector<uint32_t> wide;
+    std::vector<uint32_t> sel[17];
+    for (size_t i = 0; i < k; ++i) {
+        if (bits[i] > 446) {
+            wide.push_back((uint32_t)i);
+            continue;
+        }
+        const uint32_t K = std::max(4u, (((uint32_t)bits[i] + 2u + 27u) / 28u + 1u) & ~1u);
+        sel[K].push_back((uint32_t)i);
     }
     bool unresolved = false;
-    for (size_t i = 0; i < k; ++i) {
-        p[i] = ans[i] < np ? c->h_primes[ans[i]] : 0ull;
-        unresolved = unresolved || p[i] == 0;
+    for (int K = 4; K <= 16; K += 2) {
+        if (sel[K].empty()) continue;
+        const size_t kk = sel[K].size();
+        // K limbs of 28 bits: limb l is bits 28 l .. 28 l + 27
+        std::vector<uint32_t> h(kk * (size_t)K, 0u);
+        for (size_t a = 0; a < kk; ++a) {
+            const uint32_t *w = n + (size_t)sel[K][a] * nlimbs;
+            for (int l = 0; l < K; ++l) {
+                const uint32_t b0 = 28u * (uint32_t)l, j = b0 >> 5, o = b0 & 31u;
+                uint64_t v = j < nlimbs ? w[j] : 0u;
+                if (j + 1 < nlimbs) v |= (uint64_t)w[j + 1] << 32;
+                h[a * K + l] = (uint32_t)(v >> o) & gbbig28::kMask;
+            }
+        }
+        std::vector<uint32_t> ans;
+        gb_status r;
+        switch (K) {
+        case 4: r = big28_passes<4>(c, h, kk, ans, st); break;
+        case 6: r = big28_passes<6>(c, h, kk, ans, st); break;
+        case 8: r = big28_passes<8>(c, h, kk, ans, st); break;
+        case 10: r = big28_passes<10>(c, h, kk, ans, st); break;
+        case 12: r = big28_passes<12>(c, h, kk, ans, st); break;
+        case 14: r = big28_passes<14>(c, h, kk, ans, st); break;
+        default: r = big28_passes<16>(c, h, kk, ans, st); break;
+        }
+        if (r != GB_OK) return r;
+        for (size_t a = 0; a < kk; ++a) {
+            const uint32_t i = sel[K][a];
+            p[i] = ans[a] < c->ntab ? c->h_primes[ans[a]] : 0ull;
+            unresolved = unresolved || p[i] == 0;
+        }
+    }
+    if (!wide.empty()) {
+        const size_t kw = wide.size();
+        std::vector<uint32_t> h(kw * 32, 0u);                // padded to 32 limbs of 32 bits
+        for (size_t a = 0; a < kw; ++a) std::memcpy(&h[a * 32], n + (size_t)wide[a] * nlimbs, nlimbs * 4);
+        Workspace &ws = c->ws;
+        GB_HIP(c, ws.big_n.ensure(h.size()));
+        GB_HIP(c, hipMemcpyAsync(ws.big_n.p, h.data(), h.size() * 4, hipMemcpyHostToDevice, st));
+        GB_HIP(c, ws.big_p.ensure(kw));
+        hipLaunchKernelGGL(k_big_wave<32>, dim3((uint32_t)((kw + 3) / 4)), dim3(256), 0, st, ws.big_n.p, (uint64_t)kw,
+                           c->d_primes, c->ntab, ws.big_p.p);
+        GB_HIP(c, hipGetLastError());
+        std::vector<unsigned long long> pw(kw);
+        GB_HIP(c, hipMemcpyAsync(pw.data(), ws.big_p.p, kw * 8, hipMemcpyDeviceToHost, st));
+        GB_HIP(c, hipStreamSynchronize(st));
+        for (size_t a = 0; a < kw; ++a) {
+            p[wide[a]] = pw[a];
+            unresolved = unresolved || pw[a] == 0;
+        }
     }
     if (unresolved) return fail(c, GB_EUNRESOLVED, "no partition with p in the resident prime table");
     return GB_OK;

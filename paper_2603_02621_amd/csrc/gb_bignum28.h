@@ -4,13 +4,23 @@
 // n beyond 64 bits (paper section "Arbitrary Precision Checker", which tests
 // q = n - p with Miller-Rabin).
 //
-// Montgomery multiplication (Montgomery 1985) with R = 2^(28K) in the finely
-// integrated product-scanning order (Koc, Acar and Kaliski 1996).  With
-// 28-bit limbs a product is below 2^56 and a column of at most 2K + 1 <= 33
-// products plus the carry from the column before stays below 2^62, so a
-// column sums in one 64-bit accumulator: one 64-bit multiply-add per limb
-// product and no carry handling.  Host and device: the same code runs in a
-// lane or on the CPU.
+// Arithmetic mod an odd m with 2^(28K - 60) <= m < 2^(28K - 2), R = 2^(28K):
+//
+// - Montgomery squaring (Montgomery 1985) in the finely integrated
+//   product-scanning order (Koc, Acar and Kaliski 1996), each cross product
+//   taken once and doubled.  With 28-bit limbs a column of at most 2K + 1
+//   products plus the carry stays below 2^62, so a column sums in one 64-bit
+//   accumulator: one 64-bit multiply-add per limb product, no carry handling.
+// - Lazy reduction: operands and results lie in [0, 2m), not [0, m).  As
+//   4m < R, a squaring of a value below 2m ends below 2m without the final
+//   conditional subtraction; values are brought into [0, m) only where they
+//   are compared.
+// - Multiplication by a small integer f <= 2^20: x f - h m, with the quotient
+//   h estimated from the top three limbs of x and of m in double precision,
+//   rounded down so that h never exceeds the true quotient; the result is
+//   below 1.2 m (the bound is worked out at mul_small).
+//
+// Host and device: the same code runs in a lane or on the CPU.
 #pragma once
 #include <cstdint>
 
@@ -29,13 +39,6 @@ __host__ __device__ inline uint32_t neg_inv28(uint32_t m)
     uint32_t x = m;
     for (int i = 0; i < 4; ++i) x *= 2u - m * x;
     return (0u - x) & kMask;
-}
-
-template <int K> __host__ __device__ inline bool geq(const Num<K> &a, const Num<K> &b)
-{
-    for (int i = K - 1; i >= 0; --i)
-        if (a.w[i] != b.w[i]) return a.w[i] > b.w[i];
-    return true;
 }
 
 template <int K> __host__ __device__ inline bool equal(const Num<K> &a, const Num<K> &b)
@@ -59,71 +62,82 @@ template <int K> __host__ __device__ inline uint32_t sub(Num<K> &r, const Num<K>
     return br;
 }
 
-// (2a) mod m for a < m
-template <int K> __host__ __device__ inline void dbl_mod(Num<K> &a, const Num<K> &m)
+// a mod m for a < 2m
+template <int K> __host__ __device__ inline void reduce_once(Num<K> &a, const Num<K> &m)
 {
-    uint32_t c = 0;
+    Num<K> d;
+    const uint32_t br = sub(d, a, m);
 #pragma unroll
-    for (int i = 0; i < K; ++i) {
-        const uint32_t t = (a.w[i] << 1) | c;
-        c = t >> kBits;
-        a.w[i] = t & kMask;
-    }
-    if (c || geq(a, m)) sub(a, a, m);
+    for (int i = 0; i < K; ++i) a.w[i] = br ? a.w[i] : d.w[i];
 }
 
-// (a + b) mod m for a, b < m
-template <int K> __host__ __device__ inline void add_mod(Num<K> &a, const Num<K> &b, const Num<K> &m)
-{
-    uint32_t c = 0;
-#pragma unroll
-    for (int i = 0; i < K; ++i) {
-        const uint32_t t = a.w[i] + b.w[i] + c;
-        c = t >> kBits;
-        a.w[i] = t & kMask;
-    }
-    if (c || geq(a, m)) sub(a, a, m);
-}
-
-// a b R^(-1) mod m for a, b < m < R, m odd: column i collects every
-// a_j b_(i-j) and u_j m_(i-j); the low columns choose u_i = t ninv mod 2^28 so
-// that the column's low 28 bits become zero, the high columns are the result.
-// Fully unrolled, so every limb stays in a register.
+// a^2 R^(-1) mod m, lazily: for a < 2m the result is below 2m (4m < R).
+// Column i collects every a_j a_(i-j) (the pairs j < i - j once, doubled,
+// and a_(i/2)^2) and u_j m_(i-j); the low columns choose
+// u_i = t ninv mod 2^28 so that the column's low 28 bits become zero, the
+// high columns are the result.  Fully unrolled, so every limb stays in a
+// register.
 template <int K>
-__host__ __device__ inline void mont_mul(Num<K> &r, const Num<K> &a, const Num<K> &b, const Num<K> &m, uint32_t ninv)
+__host__ __device__ inline void mont_sqr(Num<K> &r, const Num<K> &a, const Num<K> &m, uint32_t ninv)
 {
-    static_assert(K <= 16, "a column of 2K + 1 products must stay below 2^64");
+    static_assert(K >= 4 && K <= 16, "a column of 2K + 1 products must stay below 2^64");
     uint64_t t = 0;
     uint32_t u[K];
 #pragma unroll
     for (int i = 0; i < K; ++i) {
+        uint64_t c = 0;
 #pragma unroll
-        for (int j = 0; j < i; ++j) {
-            t += (uint64_t)a.w[j] * b.w[i - j];
-            t += (uint64_t)u[j] * m.w[i - j];
-        }
-        t += (uint64_t)a.w[i] * b.w[0];
+        for (int j = 0; j < i - j; ++j) c += (uint64_t)a.w[j] * a.w[i - j];
+        t += c << 1;
+        if ((i & 1) == 0) t += (uint64_t)a.w[i / 2] * a.w[i / 2];
+#pragma unroll
+        for (int j = 0; j < i; ++j) t += (uint64_t)u[j] * m.w[i - j];
         u[i] = ((uint32_t)t * ninv) & kMask;
         t += (uint64_t)u[i] * m.w[0];                // the low 28 bits are now zero
         t >>= kBits;
     }
-    Num<K> s;
 #pragma unroll
     for (int i = K; i < 2 * K; ++i) {
+        uint64_t c = 0;
 #pragma unroll
-        for (int j = i - K + 1; j < K; ++j) {
-            t += (uint64_t)a.w[j] * b.w[i - j];
-            t += (uint64_t)u[j] * m.w[i - j];
-        }
-        s.w[i - K] = (uint32_t)t & kMask;
+        for (int j = i - K + 1; j < i - j; ++j) c += (uint64_t)a.w[j] * a.w[i - j];
+        t += c << 1;
+        if ((i & 1) == 0 && i / 2 < K) t += (uint64_t)a.w[i / 2] * a.w[i / 2];
+#pragma unroll
+        for (int j = i - K + 1; j < K; ++j) t += (uint64_t)u[j] * m.w[i - j];
+        r.w[i - K] = (uint32_t)t & kMask;
         t >>= kBits;
     }
-    // (t, s) < 2m: one conditional subtraction
-    Num<K> d;
-    const uint32_t br = sub(d, s, m);
-    const bool keep = (uint32_t)t == 0u && br != 0u;   // below m
+    // (a^2 + U m) / R < (4 m^2 + R m) / R < 2m < R: nothing is left in t
+}
+
+// The quotient estimate's scale for m: (1 - 2^-40) / (M3 + 1), where M3 is
+// m's top three limbs (m / 2^(28(K-3)) rounded down) in double precision.
+template <int K> __host__ __device__ inline double est_recip(const Num<K> &m)
+{
+    const double top = ((double)m.w[K - 1] * 268435456.0 + (double)m.w[K - 2]) * 268435456.0 + (double)m.w[K - 3];
+    return (1.0 - 0x1p-40) / (top + 1.0);
+}
+
+// x <- x f mod m, lazily, for x < 2m and 1 <= f <= 2^20 (rq = est_recip(m)).
+// With X = x f, M' = m / 2^(28(K-3)) >= 2^24 and x' = x / 2^(28(K-3)) < 2M',
+// the estimate h = floor(f X3 rq) (X3: x's top three limbs) never exceeds
+// X / m: each of the few roundings moves a value by at most 2^-51 of itself,
+// and the factor 1 - 2^-40 in rq covers them.  It falls short of X / m by
+// less than 1 + f (3 / M' + 2^-37) < 1.19, so X - h m lies in [0, 1.19 m).
+// One pass over the limbs forms x_i f - h m_i plus the signed carry.
+template <int K> __host__ __device__ inline void mul_small(Num<K> &x, uint32_t f, const Num<K> &m, double rq)
+{
+    const double xd = ((double)x.w[K - 1] * 268435456.0 + (double)x.w[K - 2]) * 268435456.0 + (double)x.w[K - 3];
+    const int32_t nh = -(int32_t)(uint32_t)(xd * (double)f * rq);   // h < 2^21
+    int64_t c = 0;
 #pragma unroll
-    for (int i = 0; i < K; ++i) r.w[i] = keep ? s.w[i] : d.w[i];
+    for (int i = 0; i < K; ++i) {
+        int64_t t = (int64_t)(int32_t)x.w[i] * (int32_t)f + c;
+        t += (int64_t)nh * (int32_t)m.w[i];
+        x.w[i] = (uint32_t)t & kMask;
+        c = t >> kBits;                              // arithmetic: the carry may be negative
+    }
 }
 
 template <int K> __host__ __device__ inline int bit_length(const Num<K> &a)
@@ -143,101 +157,84 @@ template <int K> __host__ __device__ inline uint32_t limb_at(const Num<K> &a, in
     return r;
 }
 
-template <int K> __host__ __device__ inline uint32_t bit(const Num<K> &a, int i)
-{
-    const int j = i / (int)kBits;
-    return (limb_at(a, j) >> (i - j * (int)kBits)) & 1u;
-}
-
-// R mod q, q odd with nb bits: 2^(nb-1) < q doubled 28K - nb + 1 times
-template <int K> __host__ __device__ inline void mont_one(Num<K> &one, const Num<K> &q, int nb)
+// R mod m, m odd with nb bits: 2^(nb-1) < m multiplied by 2^(28K - nb + 1)
+// in steps of at most 2^20, then brought below m.
+template <int K> __host__ __device__ inline void mont_one(Num<K> &one, const Num<K> &m, int nb, double rq)
 {
     const int top = (nb - 1) / (int)kBits;
 #pragma unroll
     for (int i = 0; i < K; ++i) one.w[i] = (i == top) ? 1u << (nb - 1 - top * (int)kBits) : 0u;
-    for (int i = nb - 1; i < (int)kBits * K; ++i) dbl_mod(one, q);
+    for (int e = (int)kBits * K - nb + 1; e > 0; e -= 20) mul_small(one, 1u << (e < 20 ? e : 20), m, rq);
+    reduce_once(one, m);
 }
 
-// The end of the strong test: with x = a^d R mod q, true when a^d = 1 or -1,
-// or a^(d 2^r) = -1 for some 0 < r < s.  R mod q and q - R mod q are formed
-// here, after the exponentiation, so that they hold no registers during it.
-template <int K> __host__ __device__ inline bool strong_tail(Num<K> &x, const Num<K> &q, uint32_t ninv, int nb, int s)
+// Strong probable prime to base a: q odd with 2^(28K - 60) <= q < 2^(28K - 2),
+// 2 <= a <= 101 (so that a^3 <= 2^20).  With q - 1 = d 2^s, d odd: true when
+// a^d = 1 or -1 mod q, or a^(d 2^r) = -1 for some 0 < r < s.
+//
+// a^d is taken left to right over 2-bit windows of d, in Montgomery form:
+// two squarings, then one multiplication by a^v <= 2^20 for the window's
+// value v (by 1 when v = 0, so that every lane does the same work).  d is
+// first shifted so that its lowest window ends at an even bit position e and
+// its top bit lies in the top window (bits 28K - 2, 28K - 1), so the windows
+// of every q sit at the same positions and a window never straddles two
+// limbs; only where the windows end (e) differs from q to q.
+template <int K> __host__ __device__ inline bool strong_prp(const Num<K> &q, uint32_t a)
 {
+    const uint32_t ninv = neg_inv28(q.w[0]);
+    const double rq = est_recip(q);
+    const int nb = bit_length(q);
+    // s: the lowest set bit of q - 1 (q odd: bit 0 is the one cleared)
+    int s = 0;
+#pragma unroll
+    for (int i = K - 1; i >= 0; --i) {
+        const uint32_t w = i == 0 ? q.w[0] & ~1u : q.w[i];
+        if (w) s = (int)kBits * i + __builtin_ctz(w);
+    }
+    if (s == 0) return false;                        // q = 1
+    // dd = (q - 1) << t: d's bits at [e, 28K), zeros below
+    const int e = ((int)kBits * K - nb + s) & ~1;
+    const int t = e - s;                             // 1 <= t <= 59
+    const int L = t / (int)kBits, b = t - L * (int)kBits;
+    Num<K> dd;
+#pragma unroll
+    for (int i = K - 1; i >= 0; --i) {
+        const uint32_t w0 = i == 0 ? q.w[0] & ~1u : q.w[i];
+        const uint32_t w1 = i < 1 ? 0u : i == 1 ? q.w[0] & ~1u : q.w[i - 1];
+        const uint32_t w2 = i < 2 ? 0u : i == 2 ? q.w[0] & ~1u : q.w[i - 2];
+        const uint32_t w3 = i < 3 ? 0u : i == 3 ? q.w[0] & ~1u : q.w[i - 3];
+        const uint32_t hi = L == 0 ? w0 : L == 1 ? w1 : w2;
+        const uint32_t lo = L == 0 ? w1 : L == 1 ? w2 : w3;
+        dd.w[i] = ((hi << b) | (b ? lo >> (kBits - b) : 0u)) & kMask;
+    }
+    const uint32_t f1 = a, f2 = a * a, f3 = a * a * a;
+    Num<K> x;
+    mont_one(x, q, nb, rq);
+    {
+        const uint32_t v = dd.w[K - 1] >> (kBits - 2);
+        mul_small(x, v == 1 ? f1 : v == 2 ? f2 : f3, q, rq);   // v != 0: the top bit of d is here
+    }
+    uint32_t wl = dd.w[K - 1];
+    for (int pos = (int)kBits * K - 4; pos >= e; pos -= 2) {
+        const int li = pos / (int)kBits, off = pos - li * (int)kBits;
+        if (off == (int)kBits - 2) wl = limb_at(dd, li);
+        const uint32_t v = (wl >> off) & 3u;
+        mont_sqr(x, x, q, ninv);
+        mont_sqr(x, x, q, ninv);
+        mul_small(x, v == 0 ? 1u : v == 1 ? f1 : v == 2 ? f2 : f3, q, rq);
+    }
+    reduce_once(x, q);                               // a^d R mod q
     Num<K> one, mone;
-    mont_one(one, q, nb);
+    mont_one(one, q, nb, rq);
     sub(mone, q, one);
     if (equal(x, one) || equal(x, mone)) return true;
     for (int r = 1; r < s; ++r) {
-        mont_mul(x, x, x, q, ninv);
+        mont_sqr(x, x, q, ninv);
+        reduce_once(x, q);
         if (equal(x, mone)) return true;
         if (equal(x, one)) return false;
     }
     return false;
-}
-
-// Strong probable prime to base 2, q odd, 2 < q < R: with q - 1 = d 2^s (d
-// odd), 2^d = 1 or 2^(d 2^r) = -1 mod q for an r < s.  Left to right in
-// Montgomery form; each multiplication by the base is a modular doubling
-// (2 x R mod q from x R mod q), so one squaring per exponent bit.
-template <int K> __host__ __device__ inline bool strong_prp2(const Num<K> &q)
-{
-    const uint32_t ninv = neg_inv28(q.w[0]);
-    const int nb = bit_length(q);
-    int s = 1;
-    while (s < (int)kBits * K && bit(q, s) == 0u) ++s;   // q odd: ends below nb
-    if (s >= (int)kBits * K) return false;
-    const int db = nb - s;                           // bit i of d is bit i + s of q
-    Num<K> x;
-    mont_one(x, q, nb);
-    dbl_mod(x, q);                                   // 2R: the top bit of d
-    for (int i = db - 2; i >= 0; --i) {
-        mont_mul(x, x, x, q, ninv);
-        if (bit(q, i + s)) dbl_mod(x, q);
-    }
-    return strong_tail(x, q, ninv, nb, s);
-}
-
-// Strong probable prime to a small base a (2 <= a < 2^28, a < q).  The
-// exponentiation has one Montgomery product call site (the multiplier
-// selected), so the code stays small.
-template <int K> __host__ __device__ inline bool strong_prp(const Num<K> &q, uint32_t a)
-{
-    const uint32_t ninv = neg_inv28(q.w[0]);
-    const int nb = bit_length(q);
-    int s = 1;
-    while (s < (int)kBits * K && bit(q, s) == 0u) ++s;
-    if (s >= (int)kBits * K) return false;
-    const int db = nb - s;
-    // am = a R mod q, by doubling and adding R mod q
-    Num<K> am;
-    {
-        Num<K> one;
-        mont_one(one, q, nb);
-#pragma unroll
-        for (int i = 0; i < K; ++i) am.w[i] = 0;
-        for (int i = (int)kBits - 1; i >= 0; --i) {
-            dbl_mod(am, q);
-            if ((a >> i) & 1u) add_mod(am, one, q);
-        }
-    }
-    Num<K> x = am;
-    int i = db - 2;
-    bool mul_next = false;
-    while (i >= 0 || mul_next) {
-        Num<K> y;
-#pragma unroll
-        for (int j = 0; j < K; ++j) y.w[j] = mul_next ? am.w[j] : x.w[j];
-        mont_mul(x, x, y, q, ninv);
-        if (mul_next) {
-            mul_next = false;
-            --i;
-        } else if (bit(q, i + s)) {
-            mul_next = true;
-        } else {
-            --i;
-        }
-    }
-    return strong_tail(x, q, ninv, nb, s);
 }
 
 }  // namespace gbbig28

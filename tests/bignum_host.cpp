@@ -6,9 +6,13 @@
 // the big-n oracle without a GPU.
 //
 // Commands on stdin, one per line, answers on stdout:
-//   mul  F K m a b      -> a b R^-1 mod m     (F = 28 or 32 limb bits, R = 2^(F K))
+//   mul  32 K m a b     -> a b R^-1 mod m     (32-bit limbs, R = 2^(32 K))
+//   sqr  28 K m a       -> "r rn": r = the lazy a^2 R^-1 mod m (R = 2^(28 K),
+//                          a < 2m; r < 2m), rn = r mod m
+//   mulsmall 28 K m x f -> "r rn": r = the lazy x f mod m (x < 2m,
+//                          f <= 2^20; r < 1.19 m), rn = r mod m
+//   one  28 K m         -> R mod m
 //   sprp F K q a        -> 1 if q is a strong probable prime to base a, else 0
-//   sprp2 K q           -> the same to base 2 by doublings (28-bit limbs only)
 //   pmin F K n          -> "p groups tests": the minimal p the GPU search
 //                          returns for n (odd primes p ascending, p = n mod r
 //                          dropped for the 24 odd bases r, q = n - p tested to
@@ -124,14 +128,6 @@ template <int K, int F> bool strong(const void *qv, uint32_t a)
         return gbbig::strong_prp<K>(*static_cast<const gbbig::Num<K> *>(qv), a);
 }
 
-template <int K, int F> bool strong2(const void *qv)
-{
-    if constexpr (F == 28)
-        return gbbig28::strong_prp2<K>(*static_cast<const gbbig28::Num<K> *>(qv));
-    else
-        return gbbig::strong_prp<K>(*static_cast<const gbbig::Num<K> *>(qv), 2u);
-}
-
 template <int K, int F> void run(const std::string &cmd, std::istringstream &in)
 {
     using N = std::conditional_t<F == 28, gbbig28::Num<K>, gbbig::Num<K>>;
@@ -140,22 +136,45 @@ template <int K, int F> void run(const std::string &cmd, std::istringstream &in)
         in >> m >> a >> b;
         const N M = from_hex<K, F, N>(m), A = from_hex<K, F, N>(a), B = from_hex<K, F, N>(b);
         N r;
-        if constexpr (F == 28)
-            gbbig28::mont_mul<K>(r, A, B, M, gbbig28::neg_inv28(M.w[0]));
-        else
+        if constexpr (F == 32) {
             gbbig::mont_mul<K>(r, A, B, M, gbbig::neg_inv32(M.w[0]));
-        std::cout << to_hex<K, F, N>(r) << "\n";
+            std::cout << to_hex<K, F, N>(r) << "\n";
+        } else {
+            std::fprintf(stderr, "mul is for 32-bit limbs; 28-bit limbs have sqr and mulsmall\n");
+            std::exit(2);
+        }
+    } else if (cmd == "sqr" || cmd == "mulsmall" || cmd == "one") {
+        if constexpr (F == 28) {
+            std::string m, a;
+            uint32_t f = 0;
+            in >> m;
+            if (cmd != "one") in >> a;
+            if (cmd == "mulsmall") in >> f;
+            const N M = from_hex<K, F, N>(m);
+            N r = cmd == "one" ? M : from_hex<K, F, N>(a);
+            if (cmd == "sqr") {
+                gbbig28::mont_sqr<K>(r, r, M, gbbig28::neg_inv28(M.w[0]));
+            } else if (cmd == "mulsmall") {
+                gbbig28::mul_small<K>(r, f, M, gbbig28::est_recip<K>(M));
+            } else {
+                gbbig28::mont_one<K>(r, M, gbbig28::bit_length<K>(M), gbbig28::est_recip<K>(M));
+                std::cout << to_hex<K, F, N>(r) << "\n";
+                return;
+            }
+            N rn = r;
+            // r < 2m is part of the contract; rn is r reduced once
+            gbbig28::reduce_once<K>(rn, M);
+            std::cout << to_hex<K, F, N>(r) << " " << to_hex<K, F, N>(rn) << "\n";
+        } else {
+            std::fprintf(stderr, "%s is for 28-bit limbs\n", cmd.c_str());
+            std::exit(2);
+        }
     } else if (cmd == "sprp") {
         std::string q;
         uint32_t a;
         in >> q >> a;
         const N Q = from_hex<K, F, N>(q);
         std::cout << (strong<K, F>(&Q, a) ? 1 : 0) << "\n";
-    } else if (cmd == "sprp2") {
-        std::string q;
-        in >> q;
-        const N Q = from_hex<K, F, N>(q);
-        std::cout << (strong2<K, F>(&Q) ? 1 : 0) << "\n";
     } else if (cmd == "pmin" || cmd == "pmin_nobase2") {
         static const std::vector<uint32_t> primes = odd_primes(1u << 22);
         std::string h;
@@ -174,7 +193,7 @@ template <int K, int F> void run(const std::string &cmd, std::istringstream &in)
             if (drop) continue;
             const N q = sub_p<K, F, N>(n, p);
             ++tests;
-            if (nob2 || !strong2<K, F>(&q)) continue;
+            if (nob2 || !strong<K, F>(&q, 2u)) continue;
             bool ok = true;
             for (int j = 1; j < 25 && ok; ++j) ok = strong<K, F>(&q, kBases[j]);
             if (ok) ans = p;
@@ -196,13 +215,15 @@ int main()
         std::string cmd;
         int F = 0, K = 0;
         in >> cmd;
-        if (cmd == "sprp2") F = 28; else in >> F;
-        in >> K;
+        in >> F >> K;
         if (F == 28) {
             switch (K) {
             case 4: run<4, 28>(cmd, in); break;
+            case 6: run<6, 28>(cmd, in); break;
             case 8: run<8, 28>(cmd, in); break;
+            case 10: run<10, 28>(cmd, in); break;
             case 12: run<12, 28>(cmd, in); break;
+            case 14: run<14, 28>(cmd, in); break;
             case 16: run<16, 28>(cmd, in); break;
             default: std::fprintf(stderr, "no 28-bit form with %d limbs\n", K); return 2;
             }

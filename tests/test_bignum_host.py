@@ -1,10 +1,12 @@
 """The GPU's multi-limb headers (gb_bignum28.h, gb_bignum.h) built for the CPU
 with g++ under the address and undefined-behaviour sanitizers, and checked
-against Python integers and the big-n oracle: Montgomery products, strong
-probable-prime tests to all 25 bases, and the minimal-p search in the
-kernels' order (odd bases filter, base 2, then the other 24 bases), at every
-limb count the library compiles (28-bit limbs: 4, 8, 12, 16; 32-bit limbs:
-32, plus 24, the form that gave wrong answers on the GPU).
+against Python integers and the big-n oracle: the 28-bit form's lazy
+Montgomery squaring, its multiplication by a small integer (quotient
+estimated in double precision) and R mod m, the 32-bit form's Montgomery
+product, strong probable-prime tests to all 25 bases, and the minimal-p
+search in the kernels' order (odd bases filter, base 2, then the other 24
+bases), at every limb count the library compiles (28-bit limbs: 4, 6, ...,
+16; 32-bit limbs: 32, plus 24, the form that gave wrong answers on the GPU).
 
 The last test models the search's trip counts: a base-2 test that never
 passes (what a wrong device build of it does) sends a wavefront through the
@@ -21,7 +23,8 @@ from oracle import big
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "bignum_host.cpp")
 LIMIT = 1 << 22                       # the driver's prime table: odd primes below 2^22
-FORMS = [(28, 4), (28, 8), (28, 12), (28, 16), (32, 24), (32, 32)]
+FORMS28 = [(28, K) for K in (4, 6, 8, 10, 12, 14, 16)]
+FORMS = FORMS28 + [(32, 24), (32, 32)]
 
 pytestmark = pytest.mark.skipif(shutil.which("g++") is None, reason="needs g++")
 
@@ -50,7 +53,12 @@ def _bits(F, K):
     return F * K
 
 
-@pytest.mark.parametrize("F,K", FORMS)
+def _widths(F, K):
+    """Modulus widths a form takes: 28-bit limbs need 2^(28K-60) <= m < 2^(28K-2)."""
+    return (28 * K - 59, 28 * K - 2) if F == 28 else (40, 32 * K)
+
+
+@pytest.mark.parametrize("F,K", [(32, 24), (32, 32)])
 def test_montgomery_product(drv, F, K):
     rng = random.Random(F * 100 + K)
     R = 1 << (F * K)
@@ -65,27 +73,53 @@ def test_montgomery_product(drv, F, K):
         assert got == a * b * pow(R, -1, m) % m, (F, K, hex(m))
 
 
+@pytest.mark.parametrize("F,K", FORMS28)
+def test_lazy_squaring_small_multiplier_and_one(drv, F, K):
+    # operands anywhere in [0, 2m), the lazy range; results must stay in
+    # [0, 2m) for the squaring and [0, 1.19 m) for the small multiplier, and
+    # agree with Python integers mod m
+    rng = random.Random(K)
+    R = 1 << (28 * K)
+    lo, hi = _widths(F, K)
+    for t in range(60):
+        w = (lo, hi)[t % 2] if t < 4 else rng.randrange(lo, hi + 1)
+        m = rng.getrandbits(w) | 1 | (1 << (w - 1))
+        a = (2 * m - 1, 0, m, 1)[t % 4] if t < 8 else rng.randrange(2 * m)
+        r, rn = (int(x, 16) for x in drv(f"sqr 28 {K} {m:x} {a:x}").split())
+        want = a * a * pow(R, -1, m) % m
+        assert r < 2 * m and r % m == want and rn == want, (K, hex(m), hex(a))
+        f = (1 << 20, 1, 97 ** 3, 2)[t % 4] if t < 8 else rng.randrange(1, (1 << 20) + 1)
+        r, rn = (int(x, 16) for x in drv(f"mulsmall 28 {K} {m:x} {a:x} {f}").split())
+        assert 100 * r < 119 * m and r % m == a * f % m and rn == a * f % m, (K, hex(m), hex(a), f)
+        assert int(drv(f"one 28 {K} {m:x}"), 16) == R % m
+
+
 @pytest.mark.parametrize("F,K", FORMS)
 def test_strong_tests_match_the_oracle(drv, F, K):
     rng = random.Random(7 * K + F)
-    top = min(_bits(F, K), 1020)
+    lo, hi = _widths(F, K)
+    lo, hi = max(lo, 66), min(hi, 1020)
     qs = []
-    for _ in range(6):
-        w = rng.randrange(max(66, top - 120), top + 1)
+    for t in range(6):
+        w = rng.randrange(max(lo, hi - 120), hi + 1) if F == 32 else rng.randrange(lo, hi + 1)
         q = rng.getrandbits(w) | 1 | (1 << (w - 1))
         while not big.probable_prime(q):
             q += 2
         qs += [q, q + 2, q + 4]
+    # q - 1 with many trailing zero bits (long squaring tails)
+    for s in (20, 45):
+        w = rng.randrange(lo, hi + 1)
+        qs.append(((rng.getrandbits(w - s) | (1 << (w - s - 1))) << s) + 1)
     # strong pseudoprimes to the first 12 and 13 prime bases
     qs += [318665857834031151167461, 3317044064679887385961981]
     for q in qs:
+        if F == 28 and not (lo <= q.bit_length() <= hi):
+            continue
         if q.bit_length() > _bits(F, K) or q < 100:
             continue
         for a in big.BASES:
             want = big.strong_probable_prime(q, a)
             assert int(drv(f"sprp {F} {K} {q:x} {a}")) == int(want), (F, K, hex(q), a)
-        if F == 28:
-            assert int(drv(f"sprp2 {K} {q:x}")) == int(big.strong_probable_prime(q, 2))
 
 
 def _random_even(bits, rng):
@@ -93,7 +127,8 @@ def _random_even(bits, rng):
     return n - (n & 1)
 
 
-@pytest.mark.parametrize("bits,F,K", [(100, 28, 4), (200, 28, 8), (333, 28, 12), (440, 28, 16),
+@pytest.mark.parametrize("bits,F,K", [(100, 28, 4), (160, 28, 6), (200, 28, 8), (250, 28, 10),
+                                      (280, 28, 12), (333, 28, 12), (390, 28, 14), (440, 28, 16),
                                       (520, 32, 32), (600, 32, 24), (700, 32, 24), (700, 32, 32),
                                       (1020, 32, 32)])
 def test_minimal_p_search_matches_the_oracle(drv, bits, F, K):

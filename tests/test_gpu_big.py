@@ -45,9 +45,9 @@ def test_batch(V):
 
 
 def test_many_open_n_share_wavefronts(V):
-    # 300 n of 440 bits: 47 of them need more than the first 64 candidates
-    # the small-base filter leaves, so the second pass gives each open n 16
-    # wavefronts (one per group of 64) that all start from one resume point
+    # 300 n of 440 bits: many need more than the first 32 candidates the
+    # small-base filter leaves, so the later passes give each open n several
+    # groups of 32 (up to 16) that all start from one resume point
     ns = [2**439 + 2 * 10**6 * i + 2 * i * i for i in range(300)]
     assert V.verify_big(ns) == [big.pmin_big(n) for n in ns]
 
@@ -75,10 +75,11 @@ def test_base2_pseudoprime_candidate_is_rejected(V, psi):
     assert got[0] > 3
 
 
-@pytest.mark.parametrize("bits", [112, 113, 224, 225, 336, 337, 448, 449])
+@pytest.mark.parametrize("bits", [110, 111, 166, 167, 222, 223, 278, 279, 334, 335, 390, 391, 446, 447])
 def test_limb_class_edges(V, bits):
     # n of exactly `bits` bits: the largest and smallest of each class of
-    # 28-bit limbs (4, 8, 12, 16 limbs) and the first n of the 32-limb form
+    # 28-bit limbs (K = 4, 6, ..., 16 limbs hold n up to 28K - 2 bits) and the
+    # first n of the 32-limb form
     rng = random.Random(1000 + bits)
     top = (1 << bits) - 2                              # all ones but the last bit
     low = 1 << (bits - 1)
@@ -86,5 +87,17 @@ def test_limb_class_edges(V, bits):
     ns = [top, low, mid]
     assert all(n.bit_length() == bits and n % 2 == 0 for n in ns)
     assert V.verify_big(ns) == [big.pmin_big(n) for n in ns]
-    # mixed with a smaller n: the call's form follows its largest n
+    # mixed with a smaller n, which runs in its own form
     assert V.verify_big([2**64 + 2, top]) == [big.pmin_big(2**64 + 2), big.pmin_big(top)]
+
+
+def test_one_call_over_every_form(V):
+    # n of every limb class in one call, interleaved: the call splits them by
+    # form and puts each answer back at its n's position
+    rng = random.Random(77)
+    sizes = [70, 130, 180, 240, 300, 333, 380, 430, 460, 600]
+    ns = []
+    for i in range(30):
+        b = sizes[(7 * i) % len(sizes)]
+        ns.append((rng.getrandbits(b - 1) | (1 << (b - 1))) & ~1)
+    assert V.verify_big(ns) == [big.pmin_big(n) for n in ns]

@@ -212,7 +212,8 @@ gb_status gb_verify_one(gb_ctx *ctx, uint64_t n, uint64_t *p, void *stream);
  * certainly composite; the returned q is a probable prime (the first 12
  * bases alone are deterministic below 3.3e24).  A base-2 search over the
  * p not ruled out by a small base, then a confirmation over the other 24
- * bases, in passes that synchronise the stream.  Status: GB_EINVAL for an
+ * bases, in passes planned on the device; the call synchronises the stream
+ * after every six passes and at its end.  Status: GB_EINVAL for an
  * odd n, an n below 2^64, nlimbs outside 3..32 or more than 2^24 n;
  * GB_EUNRESOLVED (entry 0) if no prime of the table works; GB_EDEVICE on a
  * HIP error or when the passes do not settle. */

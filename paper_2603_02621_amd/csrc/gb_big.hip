@@ -2,9 +2,11 @@
 // section "Arbitrary Precision Checker": small primes p in ascending order,
 // q = n - p tested with Miller-Rabin), up to n < 2^1024.
 //
-// Below 2^446 (n as K = 4, 6, ..., 16 limbs of 28 bits, gb_bignum28.h) the
-// host runs passes of one launch each.  A launch is a list of lane tasks,
-// 64 to a wavefront: first the search groups, then the confirmations.
+// Up to 446 bits (n as K = 4, 6, ..., 16 limbs of 28 bits, gb_bignum28.h)
+// the search runs in passes of one launch each, planned on the device (a
+// small kernel after each pass writes the next pass's lists).  A launch is
+// a list of lane tasks, 64 to a wavefront: first the search groups, then
+// the confirmations.
 //
 // - Search: the odd primes p of the resident table are filtered, 64 at a
 //   time, by the 24 odd prime bases r = 3 .. 97.  A q = n - p that r divides
@@ -121,42 +123,80 @@ __device__ __forceinline__ uint32_t big_collect(uint32_t *cand, uint32_t G, uint
     return got > lo ? got - lo : 0u;
 }
 
-// One pass.  Lane task t (64 per wavefront, blockIdx.x * 256 + threadIdx.x):
-// t < S0 = nslist nways G is lane t mod G of search group t / G, which is way
-// (t / G) mod nways of the ((t / G) / nways)-th n of slist (of all n when
-// slist is null; their found entries are all ones before the pass); the
-// next nclist * 24 tasks confirm the candidates of the n of clist, found in
-// the pass before, one odd base each.
-template <int K>
-__global__ __launch_bounds__(256) void k_big_pass(const uint32_t *n_all, const uint32_t *slist, uint32_t nslist,
-                                                  uint32_t G, uint32_t nways, const uint32_t *clist, uint32_t nclist,
-                                                  const uint32_t *primes, uint32_t nprimes, const uint32_t *resume_in,
-                                                  uint32_t *resume_out, uint32_t *found, uint32_t *bad)
+// Pass shape.  A pass takes whole rounds of one wavefront per SIMD: the
+// confirmations' rounds plus kExtraRounds (one round in the first pass),
+// and the search gets as many groups per open n (ways, at most kMaxWays) as
+// fill the rest, so that the n with large p_min do not run alone.  Groups
+// hold kGroup survivors; in a first pass whose n do not fill the round with
+// one group of kGroup each, they hold kSmallGroup (more, smaller groups per
+// n: the first candidate lies in an earlier one); the host picks the
+// kernel built for the pass's group size, and every wavefront derives the
+// ways from the list lengths in device memory.
+constexpr uint32_t kGroup = 32, kSmallGroup = 16, kExtraRounds = 1, kMaxWays = 16;
+
+// The group size of a pass: kSmallGroup only in a first pass whose n do not
+// fill one round with a group of kGroup each.
+inline uint32_t big_group(bool first, uint64_t nsl, uint32_t simds)
+{
+    return first && nsl * kGroup < 64ull * simds ? kSmallGroup : kGroup;
+}
+
+// Groups per open n for a pass with groups of G
+__host__ __device__ inline uint32_t big_ways(bool first, uint32_t G, uint32_t nsl, uint32_t ncl, uint32_t simds)
+{
+    const uint64_t cw = ((uint64_t)ncl * 24u + 63u) / 64u;
+    const uint64_t rounds = first ? 1u : (cw + simds - 1u) / simds + kExtraRounds;
+    const uint64_t room = rounds * simds > cw ? rounds * simds - cw : 0u;
+    uint64_t ways = nsl ? room * 64u / ((uint64_t)nsl * G) : 1u;
+    return (uint32_t)(ways < 1u ? 1u : ways > kMaxWays ? kMaxWays : ways);
+}
+
+// One pass.  The lists and their lengths are in device memory (written by
+// k_big_plan after the pass before), so passes follow each other on the
+// stream without the host.  Lane task t (64 per wavefront,
+// blockIdx.x * 256 + threadIdx.x): t < S0 = nsl nways G is lane t mod G of
+// search group t / G, which is way (t / G) mod nways of the
+// ((t / G) / nways)-th n of the search list (every n in the first pass;
+// their found entries are all ones before the pass); the next ncl * 24
+// tasks confirm the candidates of the n of the confirm list, found in the
+// pass before, one odd base each.  The grid covers the largest pass; the
+// wavefronts past the tasks return at once.  Block 0 also clears the
+// lengths of the next pass's lists (cnt_next).
+template <int K, uint32_t G>
+__global__ __launch_bounds__(256) void k_big_pass(const uint32_t *n_all, const uint32_t *lists, const uint32_t *cnt,
+                                                  uint32_t *cnt_next, uint32_t first, uint32_t k, uint32_t simds,
+                                                  const uint32_t *primes,
+                                                  uint32_t nprimes, const uint32_t *resume_in, uint32_t *resume_out,
+                                                  uint32_t *found, uint32_t *bad)
 {
     __shared__ uint32_t cand_all[4][64];
+    __shared__ uint32_t grp_all[4][4][2];           // per wavefront and group: n index, survivors
     const uint32_t lane = threadIdx.x & 63u;
     const uint32_t wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    // the next pass's list lengths start from zero: the plan kernel of the
+    // pass before, their last reader, has finished, and k_big_plan after
+    // this pass counts into them
+    if (blockIdx.x == 0u && threadIdx.x < 2u) cnt_next[threadIdx.x] = 0u;
+    const uint32_t nsl = first ? k : cnt[0], ncl = first ? 0u : cnt[1];
+    const uint32_t nways = big_ways(first != 0u, G, nsl, ncl, simds);
+    const uint32_t *slist = first ? nullptr : lists, *clist = lists + k;
     const uint64_t t0 = ((uint64_t)blockIdx.x * 4u + wv) * 64u;
-    const uint64_t S0 = (uint64_t)nslist * nways * G;
-    const uint64_t total = S0 + (uint64_t)nclist * 24u;
+    const uint64_t S0 = (uint64_t)nsl * nways * G;
+    const uint64_t total = S0 + (uint64_t)ncl * 24u;
     if (t0 >= total) return;                         // whole wave
     uint32_t *cand = cand_all[wv];
     // the search groups among this wave's lanes (G divides 64, so a group
     // never straddles two wavefronts)
-    uint32_t gidx0 = 0u, gidx1 = 0u, gcnt0 = 0u, gcnt1 = 0u;
-    const uint32_t ngw = 64u / G;
+    constexpr uint32_t ngw = 64u / G;
     for (uint32_t gi = 0; gi < ngw && t0 + (uint64_t)gi * G < S0; ++gi) {
         const uint32_t grp = (uint32_t)((t0 + (uint64_t)gi * G) / G);
         const uint32_t li = grp / nways, way = grp - li * nways;
         const uint32_t idx = slist ? slist[li] : li;
-        const uint32_t cnt =
+        const uint32_t cnt_g =
             big_collect<K>(cand + gi * G, G, way, nways, idx, n_all, primes, nprimes, resume_in, resume_out);
-        if (gi == 0u) {
-            gidx0 = idx;
-            gcnt0 = cnt;
-        } else {
-            gidx1 = idx;
-            gcnt1 = cnt;
+        if (lane == 0u) {
+            grp_all[wv][gi][0] = idx;
+            grp_all[wv][gi][1] = cnt_g;
         }
     }
     __builtin_amdgcn_wave_barrier();
@@ -166,12 +206,12 @@ __global__ __launch_bounds__(256) void k_big_pass(const uint32_t *n_all, const u
     uint32_t idx = 0u, c = 0u, base = 2u;
     if (srch) {
         const uint32_t gi = lane / G;
-        idx = gi ? gidx1 : gidx0;
-        act = lane - gi * G < (gi ? gcnt1 : gcnt0);
+        idx = grp_all[wv][gi][0];
+        act = lane - gi * G < grp_all[wv][gi][1];
         c = act ? cand[lane] : 0u;
     } else if (t < total) {
-        const uint64_t k = t - S0;
-        const uint32_t ci = (uint32_t)(k / 24u), j = (uint32_t)(k - (uint64_t)ci * 24u);
+        const uint64_t kk = t - S0;
+        const uint32_t ci = (uint32_t)(kk / 24u), j = (uint32_t)(kk - (uint64_t)ci * 24u);
         idx = clist[ci];
         c = found[idx];
         act = c < nprimes;                           // else nothing to confirm
@@ -184,14 +224,86 @@ __global__ __launch_bounds__(256) void k_big_pass(const uint32_t *n_all, const u
         pass = gbbig28::strong_prp<K>(q, base);
     }
     const unsigned long long m = __builtin_amdgcn_ballot_w64(srch && pass);
+    constexpr unsigned long long gmask = G == 64u ? ~0ull : (1ull << G) - 1ull;
+#pragma unroll
     for (uint32_t gi = 0; gi < ngw; ++gi) {
-        const unsigned long long gm = G == 64u ? m : (m >> (gi * 32u)) & 0xFFFFFFFFull;
+        const unsigned long long gm = (m >> (gi * G)) & gmask;
         if (gm != 0ull && lane == 0u)
-            __hip_atomic_fetch_min(&found[gi ? gidx1 : gidx0],
+            __hip_atomic_fetch_min(&found[grp_all[wv][gi][0]],
                                    __builtin_amdgcn_readlane(c, gi * G + (uint32_t)__builtin_ctzll(gm)),
                                    __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     if (!srch && act && !pass) __hip_atomic_fetch_or(&bad[idx], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Appends idx to list (length *len) for the lanes where put holds: one
+// atomic per wavefront, each lane at its rank among them.
+__device__ __forceinline__ void big_append(bool put, uint32_t idx, uint32_t *list, uint32_t *len)
+{
+    const unsigned long long m = __builtin_amdgcn_ballot_w64(put);
+    if (m == 0ull) return;
+    const uint32_t rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+    const uint32_t lead = (uint32_t)__builtin_ctzll(m);
+    uint32_t base = 0u;
+    if (put && rank == 0u) base = atomicAdd(len, (uint32_t)__popcll(m));
+    base = __builtin_amdgcn_readlane(base, lead);
+    if (put) list[base + rank] = idx;
+}
+
+// After a pass: the n whose candidate passed every base are answered
+// (ans = its table index); a candidate that failed one sends its n back to
+// the search after it; the searched n continue after their groups, to the
+// confirm list when a group found a candidate, else to the search list
+// (unless the table is spent: the n stays unanswered).  Writes the next
+// pass's lists (lists_next, cnt_next, zero before) and resets found or bad
+// for the entries it lists.
+__global__ __launch_bounds__(256) void k_big_plan(const uint32_t *lists, const uint32_t *cnt, uint32_t first,
+                                                  uint32_t k, uint32_t *lists_next, uint32_t *cnt_next,
+                                                  uint32_t nprimes, uint32_t *resume, const uint32_t *rout,
+                                                  uint32_t *found, uint32_t *bad, uint32_t *ans)
+{
+    const uint32_t nsl = first ? k : cnt[0], ncl = first ? 0u : cnt[1];
+    const uint32_t *sl = lists, *cl = lists + k;
+    const uint32_t stride = gridDim.x * blockDim.x;
+    for (uint32_t e0 = blockIdx.x * blockDim.x; e0 < nsl + ncl; e0 += stride) {
+        const uint32_t e = e0 + threadIdx.x;
+        bool to_s = false, to_c = false;
+        uint32_t idx = 0u;
+        if (e < ncl) {
+            idx = cl[e];
+            const uint32_t f = found[idx];
+            if (!bad[idx]) {
+                ans[idx] = f;
+            } else {
+                resume[idx] = f + 1u;                // a base-2 pseudoprime: resume after it
+                to_s = f + 1u < nprimes;
+            }
+        } else if (e < nsl + ncl) {
+            idx = first ? e - ncl : sl[e - ncl];
+            const uint32_t r = rout[idx];
+            resume[idx] = r;
+            to_c = found[idx] < nprimes;
+            to_s = !to_c && r < nprimes;
+        }
+        if (to_s) found[idx] = ~0u;
+        if (to_c) bad[idx] = 0u;
+        big_append(to_s, idx, lists_next, cnt_next);
+        big_append(to_c, idx, lists_next + k, cnt_next + 1);
+    }
+}
+
+// Initial state: search from the table's start, nothing found or answered;
+// list lengths zero (the first pass searches every n without a list).
+__global__ void k_big_init(uint32_t k, uint32_t *resume, uint32_t *found, uint32_t *bad, uint32_t *ans, uint32_t *cnt)
+{
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < k) {
+        resume[i] = 0u;
+        found[i] = ~0u;
+        bad[i] = 0u;
+        ans[i] = ~0u;
+    }
+    if (i < 4u) cnt[i] = 0u;
 }
 
 // The one-kernel form, used for 32 limbs: the same filter and base-2 search
@@ -273,99 +385,64 @@ __global__ __launch_bounds__(256) void k_big_wave(const uint32_t *n_all, uint64_
     if (lane == 0u) p_out[idx] = 0ull;               // no partition with p in the table
 }
 
-template <int K>
-hipError_t launch_pass(const uint32_t *n, const uint32_t *slist, uint32_t nslist, uint32_t G, uint32_t nways,
-                       const uint32_t *clist, uint32_t nclist, const uint32_t *primes, uint32_t nprimes,
-                       const uint32_t *resume_in, uint32_t *resume_out, uint32_t *found, uint32_t *bad, hipStream_t st)
-{
-    const uint64_t tasks = (uint64_t)nslist * nways * G + (uint64_t)nclist * 24u;
-    hipLaunchKernelGGL(k_big_pass<K>, dim3((uint32_t)((tasks + 255u) / 256u)), dim3(256), 0, st, n, slist, nslist, G,
-                       nways, clist, nclist, primes, nprimes, resume_in, resume_out, found, bad);
-    return hipGetLastError();
-}
-
-// Pass shape: the first pass gives every n one group of kFirstGroup
-// survivors; later passes give each open n kLaterGroup-lane groups, as many
-// ways as keep about one search wavefront per SIMD busy (at most 16), so
-// that the n with large p_min do not run alone.
-constexpr uint32_t kFirstGroup = 32, kLaterGroup = 32, kMaxWays = 16;
-
 // The n of one limb count K (28-bit limbs): h holds them, K limbs each
 // (k n); their answers go to ans (table indices, UINT32_MAX for none).
+// Passes are enqueued in batches of kBatch (each a k_big_pass and a
+// k_big_plan); after a batch the host reads the next pass's list lengths
+// and stops when both are zero.  Every pass moves each open n's resume
+// point forward, so the passes end; the cap stops a call whose device
+// results do not settle.
 template <int K>
 gb_status big28_passes(gb_ctx *c, const std::vector<uint32_t> &h, size_t k, std::vector<uint32_t> &ans,
                        hipStream_t st)
 {
+    constexpr int kBatch = 6, kMaxPasses = 1024;
     Workspace &ws = c->ws;
     GB_HIP(c, ws.big_n.ensure(h.size()));
     GB_HIP(c, hipMemcpyAsync(ws.big_n.p, h.data(), h.size() * 4, hipMemcpyHostToDevice, st));
-    GB_HIP(c, ws.big_state.ensure(4 * k));
-    GB_HIP(c, ws.big_list.ensure(2 * k));
-    GB_HIP(c, ws.h_big.ensure(6 * k));
-    const uint32_t np = (uint32_t)c->ntab;
-    // pinned host copies of the four device arrays (resume point in, found,
-    // resume point out, bad; k each), then the two lists
-    uint32_t *resume = ws.h_big.p, *found = resume + k, *rout = found + k, *bad = rout + k, *hsl = bad + k,
-             *hcl = hsl + k;
-    uint32_t *d_resume = ws.big_state.p, *d_found = d_resume + k, *d_rout = d_found + k, *d_bad = d_rout + k;
-    std::fill(resume, resume + k, 0u);
-    ans.assign(k, UINT32_MAX);
-    std::vector<uint32_t> sl, cl, nsl, ncl;
-    bool all = true;                                 // the first pass searches every n
-    uint32_t G = kFirstGroup, nways = 1;
-    // Each pass searches the open n and confirms the candidates found in the
-    // pass before.  Every pass moves each open n's resume point forward, so
-    // the loop ends; the cap stops a call whose device results do not settle.
-    const uint64_t target = (uint64_t)c->num_cu * 4u * 64u;   // search lanes: one wavefront per SIMD
-    for (int pass = 0;; ++pass) {
-        if (pass == 1024) return fail(c, GB_EDEVICE, "big-n search did not settle");
-        const uint32_t nslist = all ? (uint32_t)k : (uint32_t)sl.size(), nclist = (uint32_t)cl.size();
-        if (all)
-            std::fill(found, found + k, UINT32_MAX);
-        else
-            for (uint32_t i : sl) found[i] = UINT32_MAX;
-        std::copy(sl.begin(), sl.end(), hsl);
-        std::copy(cl.begin(), cl.end(), hcl);
-        GB_HIP(c, hipMemcpyAsync(d_resume, resume, 2 * k * 4, hipMemcpyHostToDevice, st));   // resume in, found
-        GB_HIP(c, hipMemsetAsync(d_bad, 0, k * 4, st));
-        // the two lists share one buffer: the search list, then the confirm list
-        if (!all && nslist) GB_HIP(c, hipMemcpyAsync(ws.big_list.p, hsl, nslist * 4, hipMemcpyHostToDevice, st));
-        if (nclist) GB_HIP(c, hipMemcpyAsync(ws.big_list.p + k, hcl, nclist * 4, hipMemcpyHostToDevice, st));
-        const uint32_t *dsl = all ? nullptr : ws.big_list.p, *dcl = ws.big_list.p + k;
-        GB_HIP(c, launch_pass<K>(ws.big_n.p, dsl, nslist, G, nways, dcl, nclist, c->d_primes, np, d_resume, d_rout,
-                                 d_found, d_bad, st));
-        GB_HIP(c, hipMemcpyAsync(found, d_found, 3 * k * 4, hipMemcpyDeviceToHost, st));   // found, resume out, bad
+    GB_HIP(c, ws.big_state.ensure(5 * k + 4));
+    GB_HIP(c, ws.big_list.ensure(4 * k));
+    GB_HIP(c, ws.h_big.ensure(k + 4));
+    const uint32_t np = (uint32_t)c->ntab, kk = (uint32_t)k, simds = (uint32_t)c->num_cu * 4u;
+    uint32_t *d_resume = ws.big_state.p, *d_found = d_resume + k, *d_rout = d_found + k, *d_bad = d_rout + k,
+             *d_ans = d_bad + k, *d_cnt = d_ans + k;   // d_cnt: lengths of list pair 0, then of pair 1
+    uint32_t *h_ans = ws.h_big.p, *h_cnt = h_ans + k;
+    hipLaunchKernelGGL(k_big_init, dim3((kk + 255u) / 256u), dim3(256), 0, st, kk, d_resume, d_found, d_bad, d_ans,
+                       d_cnt);
+    GB_HIP(c, hipGetLastError());
+    // the largest pass: every n in groups of the larger G, every n confirming,
+    // or the rounds the shape can ask for
+    const uint64_t gmax = std::max(kGroup, kSmallGroup);
+    const uint64_t conf_waves = ((uint64_t)k * 24u + 63u) / 64u;
+    const uint64_t waves = std::max<uint64_t>(((uint64_t)k * gmax + 63u) / 64u + conf_waves,
+                                              ((conf_waves + simds - 1u) / simds + kExtraRounds + 1u) * simds);
+    const uint32_t pass_blocks = (uint32_t)((waves + 3u) / 4u);
+    const uint32_t plan_blocks = (uint32_t)std::min<uint64_t>((k + 255u) / 256u, (uint64_t)c->num_cu * 4u);
+    for (int pass = 0;;) {
+        for (int b = 0; b < kBatch; ++b, ++pass) {
+            const uint32_t par = (uint32_t)pass & 1u, first = pass == 0 ? 1u : 0u;
+            const uint32_t *lists = ws.big_list.p + (size_t)par * 2u * k, *cnt = d_cnt + 2u * par;
+            uint32_t *lists_next = ws.big_list.p + (size_t)(par ^ 1u) * 2u * k, *cnt_next = d_cnt + 2u * (par ^ 1u);
+            if (big_group(first != 0u, k, simds) == kSmallGroup)
+                hipLaunchKernelGGL((k_big_pass<K, kSmallGroup>), dim3(pass_blocks), dim3(256), 0, st, ws.big_n.p, lists,
+                                   cnt, cnt_next, first, kk, simds, c->d_primes, np, d_resume, d_rout, d_found, d_bad);
+            else
+                hipLaunchKernelGGL((k_big_pass<K, kGroup>), dim3(pass_blocks), dim3(256), 0, st, ws.big_n.p, lists, cnt,
+                                   cnt_next, first, kk, simds, c->d_primes, np, d_resume, d_rout, d_found, d_bad);
+            GB_HIP(c, hipGetLastError());
+            hipLaunchKernelGGL(k_big_plan, dim3(plan_blocks), dim3(256), 0, st, lists, cnt, first, kk, lists_next,
+                               cnt_next, np, d_resume, d_rout, d_found, d_bad, d_ans);
+            GB_HIP(c, hipGetLastError());
+        }
+        const uint32_t *cnt_now = d_cnt + 2u * ((uint32_t)pass & 1u);
+        GB_HIP(c, hipMemcpyAsync(h_cnt, cnt_now, 8, hipMemcpyDeviceToHost, st));
         GB_HIP(c, hipStreamSynchronize(st));
-        // the searched n continue after the groups this pass took
-        for (uint32_t li = 0; li < nslist; ++li) {
-            const uint32_t i = all ? li : sl[li];
-            resume[i] = rout[i];
-        }
-        nsl.clear();
-        ncl.clear();
-        for (uint32_t i : cl) {
-            if (!bad[i]) {
-                ans[i] = found[i];
-                continue;
-            }
-            resume[i] = found[i] + 1u;               // a base-2 pseudoprime: resume after it
-            if (resume[i] < np) nsl.push_back(i);    // else the table ends: unresolved
-        }
-        for (uint32_t li = 0; li < nslist; ++li) {
-            const uint32_t i = all ? li : sl[li];
-            if (found[i] < np)
-                ncl.push_back(i);
-            else if (resume[i] < np)
-                nsl.push_back(i);
-        }
-        if (nsl.empty() && ncl.empty()) break;
-        sl.swap(nsl);
-        cl.swap(ncl);
-        all = false;
-        G = kLaterGroup;
-        nways = sl.empty() ? 1u
-                           : (uint32_t)std::max<uint64_t>(1u, std::min<uint64_t>(kMaxWays, target / ((uint64_t)sl.size() * G)));
+        if (h_cnt[0] == 0u && h_cnt[1] == 0u) break;
+        if (pass >= kMaxPasses) return fail(c, GB_EDEVICE, "big-n search did not settle");
     }
+    GB_HIP(c, hipMemcpyAsync(h_ans, d_ans, k * 4, hipMemcpyDeviceToHost, st));
+    GB_HIP(c, hipStreamSynchronize(st));
+    ans.assign(h_ans, h_ans + k);
     return GB_OK;
 }
 

@@ -98,9 +98,11 @@ struct Workspace {
     DevBuf<uint32_t> big_state;          // per n: the table index its search resumes
                                          // from, that of its candidate p, the
                                          // resume index after the pass, its
-                                         // confirmation flag (four arrays of k)
-    DevBuf<uint32_t> big_list;           // the n searched and confirmed in a pass;
-    PinBuf<uint32_t> h_big;              // host copies of both;
+                                         // confirmation flag, its answer (five
+                                         // arrays of k), then the list lengths
+    DevBuf<uint32_t> big_list;           // the n searched and confirmed in a pass
+                                         // and in the next (two pairs of lists)
+    PinBuf<uint32_t> h_big;              // host copies of the answers and lengths
     DevBuf<unsigned long long> big_p;    // the one-kernel form's answers
     PinBuf<GbSlot> h_slots;
     PinBuf<unsigned long long> h_hist;

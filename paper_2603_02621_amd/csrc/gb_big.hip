@@ -2,8 +2,9 @@
 // section "Arbitrary Precision Checker": small primes p in ascending order,
 // q = n - p tested with Miller-Rabin), up to n < 2^1024.
 //
-// Up to 446 bits (n as K = 4, 6, ..., 16 limbs of 28 bits, gb_bignum28.h)
-// the search runs in passes of one launch each, planned on the device (a
+// n is held as K limbs of 28 bits (gb_bignum28.h): K = 4, 6, ..., 16 up to
+// 446 bits, then K = 20, 24, 28, 32, 36 and 37 (up to 1034 bits).  The
+// search runs in passes of one launch each, planned on the device (a
 // small kernel after each pass writes the next pass's lists).  A launch is
 // a list of lane tasks, 64 to a wavefront: first the search groups, then
 // the confirmations.
@@ -23,19 +24,16 @@
 // The answer is the first p whose q passes all 25 bases; every smaller p
 // failed one, so its q is composite.  All lanes run the same windowed strong
 // test (base 2 or an odd base), so search groups and confirmations share
-// wavefronts.  From 447 bits on (32 limbs of 32 bits, gb_bignum.h) one
-// wavefront per n does the search and confirmation in one kernel.
+// wavefronts.
 #include <algorithm>
 #include <cstring>
 
-#include "gb_bignum.h"
 #include "gb_bignum28.h"
 #include "gb_runtime.h"
 
 namespace {
 
 using namespace gbrt;
-using gbbig::Num;
 
 __constant__ uint32_t kBigBases[25] = {2, 3, 5, 7, 11, 13, 17, 19, 23, 29, 31, 37, 41,
                                        43, 47, 53, 59, 61, 67, 71, 73, 79, 83, 89, 97};
@@ -43,17 +41,7 @@ __constant__ uint32_t kBigBases[25] = {2, 3, 5, 7, 11, 13, 17, 19, 23, 29, 31, 3
 constexpr uint32_t kOddBases[24] = {3, 5, 7, 11, 13, 17, 19, 23, 29, 31, 37, 41,
                                      43, 47, 53, 59, 61, 67, 71, 73, 79, 83, 89, 97};
 
-// n mod r for a small r (r < 2^12), most significant limb first (32- and
-// 28-bit limbs)
-template <int K> __device__ __forceinline__ uint32_t mod_small(const Num<K> &n, uint32_t r)
-{
-    const uint32_t t = (uint32_t)((1ull << 32) % r);
-    uint32_t acc = 0;
-#pragma unroll
-    for (int i = K - 1; i >= 0; --i) acc = (acc * t + n.w[i] % r) % r;
-    return acc;
-}
-
+// n mod r for a small r (r < 2^12), most significant limb first
 template <int K> __device__ __forceinline__ uint32_t mod_small(const gbbig28::Num<K> &n, uint32_t r)
 {
     const uint32_t t = (1u << gbbig28::kBits) % r;
@@ -306,85 +294,6 @@ __global__ void k_big_init(uint32_t k, uint32_t *resume, uint32_t *found, uint32
     if (i < 4u) cnt[i] = 0u;
 }
 
-// The one-kernel form, used for 32 limbs: the same filter and base-2 search
-// in one wavefront per n, the lowest passing lane's q then tested to the
-// other 24 bases by lanes 0 .. 23 of the same wavefront (next passing lane,
-// then the next 64 surviving p, when it fails one).  The two-kernel form at
-// 32 limbs did not finish a 520-bit case on the GPU; its cause is not
-// known, so that form is kept to 4 .. 16 limbs.
-template <int K>
-__global__ __launch_bounds__(256) void k_big_wave(const uint32_t *n_all, uint64_t k, const uint32_t *primes,
-                                                  uint64_t nprimes, unsigned long long *p_out)
-{
-    __shared__ uint32_t cand_all[4][64];
-    const uint32_t lane = threadIdx.x & 63u;
-    const uint32_t wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const uint64_t idx = (uint64_t)blockIdx.x * 4u + wv;
-    if (idx >= k) return;                            // whole wave
-    uint32_t *cand = cand_all[wv];
-    Num<K> n;
-#pragma unroll
-    for (int i = 0; i < K; ++i) n.w[i] = n_all[idx * K + i];
-    uint32_t nres[24];
-#pragma unroll
-    for (int j = 0; j < 24; ++j) nres[j] = mod_small(n, kOddBases[j]);
-    uint64_t next = 0;
-    for (;;) {
-        uint32_t cnt = 0;
-        while (cnt < 64u && next < nprimes) {
-            const uint64_t c = next + lane;
-            const bool valid = c < nprimes;
-            const uint32_t p = valid ? primes[c] : 0u;
-            bool hit = false;
-#pragma unroll
-            for (int j = 0; j < 24; ++j) hit = hit || (p % kOddBases[j] == nres[j]);
-            const bool keep = valid && !hit;
-            const unsigned long long m = __builtin_amdgcn_ballot_w64(keep);
-            const uint32_t rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-            const uint32_t room = 64u - cnt;
-            if (keep && rank < room) cand[cnt + rank] = p;
-            const uint32_t tot = (uint32_t)__popcll(m);
-            if (tot > room) {
-                next += (uint64_t)__builtin_ctzll(__builtin_amdgcn_ballot_w64(keep && rank == room));
-                cnt = 64u;
-            } else {
-                next += 64u;
-                cnt += tot;
-            }
-        }
-        if (cnt == 0u) break;                        // table exhausted
-        __builtin_amdgcn_wave_barrier();
-        const bool act = lane < cnt;
-        const uint32_t p = act ? cand[lane] : 3u;
-        __builtin_amdgcn_wave_barrier();
-        Num<K> q;
-        {
-            uint64_t br = p;
-#pragma unroll
-            for (int i = 0; i < K; ++i) {
-                const uint64_t t = (uint64_t)n.w[i] - br;
-                q.w[i] = (uint32_t)t;
-                br = (t >> 63) & 1u;
-            }
-        }
-        const bool pass2 = act && gbbig::strong_prp<K>(q, 2u);
-        unsigned long long m = __builtin_amdgcn_ballot_w64(pass2);
-        while (m) {
-            const uint32_t L = (uint32_t)__builtin_ctzll(m);
-            m &= m - 1ull;
-            Num<K> qL;
-#pragma unroll
-            for (int i = 0; i < K; ++i) qL.w[i] = __builtin_amdgcn_readlane(q.w[i], L);
-            const bool ok = lane >= 24u || gbbig::strong_prp<K>(qL, kBigBases[lane + 1u]);
-            if (__builtin_amdgcn_ballot_w64(!ok) == 0ull) {
-                if (lane == 0u) p_out[idx] = __builtin_amdgcn_readlane(p, L);
-                return;
-            }
-        }
-    }
-    if (lane == 0u) p_out[idx] = 0ull;               // no partition with p in the table
-}
-
 // The n of one limb count K (28-bit limbs): h holds them, K limbs each
 // (k n); their answers go to ans (table indices, UINT32_MAX for none).
 // Passes are enqueued in batches of kBatch (each a k_big_pass and a
@@ -471,31 +380,28 @@ gb_status gb_verify_big(gb_ctx *c, const uint32_t *n, uint32_t nlimbs, size_t k,
     }
     if (hipSetDevice(c->prm.device) != hipSuccess) return fail(c, GB_EDEVICE, "hipSetDevice failed");
     hipStream_t st = static_cast<hipStream_t>(stream);
-    // Forms: the smallest even K with 28K - 2 >= bits (n of at most 446 bits,
-    // so q = n - p has 28K - 58 bits or more, which the 28-bit arithmetic
-    // needs), one pass sequence per K present; 32 limbs of 32 bits (the
-    // one-kernel form) from 447 bits on.  The two-kernel form at 32 limbs did
-    // not finish a 520-bit case on the GPU and a 24-limb 32-bit form returned
-    // wrong answers (both explained by a base-2 test that failed primes), so
-    // they are not used.
-    std::vector<uint32_t> wide;
-    std::vector<uint32_t> sel[17];
+    // Forms: the smallest K of the list with 28K - 2 >= bits, one pass
+    // sequence per K present.  Consecutive K differ by at most 2 up to 16 and
+    // by at most 4 above, so q = n - p >= 2^(28 (K - 2) - 3) (2^(28 (K - 4) - 3)
+    // above 16), as the quotient estimate of the 28-bit arithmetic needs
+    // (q >= 2^(28 (K - E) + 24) with E = 3, resp. 5).
+    static constexpr int kForms[] = {4, 6, 8, 10, 12, 14, 16, 20, 24, 28, 32, 36, 37};
+    constexpr int nforms = (int)(sizeof kForms / sizeof kForms[0]);
+    std::vector<uint32_t> sel[nforms];
     for (size_t i = 0; i < k; ++i) {
-        if (bits[i] > 446) {
-            wide.push_back((uint32_t)i);
-            continue;
-        }
-        const uint32_t K = std::max(4u, (((uint32_t)bits[i] + 2u + 27u) / 28u + 1u) & ~1u);
-        sel[K].push_back((uint32_t)i);
+        int f = 0;
+        while (28 * kForms[f] - 2 < (int)bits[i]) ++f;   // bits <= 1024 <= 28 * 37 - 2
+        sel[f].push_back((uint32_t)i);
     }
     bool unresolved = false;
-    for (int K = 4; K <= 16; K += 2) {
-        if (sel[K].empty()) continue;
-        const size_t kk = sel[K].size();
+    for (int f = 0; f < nforms; ++f) {
+        if (sel[f].empty()) continue;
+        const int K = kForms[f];
+        const size_t kk = sel[f].size();
         // K limbs of 28 bits: limb l is bits 28 l .. 28 l + 27
         std::vector<uint32_t> h(kk * (size_t)K, 0u);
         for (size_t a = 0; a < kk; ++a) {
-            const uint32_t *w = n + (size_t)sel[K][a] * nlimbs;
+            const uint32_t *w = n + (size_t)sel[f][a] * nlimbs;
             for (int l = 0; l < K; ++l) {
                 const uint32_t b0 = 28u * (uint32_t)l, j = b0 >> 5, o = b0 & 31u;
                 uint64_t v = j < nlimbs ? w[j] : 0u;
@@ -512,32 +418,19 @@ gb_status gb_verify_big(gb_ctx *c, const uint32_t *n, uint32_t nlimbs, size_t k,
         case 10: r = big28_passes<10>(c, h, kk, ans, st); break;
         case 12: r = big28_passes<12>(c, h, kk, ans, st); break;
         case 14: r = big28_passes<14>(c, h, kk, ans, st); break;
-        default: r = big28_passes<16>(c, h, kk, ans, st); break;
+        case 16: r = big28_passes<16>(c, h, kk, ans, st); break;
+        case 20: r = big28_passes<20>(c, h, kk, ans, st); break;
+        case 24: r = big28_passes<24>(c, h, kk, ans, st); break;
+        case 28: r = big28_passes<28>(c, h, kk, ans, st); break;
+        case 32: r = big28_passes<32>(c, h, kk, ans, st); break;
+        case 36: r = big28_passes<36>(c, h, kk, ans, st); break;
+        default: r = big28_passes<37>(c, h, kk, ans, st); break;
         }
         if (r != GB_OK) return r;
         for (size_t a = 0; a < kk; ++a) {
-            const uint32_t i = sel[K][a];
+            const uint32_t i = sel[f][a];
             p[i] = ans[a] < c->ntab ? c->h_primes[ans[a]] : 0ull;
             unresolved = unresolved || p[i] == 0;
-        }
-    }
-    if (!wide.empty()) {
-        const size_t kw = wide.size();
-        std::vector<uint32_t> h(kw * 32, 0u);                // padded to 32 limbs of 32 bits
-        for (size_t a = 0; a < kw; ++a) std::memcpy(&h[a * 32], n + (size_t)wide[a] * nlimbs, nlimbs * 4);
-        Workspace &ws = c->ws;
-        GB_HIP(c, ws.big_n.ensure(h.size()));
-        GB_HIP(c, hipMemcpyAsync(ws.big_n.p, h.data(), h.size() * 4, hipMemcpyHostToDevice, st));
-        GB_HIP(c, ws.big_p.ensure(kw));
-        hipLaunchKernelGGL(k_big_wave<32>, dim3((uint32_t)((kw + 3) / 4)), dim3(256), 0, st, ws.big_n.p, (uint64_t)kw,
-                           c->d_primes, c->ntab, ws.big_p.p);
-        GB_HIP(c, hipGetLastError());
-        std::vector<unsigned long long> pw(kw);
-        GB_HIP(c, hipMemcpyAsync(pw.data(), ws.big_p.p, kw * 8, hipMemcpyDeviceToHost, st));
-        GB_HIP(c, hipStreamSynchronize(st));
-        for (size_t a = 0; a < kw; ++a) {
-            p[wide[a]] = pw[a];
-            unresolved = unresolved || pw[a] == 0;
         }
     }
     if (unresolved) return fail(c, GB_EUNRESOLVED, "no partition with p in the resident prime table");

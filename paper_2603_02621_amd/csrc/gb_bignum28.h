@@ -4,7 +4,8 @@
 // n beyond 64 bits (paper section "Arbitrary Precision Checker", which tests
 // q = n - p with Miller-Rabin).
 //
-// Arithmetic mod an odd m with 2^(28K - 60) <= m < 2^(28K - 2), R = 2^(28K):
+// Arithmetic mod an odd m with 2^(28(K - E) + 24) <= m < 2^(28K - 2),
+// R = 2^(28K), where E = est_limbs(K) is 3 up to K = 16 and 5 above:
 //
 // - Montgomery squaring (Montgomery 1985) in the finely integrated
 //   product-scanning order (Koc, Acar and Kaliski 1996), each cross product
@@ -16,7 +17,7 @@
 //   conditional subtraction; values are brought into [0, m) only where they
 //   are compared.
 // - Multiplication by a small integer f <= 2^20: x f - h m, with the quotient
-//   h estimated from the top three limbs of x and of m in double precision,
+//   h estimated from the top E limbs of x and of m in double precision,
 //   rounded down so that h never exceeds the true quotient; the result is
 //   below 1.2 m (the bound is worked out at mul_small).
 //
@@ -32,6 +33,9 @@ constexpr uint32_t kMask = (1u << kBits) - 1u;
 template <int K> struct Num {
     uint32_t w[K];
 };
+
+// Limbs in the quotient estimate of mul_small
+template <int K> constexpr int est_limbs() { return K <= 16 ? 3 : 5; }
 
 // -m^(-1) mod 2^28 for odd m, by Newton's iteration x <- x (2 - m x)
 __host__ __device__ inline uint32_t neg_inv28(uint32_t m)
@@ -80,7 +84,9 @@ template <int K> __host__ __device__ inline void reduce_once(Num<K> &a, const Nu
 template <int K>
 __host__ __device__ inline void mont_sqr(Num<K> &r, const Num<K> &a, const Num<K> &m, uint32_t ninv)
 {
-    static_assert(K >= 4 && K <= 16, "a column of 2K + 1 products must stay below 2^64");
+    // column: below K/2 + 1 cross products doubled, a square and K
+    // products u_j m_(i-j), each below 2^56, plus a carry below 2^36
+    static_assert(K >= 4 && K <= 40, "a column must stay below 2^64");
     uint64_t t = 0;
     uint32_t u[K];
 #pragma unroll
@@ -111,24 +117,35 @@ __host__ __device__ inline void mont_sqr(Num<K> &r, const Num<K> &a, const Num<K
     // (a^2 + U m) / R < (4 m^2 + R m) / R < 2m < R: nothing is left in t
 }
 
-// The quotient estimate's scale for m: (1 - 2^-40) / (M3 + 1), where M3 is
-// m's top three limbs (m / 2^(28(K-3)) rounded down) in double precision.
+// The top E limbs of x as a double: x / 2^(28(K-E)) rounded down, then
+// rounded to double (Horner's rule, one rounding per step)
+template <int K> __host__ __device__ inline double top_limbs(const Num<K> &x)
+{
+    constexpr int E = est_limbs<K>();
+    double v = (double)x.w[K - 1];
+#pragma unroll
+    for (int i = 2; i <= E; ++i) v = v * 268435456.0 + (double)x.w[K - i];
+    return v;
+}
+
+// The quotient estimate's scale for m: (1 - 2^-40) / (M' + 1), with M' m's
+// top E limbs (m / 2^(28(K-E)) rounded down) in double precision.
 template <int K> __host__ __device__ inline double est_recip(const Num<K> &m)
 {
-    const double top = ((double)m.w[K - 1] * 268435456.0 + (double)m.w[K - 2]) * 268435456.0 + (double)m.w[K - 3];
-    return (1.0 - 0x1p-40) / (top + 1.0);
+    return (1.0 - 0x1p-40) / (top_limbs(m) + 1.0);
 }
 
 // x <- x f mod m, lazily, for x < 2m and 1 <= f <= 2^20 (rq = est_recip(m)).
-// With X = x f, M' = m / 2^(28(K-3)) >= 2^24 and x' = x / 2^(28(K-3)) < 2M',
-// the estimate h = floor(f X3 rq) (X3: x's top three limbs) never exceeds
-// X / m: each of the few roundings moves a value by at most 2^-51 of itself,
-// and the factor 1 - 2^-40 in rq covers them.  It falls short of X / m by
-// less than 1 + f (3 / M' + 2^-37) < 1.19, so X - h m lies in [0, 1.19 m).
-// One pass over the limbs forms x_i f - h m_i plus the signed carry.
+// With X = x f, M' = m / 2^(28(K-E)) >= 2^24 and x' = x / 2^(28(K-E)) < 2M',
+// the estimate h = floor(f X' rq) (X': x's top E limbs) never exceeds X / m:
+// each of the few roundings moves a value by at most 2^-53 of itself, less
+// than 2^-48 in all, and the factor 1 - 2^-40 in rq covers them.  It falls
+// short of X / m by less than 1 + f (3 / M' + 2^-37) < 1.19, so X - h m lies
+// in [0, 1.19 m).  One pass over the limbs forms x_i f - h m_i plus the
+// signed carry.
 template <int K> __host__ __device__ inline void mul_small(Num<K> &x, uint32_t f, const Num<K> &m, double rq)
 {
-    const double xd = ((double)x.w[K - 1] * 268435456.0 + (double)x.w[K - 2]) * 268435456.0 + (double)x.w[K - 3];
+    const double xd = top_limbs(x);
     const int32_t nh = -(int32_t)(uint32_t)(xd * (double)f * rq);   // h < 2^21
     int64_t c = 0;
 #pragma unroll
@@ -168,7 +185,7 @@ template <int K> __host__ __device__ inline void mont_one(Num<K> &one, const Num
     reduce_once(one, m);
 }
 
-// Strong probable prime to base a: q odd with 2^(28K - 60) <= q < 2^(28K - 2),
+// Strong probable prime to base a: q odd with 2^(28(K - E) + 24) <= q < 2^(28K - 2),
 // 2 <= a <= 101 (so that a^3 <= 2^20).  With q - 1 = d 2^s, d odd: true when
 // a^d = 1 or -1 mod q, or a^(d 2^r) = -1 for some 0 < r < s.
 //
@@ -192,19 +209,28 @@ template <int K> __host__ __device__ inline bool strong_prp(const Num<K> &q, uin
         if (w) s = (int)kBits * i + __builtin_ctz(w);
     }
     if (s == 0) return false;                        // q = 1
-    // dd = (q - 1) << t: d's bits at [e, 28K), zeros below
+    // dd = (q - 1) << t: d's bits at [e, 28K), zeros below; t <= 28E - 25
+    // (q has at least 28 (K - E) + 25 bits), so t / 28 < E
     const int e = ((int)kBits * K - nb + s) & ~1;
-    const int t = e - s;                             // 1 <= t <= 59
+    const int t = e - s;
     const int L = t / (int)kBits, b = t - L * (int)kBits;
+    constexpr int E = est_limbs<K>();
     Num<K> dd;
 #pragma unroll
     for (int i = K - 1; i >= 0; --i) {
+        // limbs i - L and i - L - 1 of q - 1 (w0 .. w5: limbs i .. i - 5)
         const uint32_t w0 = i == 0 ? q.w[0] & ~1u : q.w[i];
         const uint32_t w1 = i < 1 ? 0u : i == 1 ? q.w[0] & ~1u : q.w[i - 1];
         const uint32_t w2 = i < 2 ? 0u : i == 2 ? q.w[0] & ~1u : q.w[i - 2];
         const uint32_t w3 = i < 3 ? 0u : i == 3 ? q.w[0] & ~1u : q.w[i - 3];
-        const uint32_t hi = L == 0 ? w0 : L == 1 ? w1 : w2;
-        const uint32_t lo = L == 0 ? w1 : L == 1 ? w2 : w3;
+        uint32_t hi = L == 0 ? w0 : L == 1 ? w1 : w2;
+        uint32_t lo = L == 0 ? w1 : L == 1 ? w2 : w3;
+        if constexpr (E > 3) {
+            const uint32_t w4 = i < 4 ? 0u : i == 4 ? q.w[0] & ~1u : q.w[i - 4];
+            const uint32_t w5 = i < 5 ? 0u : i == 5 ? q.w[0] & ~1u : q.w[i - 5];
+            hi = L == 3 ? w3 : L == 4 ? w4 : hi;
+            lo = L == 3 ? w4 : L == 4 ? w5 : lo;
+        }
         dd.w[i] = ((hi << b) | (b ? lo >> (kBits - b) : 0u)) & kMask;
     }
     const uint32_t f1 = a, f2 = a * a, f3 = a * a * a;

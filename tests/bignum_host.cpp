@@ -1,25 +1,25 @@
-// bignum_host.cpp -- host build of the GPU's multi-limb headers
-// (gb_bignum28.h: 28-bit limbs, gb_bignum.h: 32-bit limbs) for the CPU
-// tests.  The headers are written for both sides; compiled here with g++
-// (and the sanitizers), the same Montgomery products and strong tests run on
-// the CPU, so their arithmetic can be checked against Python integers and
-// the big-n oracle without a GPU.
+// bignum_host.cpp -- host build of the GPU's multi-limb header
+// (gb_bignum28.h: 28-bit limbs) for the CPU tests.  The header is written
+// for both sides; compiled here with g++ (and the sanitizers), the same
+// Montgomery squarings, small multiplications and strong tests run on the
+// CPU, so their arithmetic can be checked against Python integers and the
+// big-n oracle without a GPU.
 //
-// Commands on stdin, one per line, answers on stdout:
-//   mul  32 K m a b     -> a b R^-1 mod m     (32-bit limbs, R = 2^(32 K))
-//   sqr  28 K m a       -> "r rn": r = the lazy a^2 R^-1 mod m (R = 2^(28 K),
-//                          a < 2m; r < 2m), rn = r mod m
-//   mulsmall 28 K m x f -> "r rn": r = the lazy x f mod m (x < 2m,
+// Commands on stdin, one per line, answers on stdout (K: limbs of 28 bits,
+// R = 2^(28 K)):
+//   sqr  K m a          -> "r rn": r = the lazy a^2 R^-1 mod m (a < 2m;
+//                          r < 2m), rn = r mod m
+//   mulsmall K m x f    -> "r rn": r = the lazy x f mod m (x < 2m,
 //                          f <= 2^20; r < 1.19 m), rn = r mod m
-//   one  28 K m         -> R mod m
-//   sprp F K q a        -> 1 if q is a strong probable prime to base a, else 0
-//   pmin F K n          -> "p groups tests": the minimal p the GPU search
+//   one  K m            -> R mod m
+//   sprp K q a          -> 1 if q is a strong probable prime to base a, else 0
+//   pmin K n            -> "p groups tests": the minimal p the GPU search
 //                          returns for n (odd primes p ascending, p = n mod r
 //                          dropped for the 24 odd bases r, q = n - p tested to
 //                          base 2, then to the other 24 bases), the groups of
 //                          64 table entries the filter read and the base-2
 //                          tests it ran
-//   pmin_nobase2 F K n  -> the same search when every base-2 test fails (the
+//   pmin_nobase2 K n    -> the same search when every base-2 test fails (the
 //                          trip counts of a search that never finds a
 //                          candidate: the whole table)
 // Numbers are hexadecimal without a prefix.
@@ -34,7 +34,6 @@
 #include <type_traits>
 #include <vector>
 
-#include "../paper_2603_02621_amd/csrc/gb_bignum.h"
 #include "../paper_2603_02621_amd/csrc/gb_bignum28.h"
 
 namespace {
@@ -120,61 +119,37 @@ template <int K, int F, class N> N sub_p(const N &n, uint32_t p)
     return q;
 }
 
-template <int K, int F> bool strong(const void *qv, uint32_t a)
+template <int K> void run(const std::string &cmd, std::istringstream &in)
 {
-    if constexpr (F == 28)
-        return gbbig28::strong_prp<K>(*static_cast<const gbbig28::Num<K> *>(qv), a);
-    else
-        return gbbig::strong_prp<K>(*static_cast<const gbbig::Num<K> *>(qv), a);
-}
-
-template <int K, int F> void run(const std::string &cmd, std::istringstream &in)
-{
-    using N = std::conditional_t<F == 28, gbbig28::Num<K>, gbbig::Num<K>>;
-    if (cmd == "mul") {
-        std::string m, a, b;
-        in >> m >> a >> b;
-        const N M = from_hex<K, F, N>(m), A = from_hex<K, F, N>(a), B = from_hex<K, F, N>(b);
-        N r;
-        if constexpr (F == 32) {
-            gbbig::mont_mul<K>(r, A, B, M, gbbig::neg_inv32(M.w[0]));
+    constexpr int F = 28;
+    using N = gbbig28::Num<K>;
+    if (cmd == "sqr" || cmd == "mulsmall" || cmd == "one") {
+        std::string m, a;
+        uint32_t f = 0;
+        in >> m;
+        if (cmd != "one") in >> a;
+        if (cmd == "mulsmall") in >> f;
+        const N M = from_hex<K, F, N>(m);
+        N r = cmd == "one" ? M : from_hex<K, F, N>(a);
+        if (cmd == "sqr") {
+            gbbig28::mont_sqr<K>(r, r, M, gbbig28::neg_inv28(M.w[0]));
+        } else if (cmd == "mulsmall") {
+            gbbig28::mul_small<K>(r, f, M, gbbig28::est_recip<K>(M));
+        } else {
+            gbbig28::mont_one<K>(r, M, gbbig28::bit_length<K>(M), gbbig28::est_recip<K>(M));
             std::cout << to_hex<K, F, N>(r) << "\n";
-        } else {
-            std::fprintf(stderr, "mul is for 32-bit limbs; 28-bit limbs have sqr and mulsmall\n");
-            std::exit(2);
+            return;
         }
-    } else if (cmd == "sqr" || cmd == "mulsmall" || cmd == "one") {
-        if constexpr (F == 28) {
-            std::string m, a;
-            uint32_t f = 0;
-            in >> m;
-            if (cmd != "one") in >> a;
-            if (cmd == "mulsmall") in >> f;
-            const N M = from_hex<K, F, N>(m);
-            N r = cmd == "one" ? M : from_hex<K, F, N>(a);
-            if (cmd == "sqr") {
-                gbbig28::mont_sqr<K>(r, r, M, gbbig28::neg_inv28(M.w[0]));
-            } else if (cmd == "mulsmall") {
-                gbbig28::mul_small<K>(r, f, M, gbbig28::est_recip<K>(M));
-            } else {
-                gbbig28::mont_one<K>(r, M, gbbig28::bit_length<K>(M), gbbig28::est_recip<K>(M));
-                std::cout << to_hex<K, F, N>(r) << "\n";
-                return;
-            }
-            N rn = r;
-            // r < 2m is part of the contract; rn is r reduced once
-            gbbig28::reduce_once<K>(rn, M);
-            std::cout << to_hex<K, F, N>(r) << " " << to_hex<K, F, N>(rn) << "\n";
-        } else {
-            std::fprintf(stderr, "%s is for 28-bit limbs\n", cmd.c_str());
-            std::exit(2);
-        }
+        N rn = r;
+        // r < 2m is part of the contract; rn is r reduced once
+        gbbig28::reduce_once<K>(rn, M);
+        std::cout << to_hex<K, F, N>(r) << " " << to_hex<K, F, N>(rn) << "\n";
     } else if (cmd == "sprp") {
         std::string q;
         uint32_t a;
         in >> q >> a;
         const N Q = from_hex<K, F, N>(q);
-        std::cout << (strong<K, F>(&Q, a) ? 1 : 0) << "\n";
+        std::cout << (gbbig28::strong_prp<K>(Q, a) ? 1 : 0) << "\n";
     } else if (cmd == "pmin" || cmd == "pmin_nobase2") {
         static const std::vector<uint32_t> primes = odd_primes(1u << 22);
         std::string h;
@@ -193,9 +168,9 @@ template <int K, int F> void run(const std::string &cmd, std::istringstream &in)
             if (drop) continue;
             const N q = sub_p<K, F, N>(n, p);
             ++tests;
-            if (nob2 || !strong<K, F>(&q, 2u)) continue;
+            if (nob2 || !gbbig28::strong_prp<K>(q, 2u)) continue;
             bool ok = true;
-            for (int j = 1; j < 25 && ok; ++j) ok = strong<K, F>(&q, kBases[j]);
+            for (int j = 1; j < 25 && ok; ++j) ok = gbbig28::strong_prp<K>(q, kBases[j]);
             if (ok) ans = p;
         }
         std::cout << ans << " " << groups << " " << tests << "\n";
@@ -213,29 +188,23 @@ int main()
     while (std::getline(std::cin, line)) {
         std::istringstream in(line);
         std::string cmd;
-        int F = 0, K = 0;
-        in >> cmd;
-        in >> F >> K;
-        if (F == 28) {
-            switch (K) {
-            case 4: run<4, 28>(cmd, in); break;
-            case 6: run<6, 28>(cmd, in); break;
-            case 8: run<8, 28>(cmd, in); break;
-            case 10: run<10, 28>(cmd, in); break;
-            case 12: run<12, 28>(cmd, in); break;
-            case 14: run<14, 28>(cmd, in); break;
-            case 16: run<16, 28>(cmd, in); break;
-            default: std::fprintf(stderr, "no 28-bit form with %d limbs\n", K); return 2;
-            }
-        } else if (F == 32) {
-            switch (K) {
-            case 24: run<24, 32>(cmd, in); break;
-            case 32: run<32, 32>(cmd, in); break;
-            default: std::fprintf(stderr, "no 32-bit form with %d limbs\n", K); return 2;
-            }
-        } else {
-            std::fprintf(stderr, "limb bits must be 28 or 32\n");
-            return 2;
+        int K = 0;
+        in >> cmd >> K;
+        switch (K) {
+        case 4: run<4>(cmd, in); break;
+        case 6: run<6>(cmd, in); break;
+        case 8: run<8>(cmd, in); break;
+        case 10: run<10>(cmd, in); break;
+        case 12: run<12>(cmd, in); break;
+        case 14: run<14>(cmd, in); break;
+        case 16: run<16>(cmd, in); break;
+        case 20: run<20>(cmd, in); break;
+        case 24: run<24>(cmd, in); break;
+        case 28: run<28>(cmd, in); break;
+        case 32: run<32>(cmd, in); break;
+        case 36: run<36>(cmd, in); break;
+        case 37: run<37>(cmd, in); break;
+        default: std::fprintf(stderr, "no form with %d limbs\n", K); return 2;
         }
         std::cout.flush();
     }

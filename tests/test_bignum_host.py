@@ -1,15 +1,15 @@
-"""The GPU's multi-limb headers (gb_bignum28.h, gb_bignum.h) built for the CPU
-with g++ under the address and undefined-behaviour sanitizers, and checked
-against Python integers and the big-n oracle: the 28-bit form's lazy
-Montgomery squaring, its multiplication by a small integer (quotient
-estimated in double precision) and R mod m, the 32-bit form's Montgomery
-product, strong probable-prime tests to all 25 bases, and the minimal-p
-search in the kernels' order (odd bases filter, base 2, then the other 24
-bases), at every limb count the library compiles (28-bit limbs: 4, 6, ...,
-16; 32-bit limbs: 32, plus 24, the form that gave wrong answers on the GPU).
+"""The GPU's multi-limb header (gb_bignum28.h, 28-bit limbs) built for the
+CPU with g++ under the address and undefined-behaviour sanitizers, and
+checked against Python integers and the big-n oracle: the lazy Montgomery
+squaring, the multiplication by a small integer (quotient estimated in
+double precision from the top limbs), R mod m, strong probable-prime tests
+to all 25 bases, and the minimal-p search in the kernels' order (odd bases
+filter, base 2, then the other 24 bases), at every limb count the library
+compiles (K = 4, 6, ..., 16, 20, 24, ..., 36, 37) and at the bounds of the
+moduli each takes.
 
 The last test models the search's trip counts: a base-2 test that never
-passes (what a wrong device build of it does) sends a wavefront through the
+passes (what a wrong device build of it does) sends a search through the
 whole prime table instead of a few groups of 64."""
 import os
 import random
@@ -23,8 +23,7 @@ from oracle import big
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "bignum_host.cpp")
 LIMIT = 1 << 22                       # the driver's prime table: odd primes below 2^22
-FORMS28 = [(28, K) for K in (4, 6, 8, 10, 12, 14, 16)]
-FORMS = FORMS28 + [(32, 24), (32, 32)]
+FORMS = (4, 6, 8, 10, 12, 14, 16, 20, 24, 28, 32, 36, 37)
 
 pytestmark = pytest.mark.skipif(shutil.which("g++") is None, reason="needs g++")
 
@@ -49,59 +48,47 @@ def drv(tmp_path_factory):
     assert p.wait(timeout=30) == 0
 
 
-def _bits(F, K):
-    return F * K
+def _widths(K):
+    """Modulus widths a form takes: 2^(28(K-E)+24) <= m < 2^(28K-2), with E the
+    limbs of the quotient estimate (3 up to K = 16, 5 above)."""
+    E = 3 if K <= 16 else 5
+    return 28 * (K - E) + 25, 28 * K - 2
 
 
-def _widths(F, K):
-    """Modulus widths a form takes: 28-bit limbs need 2^(28K-60) <= m < 2^(28K-2)."""
-    return (28 * K - 59, 28 * K - 2) if F == 28 else (40, 32 * K)
+def _form(bits):
+    """The form the library picks for an n of this many bits."""
+    return next(K for K in FORMS if 28 * K - 2 >= bits)
 
 
-@pytest.mark.parametrize("F,K", [(32, 24), (32, 32)])
-def test_montgomery_product(drv, F, K):
-    rng = random.Random(F * 100 + K)
-    R = 1 << (F * K)
-    for t in range(40):
-        # moduli of every width up to the form's, including the full width
-        w = _bits(F, K) if t % 3 == 0 else rng.randrange(40, _bits(F, K) + 1)
-        m = rng.getrandbits(w) | 1 | (1 << (w - 1))
-        a, b = rng.randrange(m), rng.randrange(m)
-        if t == 1:
-            a, b = m - 1, m - 1
-        got = int(drv(f"mul {F} {K} {m:x} {a:x} {b:x}"), 16)
-        assert got == a * b * pow(R, -1, m) % m, (F, K, hex(m))
-
-
-@pytest.mark.parametrize("F,K", FORMS28)
-def test_lazy_squaring_small_multiplier_and_one(drv, F, K):
+@pytest.mark.parametrize("K", FORMS)
+def test_lazy_squaring_small_multiplier_and_one(drv, K):
     # operands anywhere in [0, 2m), the lazy range; results must stay in
     # [0, 2m) for the squaring and [0, 1.19 m) for the small multiplier, and
     # agree with Python integers mod m
     rng = random.Random(K)
     R = 1 << (28 * K)
-    lo, hi = _widths(F, K)
+    lo, hi = _widths(K)
     for t in range(60):
         w = (lo, hi)[t % 2] if t < 4 else rng.randrange(lo, hi + 1)
         m = rng.getrandbits(w) | 1 | (1 << (w - 1))
         a = (2 * m - 1, 0, m, 1)[t % 4] if t < 8 else rng.randrange(2 * m)
-        r, rn = (int(x, 16) for x in drv(f"sqr 28 {K} {m:x} {a:x}").split())
+        r, rn = (int(x, 16) for x in drv(f"sqr {K} {m:x} {a:x}").split())
         want = a * a * pow(R, -1, m) % m
         assert r < 2 * m and r % m == want and rn == want, (K, hex(m), hex(a))
         f = (1 << 20, 1, 97 ** 3, 2)[t % 4] if t < 8 else rng.randrange(1, (1 << 20) + 1)
-        r, rn = (int(x, 16) for x in drv(f"mulsmall 28 {K} {m:x} {a:x} {f}").split())
+        r, rn = (int(x, 16) for x in drv(f"mulsmall {K} {m:x} {a:x} {f}").split())
         assert 100 * r < 119 * m and r % m == a * f % m and rn == a * f % m, (K, hex(m), hex(a), f)
-        assert int(drv(f"one 28 {K} {m:x}"), 16) == R % m
+        assert int(drv(f"one {K} {m:x}"), 16) == R % m
 
 
-@pytest.mark.parametrize("F,K", FORMS)
-def test_strong_tests_match_the_oracle(drv, F, K):
-    rng = random.Random(7 * K + F)
-    lo, hi = _widths(F, K)
-    lo, hi = max(lo, 66), min(hi, 1020)
+@pytest.mark.parametrize("K", FORMS)
+def test_strong_tests_match_the_oracle(drv, K):
+    rng = random.Random(7 * K + 28)
+    lo, hi = _widths(K)
+    lo = max(lo, 66)
     qs = []
-    for t in range(6):
-        w = rng.randrange(max(lo, hi - 120), hi + 1) if F == 32 else rng.randrange(lo, hi + 1)
+    for t in range(6 if K <= 16 else 3):
+        w = (lo, hi)[t % 2] if t < 2 else rng.randrange(lo, hi + 1)
         q = rng.getrandbits(w) | 1 | (1 << (w - 1))
         while not big.probable_prime(q):
             q += 2
@@ -113,13 +100,11 @@ def test_strong_tests_match_the_oracle(drv, F, K):
     # strong pseudoprimes to the first 12 and 13 prime bases
     qs += [318665857834031151167461, 3317044064679887385961981]
     for q in qs:
-        if F == 28 and not (lo <= q.bit_length() <= hi):
-            continue
-        if q.bit_length() > _bits(F, K) or q < 100:
+        if not (lo <= q.bit_length() <= hi):
             continue
         for a in big.BASES:
             want = big.strong_probable_prime(q, a)
-            assert int(drv(f"sprp {F} {K} {q:x} {a}")) == int(want), (F, K, hex(q), a)
+            assert int(drv(f"sprp {K} {q:x} {a}")) == int(want), (K, hex(q), a)
 
 
 def _random_even(bits, rng):
@@ -127,32 +112,29 @@ def _random_even(bits, rng):
     return n - (n & 1)
 
 
-@pytest.mark.parametrize("bits,F,K", [(100, 28, 4), (160, 28, 6), (200, 28, 8), (250, 28, 10),
-                                      (280, 28, 12), (333, 28, 12), (390, 28, 14), (440, 28, 16),
-                                      (520, 32, 32), (600, 32, 24), (700, 32, 24), (700, 32, 32),
-                                      (1020, 32, 32)])
-def test_minimal_p_search_matches_the_oracle(drv, bits, F, K):
-    # the inputs of the GPU tests at these sizes (random.Random(bits)); the
-    # 520-bit n are those of the GPU case that did not finish, the 600- and
-    # 700-bit n those of the 24-limb case that gave wrong answers
+@pytest.mark.parametrize("bits", [100, 160, 200, 250, 280, 333, 390, 440, 447, 520, 600, 700, 1020, 1024])
+def test_minimal_p_search_matches_the_oracle(drv, bits):
+    # the inputs of the GPU tests at these sizes (random.Random(bits)), in
+    # the form the library picks for them
     rng = random.Random(bits)
     ns = [_random_even(bits, rng) for _ in range(6)]
-    for n in ns[:3]:
-        p, groups, tests = (int(x) for x in drv(f"pmin {F} {K} {n:x}").split())
-        assert p == big.pmin_big(n, limit=LIMIT), (bits, F, K)
+    K = _form(bits)
+    for n in ns[:3 if bits < 600 else 1]:
+        p, groups, tests = (int(x) for x in drv(f"pmin {K} {n:x}").split())
+        assert p == big.pmin_big(n, limit=LIMIT), (bits, K)
         assert p > 0 and tests >= 1 and groups >= 1
 
 
 def test_search_without_base2_passes_reads_the_whole_table(drv):
-    # A wavefront stops at its first candidate; with a base-2 test that never
+    # A search stops at its first candidate; with a base-2 test that never
     # passes it filters every table entry instead.  At 520 bits the real
     # search reads a handful of groups of 64 entries; the failing one reads
     # all of them (here 2^22 / ln-density ~ 4.6k groups, in the library's
     # 2.07M-prime table about 32k groups and 4.4e5 base-2 tests per n).
     rng = random.Random(520)
     n = _random_even(520, rng)
-    p, g_ok, t_ok = (int(x) for x in drv(f"pmin 32 32 {n:x}").split())
-    z, g_all, t_all = (int(x) for x in drv(f"pmin_nobase2 32 32 {n:x}").split())
+    p, g_ok, t_ok = (int(x) for x in drv(f"pmin 20 {n:x}").split())
+    z, g_all, t_all = (int(x) for x in drv(f"pmin_nobase2 20 {n:x}").split())
     nprimes = sum(1 for _ in big._odd_primes(LIMIT))
     assert p > 0 and z == 0
     assert g_all == (nprimes + 63) // 64

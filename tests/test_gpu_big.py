@@ -1,6 +1,8 @@
 """Minimal Goldbach prime of even n beyond 64 bits on the GPU against the
 big-n oracle (GPU): the paper's Table 5 values, random n in every limb-count
-class (up to 1020 bits), n just above 2^64, a batch, and the argument checks."""
+class (up to 1024 bits) and at each class's edges, n just above 2^64, a
+batch, base-2 pseudoprime candidates, one call over every class, and the
+argument checks."""
 import random
 
 import pytest
@@ -75,11 +77,12 @@ def test_base2_pseudoprime_candidate_is_rejected(V, psi):
     assert got[0] > 3
 
 
-@pytest.mark.parametrize("bits", [110, 111, 166, 167, 222, 223, 278, 279, 334, 335, 390, 391, 446, 447])
+@pytest.mark.parametrize("bits", [110, 111, 166, 167, 222, 223, 278, 279, 334, 335, 390, 391, 446, 447,
+                                  558, 559, 670, 671, 782, 783, 894, 895, 1006, 1007, 1024])
 def test_limb_class_edges(V, bits):
     # n of exactly `bits` bits: the largest and smallest of each class of
-    # 28-bit limbs (K = 4, 6, ..., 16 limbs hold n up to 28K - 2 bits) and the
-    # first n of the 32-limb form
+    # 28-bit limbs (K = 4, 6, ..., 16, 20, 24, ..., 36, 37 limbs hold n up to
+    # 28K - 2 bits), up to the largest n the call takes
     rng = random.Random(1000 + bits)
     top = (1 << bits) - 2                              # all ones but the last bit
     low = 1 << (bits - 1)

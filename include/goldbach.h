@@ -384,7 +384,9 @@ typedef struct gb_server_stats {
 
 /* Start a server on prm->device (prm may be NULL) with `streams` device
  * streams (1..8, 0 -> 2) and at most `max_batch` requests per launch
- * (0 -> 4096). */
+ * (0 -> 4096).  Unlike gb_create, a tile_log2 or wg_threads left 0 takes
+ * 16 and 1024: small tiles spread one range over many workgroups, which
+ * cuts request latency (tiles of 2^19 n suit whole-range throughput). */
 gb_status gb_server_start(gb_server **srv, const gb_params *prm, uint32_t streams,
                           uint32_t max_batch);
 /* Queue one request; *id receives its id.  GB_EINVAL for a malformed

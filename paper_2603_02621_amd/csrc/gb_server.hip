@@ -62,6 +62,8 @@ struct Req {
 
 constexpr uint64_t kStageN = 1ull << 24;       // per-n staging entries set up at start
 constexpr uint64_t kStageTiles = 1ull << 16;   // tile records set up at start
+constexpr uint32_t kServeTileLog2 = 16;         // server tiles when the caller sets none
+constexpr uint32_t kServeThreads = 1024;        // and their workgroup size
 
 struct Lane {
     hipStream_t stream = nullptr;
@@ -411,24 +413,31 @@ gb_status submit_at(gb_server *s, const gb_request &r, uint64_t submit_ns, uint6
 gb_status warm_lanes(gb_server *s)
 {
     gb_ctx *c = s->ctx;
+    // every launch path once per lane: a single n beside a range with no
+    // per-n output, with it in host memory, and with it in device memory,
+    // so that no request pays a first launch of a kernel
     std::vector<uint16_t> out(256);
-    for (uint32_t i = 0; i < s->lanes.size(); ++i) {
+    uint16_t *dout = nullptr;
+    GB_HIP(c, hipMalloc(&dout, 256 * sizeof(uint16_t)));
+    gb_status st = GB_OK;
+    for (uint32_t i = 0; i < s->lanes.size() && st == GB_OK; ++i) {
         Lane &L = s->lanes[i];
-        for (int with_out = 0; with_out < 2; ++with_out) {
+        for (int form = 0; form < 3 && st == GB_OK; ++form) {
             L.batch.clear();
             Req a, b;
             a.r = gb_request{GB_REQ_ONE, 0, 1000000000000ull, 1, nullptr, 0};
-            b.r = gb_request{GB_REQ_RANGE, 0, 1000000000000ull, 256, with_out ? out.data() : nullptr, 0};
+            b.r = gb_request{GB_REQ_RANGE, form == 2 ? GB_REQ_PMIN_DEVICE : 0u, 1000000000000ull, 256,
+                             form == 0 ? nullptr : form == 1 ? out.data() : dout, 0};
             L.batch.push_back(a);
             L.batch.push_back(b);
-            gb_status st = launch_batch(s, L);
-            GB_HIP(c, hipStreamSynchronize(L.stream));
-            if (st != GB_OK) return st;
+            st = launch_batch(s, L);
+            if (hipStreamSynchronize(L.stream) != hipSuccess && st == GB_OK) st = GB_EDEVICE;
             L.batch.clear();
             L.ones_open = L.ranges_open = false;
         }
     }
-    return GB_OK;
+    (void)hipFree(dout);
+    return st;
 }
 
 void release_lanes(gb_server *s)
@@ -460,7 +469,13 @@ gb_status gb_server_start(gb_server **out, const gb_params *prm, uint32_t stream
     gb_server *s = new (std::nothrow) gb_server();
     if (!s) return GB_ENOMEM;
     s->max_batch = max_batch ? max_batch : 4096;
-    gb_status st = gb_create(&s->ctx, prm);
+    // latency first: tiles of 2^16 n with 1024 threads unless the caller
+    // sets them, so that a range spreads over many workgroups
+    gb_params p{};
+    if (prm) p = *prm;
+    if (p.tile_log2 == 0) p.tile_log2 = kServeTileLog2;
+    if (p.wg_threads == 0) p.wg_threads = kServeThreads;
+    gb_status st = gb_create(&s->ctx, &p);
     if (st != GB_OK) {
         delete s;
         return st;
@@ -479,7 +494,7 @@ gb_status gb_server_start(gb_server **out, const gb_params *prm, uint32_t stream
              L.ws.hist.ensure(GB_HIST_BINS_I) == hipSuccess && L.ws.h_hist.ensure(GB_HIST_BINS_I) == hipSuccess &&
              L.ws.q.ensure(2 * mb) == hipSuccess && L.ws.h_q.ensure(2 * mb) == hipSuccess &&
              L.ws.pmin.ensure(2 * kStageN) == hipSuccess && L.h_pmin.ensure(kStageN) == hipSuccess &&
-             L.h_win.ensure(mb) == hipSuccess && L.scat.ensure(256) == hipSuccess && L.h_scat.ensure(256) == hipSuccess;
+             L.h_win.ensure(mb) == hipSuccess && L.scat.ensure(mb) == hipSuccess && L.h_scat.ensure(mb) == hipSuccess;
         if (!ok) break;
     }
     if (ok) ok = warm_lanes(s) == GB_OK;

@@ -41,7 +41,7 @@ struct GbScatter {
     unsigned long long len;
 };
 
-constexpr uint32_t kScatterChunk = 1u << 16;   // entries per workgroup
+constexpr uint32_t kScatterChunk = 1u << 12;   // entries per workgroup (16 per thread)
 
 // blockIdx.y: the range; blockIdx.x: its chunk of kScatterChunk entries
 __global__ __launch_bounds__(256) void k_scatter16(const GbScatter *e, const uint16_t *src)

@@ -136,6 +136,8 @@ gb_status enqueue_tiles(gb_ctx *c, Workspace &ws, const Job &j, hipStream_t st)
     a.hist = ws.hist.p;
     a.hist_per_slot = j.hist_rows > 1 ? 1u : 0u;
     a.recs = ws.recs.p;
+    a.rec_count = ws.counters.p + 2;
+    a.rec_cap = ws.recs.cap;
     a.pmin = j.pmin_dev;
     const Plan &pl = *j.pl;
     if (j.persistent) {
@@ -183,8 +185,8 @@ gb_status enqueue_rest(gb_ctx *c, Workspace &ws, const Job &j, hipStream_t st)
     m.hist = ws.hist.p;
     m.hist_per_slot = j.hist_rows > 1 ? 1u : 0u;
     GB_HIP(c, gb_launch_mr(m, mr_grid(c), st));
-    GB_HIP(c, gb_launch_argmax(ws.slots.p, ws.recs.p, j.pl->ntiles, ws.list.p, ws.counters.p,
-                               c->prm.max_unresolved, st));
+    GB_HIP(c, gb_launch_argmax(ws.slots.p, ws.recs.p, ws.counters.p + 2, ws.recs.cap, ws.list.p,
+                               ws.counters.p, c->prm.max_unresolved, st));
     GB_HIP(c, hipMemcpyAsync(ws.h_slots.p, ws.slots.p, j.nslots * sizeof(GbSlot), hipMemcpyDeviceToHost, st));
     GB_HIP(c, hipMemcpyAsync(ws.h_hist.p, ws.hist.p, j.hist_rows * GB_HIST_BINS_I * 8, hipMemcpyDeviceToHost,
                              st));

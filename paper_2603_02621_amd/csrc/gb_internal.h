@@ -29,8 +29,9 @@ struct GbSlot {
         n_failed, first_failed_n, pad;
 };
 
-// Per-tile record for the argmax pass: the tile's largest p_min and the
-// smallest n in the tile that has it.
+// Record for the argmax pass: the largest p_min of a run of tiles of one
+// slot that one workgroup took in turn, and the smallest n of the run that
+// has it.
 struct GbTileRec {
     unsigned long long argmax_n;
     uint32_t max_p;
@@ -67,7 +68,9 @@ struct GbTileArgs {
     GbSlot *slots;
     unsigned long long *hist;  // rows of GB_HIST_BINS_I
     uint32_t hist_per_slot;    // 1: row = slot, 0: row 0
-    GbTileRec *recs;           // one per global tile
+    GbTileRec *recs;           // argmax records, appended by workgroups
+    unsigned long long *rec_count;  // records appended so far
+    unsigned long long rec_cap;     // capacity of recs (at least the tile count)
     GbExh *list;
     unsigned long long *list_count;
     unsigned long long list_cap;
@@ -101,9 +104,10 @@ hipError_t gb_tile_occupancy(uint32_t threads, size_t lds_bytes, bool group_wind
 size_t gb_tile_lds_bytes(uint32_t tile_n, uint32_t halo_bits, uint32_t np_search,
                          uint32_t n_off);
 hipError_t gb_launch_mr(const GbMrArgs &a, uint32_t grid, hipStream_t st);
-hipError_t gb_launch_argmax(GbSlot *slots, const GbTileRec *recs, uint64_t nrecs,
-                            const GbExh *list, const unsigned long long *list_count,
-                            unsigned long long list_cap, hipStream_t st);
+hipError_t gb_launch_argmax(GbSlot *slots, const GbTileRec *recs, const unsigned long long *rec_count,
+                            unsigned long long rec_cap, const GbExh *list,
+                            const unsigned long long *list_count, unsigned long long list_cap,
+                            hipStream_t st);
 hipError_t gb_launch_init(GbSlot *slots, uint64_t nslots, unsigned long long *hist,
                           uint64_t hist_words, unsigned long long *counters,
                           uint32_t ncounters, hipStream_t st);

@@ -165,7 +165,11 @@ struct TileLds {
     // 2^16 - (p+1)/2, the four hit counts of this tile
     uint32_t *pr;
     uint32_t *offs;           // first bit index (or ~0) of each small/medium sieving prime
-    unsigned long long *red;  // 4: checksum, n_exhaustive, max key, OR words
+    unsigned long long *red;  // 7: checksum, n_exhaustive, max key, OR words,
+                              // deficits (floor(n/128), 2^i of half 0, half 1)
+    // the slot summaries of the workgroup's current run of tiles of one slot
+    // (thread 0 only): count, checksum, n_exhaustive, argmax n, slot, max p
+    unsigned long long *carry;
     unsigned long long *tile; // persistent mode: the tile just taken
     uint32_t *next;           // next block of the tile to hand out
 };
@@ -183,7 +187,9 @@ __device__ __forceinline__ TileLds carve(uint32_t *smem, const GbTileArgs &a)
     o += a.n_off;
     o = (o + 1) & ~1u;
     L.red = reinterpret_cast<unsigned long long *>(smem + o);
-    o += 2 * 4;
+    o += 2 * 7;
+    L.carry = reinterpret_cast<unsigned long long *>(smem + o);
+    o += 2 * 6;
     o = (o + 1) & ~1u;
     L.tile = reinterpret_cast<unsigned long long *>(smem + o);
     o += 2;
@@ -224,6 +230,33 @@ __device__ void setup_primes(const GbTileArgs &a, const TileLds &L)
         L.pr[pr_gl(i)] = VERIFY ? (65536u - h) << 16 : 65536u - h;
         L.pr[pr_lh(i)] = 0;
     }
+}
+
+// The slot summaries a workgroup carries from tile to tile (thread 0, in
+// LDS): one set of slot atomics and one argmax record per run of tiles of
+// one slot instead of per tile.
+constexpr unsigned long long kNoSlot = ~0ull;
+enum { CY_COUNT, CY_SUM, CY_EXH, CY_ARGN, CY_SLOT, CY_MAXP };
+
+__device__ void flush_slot(const GbTileArgs &a, unsigned long long *C)
+{
+    if (C[CY_SLOT] == kNoSlot) return;
+    GbSlot *S = a.slots + C[CY_SLOT];
+    atomicAdd(&S->count, C[CY_COUNT]);
+    if (C[CY_SUM]) atomicAdd(&S->checksum, C[CY_SUM]);
+    if (C[CY_EXH]) atomicAdd(&S->n_exhaustive, C[CY_EXH]);
+    if (C[CY_MAXP]) {
+        atomicMax(&S->max_p, C[CY_MAXP]);
+        const unsigned long long e = atomicAdd(a.rec_count, 1ull);
+        if (e < a.rec_cap) {
+            GbTileRec r;
+            r.argmax_n = C[CY_ARGN];
+            r.max_p = (uint32_t)C[CY_MAXP];
+            r.slot = (uint32_t)C[CY_SLOT];
+            a.recs[e] = r;
+        }
+    }
+    C[CY_SLOT] = kNoSlot;
 }
 
 // Add the workgroup's per-prime hit counts to histogram row `row` and clear
@@ -283,7 +316,7 @@ __device__ void process_tile(const GbTileArgs &a, unsigned long long g, const Ti
 
     // ---- per-tile reductions; the workgroup's histogram row ----------------
     if (!SIEVE_ONLY) {
-        if (tid < 4) L.red[tid] = 0ull;   // tile sums, max key, OR words
+        if (tid < 7) L.red[tid] = 0ull;   // tile sums, max key, OR words, deficits
         if (tid == 0) *L.next = NT;       // blocks 0..NT-1 go to the threads in order
         // The per-prime hit counts in L.pr stay in LDS across the tiles of a
         // workgroup and go to the histogram when its row changes (one row per
@@ -492,29 +525,31 @@ __device__ void process_tile(const GbTileArgs &a, unsigned long long g, const Ti
     // At the tile's end these turn into the checksum of the n the search
     // resolved, with p = 2^17 - 1 - 2g, together with the n it did not
     // resolve (masked in front or behind, or left to the exhaustive phase):
-    //   sum of floor(n/128) dB, sum of 2^i per half dx0, dx1.
+    //   sum of floor(n/128), sum of 2^i per half (LDS atomics into red[4..6],
+    //   a rare path, so they hold no registers in the search loop).
     // largest p_min of the lane and its first block, as the smallest key
     // (g << 16) | block over the blocks' last hits (g falls as p grows; the
     // key 0xFFFF << 16 stands for p = 2, and ~0 for no hit)
     uint32_t minkey = 0xFFFFFFFFu;
-    uint32_t nexh = 0;                 // n left to the exhaustive phase
-    uint32_t sumg = 0, sumg0 = 0;      // sumg0: sumg when the current block began
+    // accbg telescopes: at the end of a block b followed by block b' it adds
+    // (b - b') sumg, and after the last block b'' sumg, which sums b times
+    // each block's part of sumg without a copy of sumg per block
+    uint32_t sumg = 0;
     unsigned long long accbg = 0;
     unsigned long long s0 = 0, s1 = 0;
-    unsigned long long dx0 = 0, dx1 = 0;
-    unsigned long long dB = 0;
     auto deficit = [&](uint32_t blk, uint32_t mlo, uint32_t mhi) {
         const uint32_t c = __popc(mlo) + __popc(mhi);
-        dB += ((N0 >> 7) + blk) * (unsigned long long)c;
-        dx0 += mlo;
-        dx1 += mhi;
+        if (c == 0u) return;
+        atomicAdd(&L.red[4], ((N0 >> 7) + blk) * (unsigned long long)c);
+        if (mlo) atomicAdd(&L.red[5], (unsigned long long)mlo);
+        if (mhi) atomicAdd(&L.red[6], (unsigned long long)mhi);
     };
 
     // n no fast-path prime resolves go to the exhaustive phase's list
     auto push_unresolved = [&](uint32_t blk, uint32_t ulo, uint32_t uhi) {
         deficit(blk, ulo, uhi);
         unsigned long long u = ((unsigned long long)uhi << 32) | ulo;
-        nexh += __popcll(u);
+        atomicAdd(&L.red[1], (unsigned long long)__popcll(u));
         while (u) {
             const uint32_t j = (uint32_t)__builtin_ctzll(u);
             u &= u - 1ull;
@@ -706,8 +741,7 @@ __device__ void process_tile(const GbTileArgs &a, unsigned long long g, const Ti
                     // necessarily a hit, so its last hit is found again
                     if (Ulo | Uhi) lastkey = last_hit_key(b);
                 } else {
-                    accbg += (unsigned long long)b * (sumg - sumg0);
-                    sumg0 = sumg;
+                    accbg += (unsigned long long)(long long)((int)b - (int)nb) * sumg;
                 }
                 minkey = min(minkey, lastkey | b);
                 if (Ulo | Uhi) push_unresolved(b, Ulo, Uhi);
@@ -745,8 +779,9 @@ __device__ void process_tile(const GbTileArgs &a, unsigned long long g, const Ti
             deficit(nblk - 1u, ~lo, ~hi);
         }
     }
-    unsigned long long ysum = 0ull - 131071ull * dB - 2ull * ((N0 >> 7) * sumg + accbg);
-    unsigned long long zsum = (0ull - 131071ull * dx0 - 2ull * s0) + 3ull * (0ull - 131071ull * dx1 - 2ull * s1);
+    accbg += (unsigned long long)b * sumg;
+    unsigned long long ysum = 0ull - 2ull * ((N0 >> 7) * sumg + accbg);
+    unsigned long long zsum = (0ull - 2ull * s0) + 3ull * (0ull - 2ull * s1);
     if (tid == 0u) {
         // every block's floor(n/128) for its 64 n, and every half's 2^i sum
         const unsigned long long nb = nblk;
@@ -762,11 +797,15 @@ __device__ void process_tile(const GbTileArgs &a, unsigned long long g, const Ti
     // LDS atomics instead of shuffles: nothing per lane stays live for them
     // across the tiles of a persistent workgroup
     if (cs) atomicAdd(&L.red[0], cs);
-    if (nexh) atomicAdd(&L.red[1], (unsigned long long)nexh);
     if (maxp) atomicMax(&L.red[2], key);
     __syncthreads();
     if (wave == 0) {
-        const unsigned long long csum = L.red[0], xsum = L.red[1], kmax = L.red[2];
+        // the lanes' parts plus the deficit terms of the n not resolved here
+        const unsigned long long csum =
+            VERIFY ? 0ull
+                   : L.red[0] + ((0ull - 131071ull * L.red[4]) << 33) + (0ull - 131071ull * L.red[5]) +
+                         3ull * (0ull - 131071ull * L.red[6]);
+        const unsigned long long xsum = L.red[1], kmax = L.red[2];
         const uint32_t mp = (uint32_t)(kmax >> 32);
         const uint32_t mb = 0xFFFFFFFFu - (uint32_t)(kmax & 0xFFFFFFFFu);
         // smallest n of block mb with p_min = mp: the n of the block that mp
@@ -801,16 +840,21 @@ __device__ void process_tile(const GbTileArgs &a, unsigned long long g, const Ti
             am = 64u * mb + (hlo ? (uint32_t)__builtin_ctz(hlo) : 32u + (uint32_t)__builtin_ctz(hhi));
         }
         if (lane == 0) {
-            GbSlot *S = a.slots + slot;
-            atomicAdd(&S->count, (unsigned long long)(cnt - lead));
-            atomicAdd(&S->checksum, csum);
-            if (xsum) atomicAdd(&S->n_exhaustive, xsum);
-            if (mp) atomicMax(&S->max_p, (unsigned long long)mp);
-            GbTileRec r;
-            r.argmax_n = mp ? N0 + 2ull * am : 0ull;
-            r.max_p = mp;
-            r.slot = slot;
-            a.recs[g] = r;
+            unsigned long long *C = L.carry;
+            if (C[CY_SLOT] != slot) {
+                flush_slot(a, C);
+                C[CY_COUNT] = C[CY_SUM] = C[CY_EXH] = C[CY_MAXP] = 0ull;
+                C[CY_ARGN] = ~0ull;
+                C[CY_SLOT] = slot;
+            }
+            C[CY_COUNT] += cnt - lead;
+            C[CY_SUM] += csum;
+            C[CY_EXH] += xsum;
+            const unsigned long long an = N0 + 2ull * am;
+            if (mp > C[CY_MAXP] || (mp != 0u && mp == C[CY_MAXP] && an < C[CY_ARGN])) {
+                C[CY_MAXP] = mp;
+                C[CY_ARGN] = an;
+            }
         }
     }
     __syncthreads();
@@ -822,7 +866,10 @@ __global__ __launch_bounds__(NT) void k_tile(GbTileArgs a)
     extern __shared__ uint32_t smem[];
     const TileLds L = carve(smem, a);
     HistCarry hc;
-    if constexpr (!SIEVE_ONLY) setup_primes<NT, PB == 1, GW>(a, L);   // behind the first barrier below
+    if constexpr (!SIEVE_ONLY) {
+        setup_primes<NT, PB == 1, GW>(a, L);   // behind the first barrier below
+        if (threadIdx.x == 0) L.carry[CY_SLOT] = kNoSlot;
+    }
     if constexpr (PERS) {
         for (;;) {
             if (threadIdx.x == 0) *L.tile = atomicAdd(a.queue, 1ull);
@@ -838,6 +885,8 @@ __global__ __launch_bounds__(NT) void k_tile(GbTileArgs a)
     // process_tile ends with a barrier, so every count is in LDS
     if constexpr (!SIEVE_ONLY && PB != 1)
         if (hc.row != kNoRow) flush_hist(a, L, hc.row);
+    if constexpr (!SIEVE_ONLY)
+        if (threadIdx.x == 0) flush_slot(a, L.carry);
 }
 
 
@@ -993,11 +1042,14 @@ __global__ __launch_bounds__(256) void k_mr(GbMrArgs a)
     }
 }
 
-__global__ void k_argmax(GbSlot *slots, const GbTileRec *recs, uint64_t nrecs, const GbExh *list,
+__global__ void k_argmax(GbSlot *slots, const GbTileRec *recs, const unsigned long long *rec_count,
+                         unsigned long long rec_cap, const GbExh *list,
                          const unsigned long long *list_count, unsigned long long cap)
 {
     unsigned long long cnt = *list_count;
     if (cnt > cap) cnt = cap;
+    unsigned long long nrecs = *rec_count;
+    if (nrecs > rec_cap) nrecs = rec_cap;
     const unsigned long long stride = (unsigned long long)gridDim.x * blockDim.x;
     for (unsigned long long i = blockIdx.x * (unsigned long long)blockDim.x + threadIdx.x;
          i < nrecs + cnt; i += stride) {
@@ -1117,7 +1169,8 @@ size_t gb_tile_lds_bytes(uint32_t tile_n, uint32_t halo_bits, uint32_t np_search
     words += 12 * (((size_t)np_search + 3) / 4 + 2);          // prime groups
     words += n_off;                                       // first strikes
     words = (words + 1) & ~(size_t)1;
-    words += 2 * 4;                                       // tile reductions
+    words += 2 * 7;                                       // tile reductions
+    words += 2 * 6;                                       // the slot carry
     words = (words + 1) & ~(size_t)1;
     words += 2;                                           // the persistent tile index
     words += 2;                                           // the block counter (and padding)
@@ -1169,12 +1222,13 @@ hipError_t gb_launch_mr(const GbMrArgs &a, uint32_t grid, hipStream_t st)
     return hipGetLastError();
 }
 
-hipError_t gb_launch_argmax(GbSlot *slots, const GbTileRec *recs, uint64_t nrecs, const GbExh *list,
+hipError_t gb_launch_argmax(GbSlot *slots, const GbTileRec *recs, const unsigned long long *rec_count,
+                            unsigned long long rec_cap, const GbExh *list,
                             const unsigned long long *list_count, unsigned long long list_cap,
                             hipStream_t st)
 {
-    hipLaunchKernelGGL(k_argmax, dim3(1024), dim3(256), 0, st, slots, recs, nrecs, list, list_count,
-                       list_cap);
+    hipLaunchKernelGGL(k_argmax, dim3(1024), dim3(256), 0, st, slots, recs, rec_count, rec_cap, list,
+                       list_count, list_cap);
     return hipGetLastError();
 }
 

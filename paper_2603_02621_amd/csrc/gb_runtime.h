@@ -12,7 +12,7 @@
 namespace gbrt {
 
 constexpr uint64_t kDefaultMaxHi = 1ull << 50;
-constexpr uint32_t kCounters = 4;  // [0] exhaustive-list length, [1] work queue
+constexpr uint32_t kCounters = 4;  // [0] exhaustive-list length, [1] work queue, [2] argmax records
 
 // Every move of a device or pinned scratch buffer bumps this, so a cached
 // HIP graph that captured the old addresses is never replayed.

@@ -21,13 +21,17 @@
  *   count          number of even n examined
  *   max_p/argmax_n largest p_min and the smallest n attaining it
  *   checksum       sum over n of w(n) * p_min(n), modulo 2^64, with the
- *                  weight w(n) = 2^33 * floor(n/128) + (2c+1) * 2^i, where
- *                  j = (n/2) mod 64, c = floor(j/32), i = j mod 32
- *                  (orc_checksum_weight).  w(n) has exactly i <= 31
- *                  factors of 2 and the difference of two p below 2^16 at
- *                  most 15, so any single wrong p_min changes it; so does
- *                  any exchange of p between two n within 256 of each other
- *                  (their weights differ by at most 33 factors of 2).
+ *                  weight w(n) = 2^33 * b(n) + (2c+1) * 2^i, where
+ *                  b(n) = 3 floor(n/384) + (n mod 6)/2 numbers the sets of
+ *                  64 even n of one residue class mod 6 and one stretch of
+ *                  384, j = floor(n/6) mod 64 is the place of n in its set,
+ *                  c = floor(j/32), i = j mod 32 (orc_checksum_weight).
+ *                  w(n) has exactly i <= 31 factors of 2 and the
+ *                  difference of two p below 2^16 at most 15, so any single
+ *                  wrong p_min changes it; so does any exchange of p
+ *                  between two n whose b differ by less than 2^16 (n closer
+ *                  than 8 million): their weights differ by at most 33 + 15
+ *                  factors of 2.
  *   hist[i]        number of n whose p_min is the i-th prime (2 -> 0,
  *                  3 -> 1, ...) for p_min < 2^16; bin 6542 counts larger p
  *   n_exhaustive   number of n that no prime p <= P_max resolves (the n a
@@ -224,9 +228,10 @@ static uint32_t hist_bin(uint64_t p, const uint32_t *small, uint64_t nsmall)
 /* The checksum weight of n, written out from its definition above. */
 uint64_t orc_checksum_weight(uint64_t n)
 {
-    uint64_t j = (n / 2) % 64;
+    uint64_t b = 3 * (n / 384) + (n % 6) / 2;
+    uint64_t j = (n / 6) % 64;
     uint64_t c = j / 32, i = j % 32;
-    return ((n / 128) << 33) + ((2 * c + 1) << i);
+    return (b << 33) + ((2 * c + 1) << i);
 }
 
 static void record(orc_summary *s, uint64_t *hist, const uint32_t *small,

@@ -162,9 +162,11 @@ def test_pmin_bruteforce_1e5(orc, td_table):
 
 
 def _weight(n):
-    """Checksum weight of n: 2^33 floor(n/128) + (2c+1) 2^i, j = n/2 mod 64 = 32c + i."""
-    c, i = divmod((n // 2) % 64, 32)
-    return ((n // 128 << 33) + ((2 * c + 1) << i)) % 2**64
+    """Checksum weight of n: 2^33 b + (2c+1) 2^i with b = 3 floor(n/384) +
+    (n mod 6)/2 and j = floor(n/6) mod 64 = 32c + i."""
+    b = 3 * (n // 384) + (n % 6) // 2
+    c, i = divmod((n // 6) % 64, 32)
+    return ((b << 33) + ((2 * c + 1) << i)) % 2**64
 
 
 def _summaries_by_hand(ns, ps, pmax):
@@ -204,7 +206,7 @@ def _v2(x):
 
 def test_checksum_weight_definition(orc):
     rng = np.random.default_rng(11)
-    ns = [4, 6, 126, 128, 130, 254, 256, 2**63, 2**63 - 2] + \
+    ns = [4, 6, 8, 126, 128, 130, 254, 256, 382, 384, 386, 388, 2**63, 2**63 - 2] + \
         [int(x) * 2 for x in rng.integers(2, 2**62, size=2000)]
     for n in ns:
         assert orc.checksum_weight(n) == _weight(n), n
@@ -213,21 +215,33 @@ def test_checksum_weight_definition(orc):
 def test_checksum_detects_single_and_swapped_errors():
     # a wrong p_min changes p by an even delta with |delta| < 2^16, i.e. at
     # most 15 factors of 2: the change delta * w(n) is nonzero mod 2^64
-    # because w(n) has exactly (n/2) mod 32 <= 31 of them
+    # because w(n) has exactly floor(n/6) mod 32 <= 31 of them
     rng = np.random.default_rng(12)
     for n in [int(x) * 2 for x in rng.integers(2, 2**62, size=4000)] + list(range(4, 1 << 14, 2)):
-        assert _v2(_weight(n)) == (n // 2) % 32, n
-    # two n of one 256-wide stretch exchanging their p change the sum by
-    # (p1 - p2) (w1 - w2); w1 - w2 has at most 33 factors of 2 (n and n + 128
-    # with the same (n/2) mod 64), and p1 - p2 at most 15, so every such
-    # exchange is seen
+        assert _v2(_weight(n)) == (n // 6) % 32, n
+    # two n exchanging their p change the sum by (p1 - p2) (w1 - w2), and
+    # p1 - p2 has at most 15 factors of 2.  Within 16 stretches of 384 (16
+    # sets of 64 n of each class) w1 - w2 has at most 38 of them (the same
+    # place j in sets whose b differ by 32)...
     worst = 0
-    for base in (0, 10**12 - 2**36, 2**62, 2**63 - 256):
-        ws = [_weight(base + 2 * k) for k in range(128)]
-        for a in range(128):
-            for b in range(a + 1, 128):
+    for base in (0, 10**12 - 2**36, 2**62, 2**63 - 6144):
+        base -= base % 384
+        ws = [_weight(base + 2 * k) for k in range(3072)]
+        for a in range(0, 3072, 11):
+            for b in range(a + 1, 3072):
                 worst = max(worst, _v2(ws[a] - ws[b]))
-    assert worst == 33
+    assert worst == 38
+    # ...and for n closer than 8 million the b differ by less than 2^16, so
+    # w1 - w2 has at most 33 + 15 factors of 2: every such exchange is seen
+    for _ in range(20000):
+        n1 = int(rng.integers(2, 2**62)) * 2
+        n2 = n1 + 2 * int(rng.integers(1, 4_000_000))
+        if n2 >= 2**64:
+            continue
+        b1 = 3 * (n1 // 384) + (n1 % 6) // 2
+        b2 = 3 * (n2 // 384) + (n2 % 6) // 2
+        assert abs(b1 - b2) < 2**16
+        assert _v2(_weight(n1) - _weight(n2)) <= 48
 
 
 def test_config1_summary(orc):

@@ -244,13 +244,22 @@ gb_status gb_verify_many_noalloc(gb_ctx *ctx, const uint64_t *n, uint64_t *p, si
 /* The sieve alone (the segment bitset of subsection "Correct segmentation",
  * there built on the host; a GPU-built sieve is a direction of section
  * "Future work"): bit i of the output (LSB-first uint32 words) is 1 iff the
- * odd number w0 + 2i is prime, for 0 <= i < nbits, built by the same LDS tile
- * sieve the range calls use (wheel pattern, then strided marking of the odd
+ * odd number w0 + 2i is prime, for 0 <= i < nbits, built by the LDS tile
+ * sieve of the bulk form (wheel pattern, then strided marking of the odd
  * multiples of each sieving prime from max(p^2, w0)).  w0 is odd, w0 >= 1,
  * w0 + 2*nbits <= max_hi; nbits is a multiple of 64; bits is device memory of
  * nbits/32 words. */
 gb_status gb_sieve_window(gb_ctx *ctx, uint64_t w0, uint64_t nbits,
                           uint32_t *bits, void *stream);
+
+/* The sieve of the minimal-p range calls alone (the same segment bitset,
+ * in the layout those calls search): the numbers 6k + 1 and 6k + 5 in two
+ * planes.  Bit k of plane i (LSB-first uint32 words, plane i at word offset
+ * i*nk/32 of planes) is 1 iff 6(k0 + k) + c_i is prime, c = (1, 5), for
+ * 0 <= k < nk.  k0 and nk are multiples of 64, nk > 0, 6(k0 + nk) <= max_hi;
+ * planes is device memory of nk/16 words.  Status: GB_EINVAL for bad
+ * arguments, GB_ERANGE above max_hi, GB_EDEVICE on a HIP error. */
+gb_status gb_sieve_planes(gb_ctx *ctx, uint64_t k0, uint64_t nk, uint32_t *planes, void *stream);
 
 /* Goldbach partition counts (paper section "Future work": large-scale
  * counts c(n) of the partitions n = p + q into primes p <= q).  c(4) = 1;

@@ -244,6 +244,13 @@ class Verifier:
                                               _stream_ptr(stream)))
         return out
 
+    def sieve_planes(self, k0: int, nk: int, out, stream=None):
+        """The minimal-p search's sieve planes: row i of ``out`` (a torch int32
+        tensor of 2 x nk/32 words on the GPU) holds bit k = [6(k0+k) + c_i is
+        prime], c = (1, 5)."""
+        self._check(self._lib.gb_sieve_planes(self._h, k0, nk, out.data_ptr(), _stream_ptr(stream)))
+        return out
+
     def exhaustive_list(self):
         import numpy as np
         cnt = ctypes.c_size_t()

@@ -107,6 +107,7 @@ SIGNATURES = {
     "gb_verify_many": ([vp, vp, vp, ctypes.c_size_t, ctypes.c_int, vp], i32),
     "gb_verify_many_noalloc": ([vp, vp, vp, ctypes.c_size_t, vp], i32),
     "gb_sieve_window": ([vp, u64, u64, vp, vp], i32),
+    "gb_sieve_planes": ([vp, u64, u64, vp, vp], i32),
     "gb_partition_counts": ([vp, u64, u64, vp, ctypes.POINTER(PcResult), vp], i32),
     "gb_measure_peaks": ([vp, ctypes.POINTER(Peaks), vp], i32),
     "gb_verify_big": ([vp, vp, u32, ctypes.c_size_t, vp, vp], i32),

@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libgoldbach.so")
-SOURCES = ["gb_kernels.hip", "gb_host.hip", "gb_tune.hip", "gb_server.hip", "gb_pcount.hip", "gb_peaks.hip", "gb_big.hip", "gb_noalloc.hip"]
+SOURCES = ["gb_kernels.hip", "gb_class.hip", "gb_host.hip", "gb_tune.hip", "gb_server.hip", "gb_pcount.hip", "gb_peaks.hip", "gb_big.hip", "gb_noalloc.hip"]
 ARCH = os.environ.get("GB_OFFLOAD_ARCH", "gfx950")
 
 HIPCC_FLAGS = [

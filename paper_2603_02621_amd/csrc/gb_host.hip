@@ -78,7 +78,7 @@ uint32_t count_le(const std::vector<uint32_t> &v, uint64_t x)
 GbTileArgs base_args(gb_ctx *c, Workspace &ws)
 {
     GbTileArgs a{};
-    a.tile_n = c->tile_n;
+    a.tile_n = c->tile_n_odd;
     a.halo_bits = c->halo_bits;
     a.np_search = c->np_search;
     a.primes = c->d_primes;
@@ -94,6 +94,21 @@ GbTileArgs base_args(gb_ctx *c, Workspace &ws)
     a.list_count = ws.counters.p;
     a.list_cap = c->prm.max_unresolved;
     a.queue = ws.counters.p + 1;
+    a.cls = c->d_cls;
+    a.cls_words = c->cls_words;
+    a.np_cls = c->np_cls;
+    a.hk = c->hk;
+    a.sb_per_tile = c->sb_per_tile;
+    a.wheel6 = c->d_wheel6;
+    a.wheel6_len = c->wheel6_len;
+    a.wheel6_stride = c->wheel6_stride;
+    a.k6_first = c->k6_first;
+    a.k6_wg_end = c->k6_wg_end;
+    a.k6_wave_end = c->k6_wave_end;
+    a.k6_single = c->k6_single;
+    a.pmax_fast = c->prm.pmax;
+    a.prime6 = c->d_prime6;
+    a.n_prime6 = c->n_prime6;
     return a;
 }
 
@@ -140,12 +155,20 @@ gb_status enqueue_tiles(gb_ctx *c, Workspace &ws, const Job &j, hipStream_t st)
     a.rec_cap = ws.recs.cap;
     a.pmin = j.pmin_dev;
     const Plan &pl = *j.pl;
+    // the bulk form runs on consecutive odd numbers, the minimal-p search in
+    // the residue-class layout
+    const bool bulk = j.pmin_bits == 1;
+    if (!bulk) a.tile_n = c->tile_n;
+    auto launch = [&](const GbTileArgs &b, uint32_t grid, bool pers, hipStream_t ls) -> hipError_t {
+        return bulk ? gb_launch_tiles(b, grid, c->threads, c->lds, j.pmin_bits, pers, false, c->group_window, ls)
+                    : gb_launch_cls(b, grid, c->threads, c->lds6, j.pmin_bits, pers, false, ls);
+    };
     if (j.persistent) {
         a.win = ws.win.p;
         a.nwin = (uint32_t)pl.w.size();
         a.ntiles = pl.ntiles;
-        const uint64_t g = std::min<uint64_t>(pl.ntiles, (uint64_t)c->num_cu * c->occupancy);
-        GB_HIP(c, gb_launch_tiles(a, (uint32_t)g, c->threads, c->lds, j.pmin_bits, true, false, c->group_window, st));
+        const uint64_t g = std::min<uint64_t>(pl.ntiles, (uint64_t)c->num_cu * (bulk ? c->occupancy : c->occ6));
+        GB_HIP(c, launch(a, (uint32_t)g, true, st));
     } else {
         // One launch per segment.  A segment of S even n is S/T tiles, fewer
         // than the device holds at S = 2^24, so consecutive segments go to
@@ -163,10 +186,10 @@ gb_status enqueue_tiles(gb_ctx *c, Workspace &ws, const Job &j, hipStream_t st)
             b.win = ws.win.p + i;
             b.nwin = 1;
             b.tile0 = pl.w[i].tile_base;
-            const uint64_t nt = (pl.w[i].count + c->tile_n - 1) / c->tile_n;
+            const uint64_t nt = (pl.w[i].count + a.tile_n - 1) / a.tile_n;
             const int l = (int)(i % (size_t)lanes);
             hipStream_t ls = l == 0 ? st : c->plain_st[l - 1];
-            GB_HIP(c, gb_launch_tiles(b, (uint32_t)nt, c->threads, c->lds, j.pmin_bits, false, false, c->group_window, ls));
+            GB_HIP(c, launch(b, (uint32_t)nt, false, ls));
         }
         for (int l = 1; l < lanes; ++l) {
             GB_HIP(c, hipEventRecord(c->plain_join[l - 1], c->plain_st[l - 1]));
@@ -184,6 +207,11 @@ gb_status enqueue_rest(gb_ctx *c, Workspace &ws, const Job &j, hipStream_t st)
     m.slots = ws.slots.p;
     m.hist = ws.hist.p;
     m.hist_per_slot = j.hist_rows > 1 ? 1u : 0u;
+    // the class search leaves n_exhaustive to this phase: an n counts when
+    // no prime up to P_max gives it a partition (the class lists may stop
+    // below P_max when they do not fit the LDS)
+    m.count_exh = j.pmin_bits == 1 ? 0u : 1u;
+    m.pmax_fast = c->prm.pmax;
     GB_HIP(c, gb_launch_mr(m, mr_grid(c), st));
     GB_HIP(c, gb_launch_argmax(ws.slots.p, ws.recs.p, ws.counters.p + 2, ws.recs.cap, ws.list.p,
                                ws.counters.p, c->prm.max_unresolved, st));
@@ -315,24 +343,103 @@ gb_status build_tables(gb_ctx *c)
     GB_HIP(c, hipMalloc(&c->d_magic, c->ntab * 8));
     GB_HIP(c, hipMemcpy(c->d_primes, c->h_primes.data(), c->ntab * 4, hipMemcpyHostToDevice));
     GB_HIP(c, hipMemcpy(c->d_magic, magic.data(), c->ntab * 8, hipMemcpyHostToDevice));
+    // plane-sieve entries: p, the first k of plane 6k+1 that p divides, 1/p
+    c->n_prime6 = (uint32_t)count_le(c->h_primes, (1u << 27) - 1u);
+    std::vector<uint32_t> e6(4ull * c->n_prime6);
+    for (uint32_t i = 0; i < c->n_prime6; ++i) {
+        const uint32_t p = c->h_primes[i];
+        const double r = 1.0 / (double)p;
+        uint64_t rb;
+        std::memcpy(&rb, &r, 8);
+        e6[4ull * i] = p;
+        e6[4ull * i + 1] = (uint32_t)(((uint64_t)(p % 6u) * p - 1u) / 6u);   // 6 k + 1 = (p mod 6) p
+        e6[4ull * i + 2] = (uint32_t)rb;
+        e6[4ull * i + 3] = (uint32_t)(rb >> 32);
+    }
+    GB_HIP(c, hipMalloc(&c->d_prime6, e6.size() * 4 + 16));
+    GB_HIP(c, hipMemcpy(c->d_prime6, e6.data(), e6.size() * 4, hipMemcpyHostToDevice));
     return GB_OK;
 }
 
 void free_tables(gb_ctx *c)
 {
-    if (c->d_primes) (void)hipFree(c->d_primes);
-    if (c->d_magic) (void)hipFree(c->d_magic);
-    if (c->d_wheel) (void)hipFree(c->d_wheel);
+    for (void *q : {(void *)c->d_primes, (void *)c->d_magic, (void *)c->d_prime6, (void *)c->d_wheel,
+                    (void *)c->d_cls, (void *)c->d_wheel6})
+        if (q) (void)hipFree(q);
     c->d_primes = nullptr;
     c->d_magic = nullptr;
+    c->d_prime6 = nullptr;
     c->d_wheel = nullptr;
+    c->d_cls = nullptr;
+    c->d_wheel6 = nullptr;
 }
+
+namespace {
+
+// The class table of the search split by residue mod 6 for the first np
+// odd primes of the table (layout: GB_CLS_* in gb_internal.h), and its
+// plane halo hk.  Class h = a/2 lists the primes p with a - p not a
+// multiple of 3, in groups of four whose probes start within two rows of
+// the group's lowest start; a group that would be wider is closed early and
+// padded with copies of its last entry (a copy cannot hit an n twice).
+std::vector<uint32_t> class_table(const gb_ctx *c, uint32_t np, uint32_t &hk)
+{
+    std::vector<uint32_t> T(GB_CLS_HDR, 0u);
+    // q = n - p lies d stretches of 6 below n, in the plane of c = (a - p) mod 6
+    uint32_t dmax = 0;
+    for (uint32_t h = 0; h < 3; ++h)
+        for (uint32_t e = 0; e < np; ++e) {
+            const uint32_t p = c->h_primes[e], a = 2 * h, cc = (a + 6 - p % 6) % 6;
+            if (cc == 1 || cc == 5) dmax = std::max(dmax, (p + cc - a) / 6);
+        }
+    hk = std::max<uint32_t>(64, (dmax + 63) / 64 * 64);
+    std::vector<uint32_t> rec;
+    for (uint32_t h = 0; h < 3; ++h) {
+        struct Ent { uint32_t sb, plane, g; };
+        std::vector<Ent> ent;
+        for (uint32_t e = 0; e < np; ++e) {
+            const uint32_t p = c->h_primes[e], a = 2 * h, cc = (a + 6 - p % 6) % 6;
+            if (cc != 1 && cc != 5) continue;
+            ent.push_back({hk - (p + cc - a) / 6, cc == 5 ? 1u : 0u, 65536u - (p + 1) / 2});
+        }
+        std::vector<std::vector<Ent>> groups;
+        for (size_t e = 0; e < ent.size();) {
+            std::vector<Ent> gr{ent[e]};
+            size_t f = e + 1;
+            // start bits fall with p: the first entry has the highest row
+            while (f < ent.size() && gr.size() < 4 && ent[e].sb / 32 - ent[f].sb / 32 <= 1) gr.push_back(ent[f++]);
+            while (gr.size() < 4) gr.push_back(gr.back());
+            groups.push_back(gr);
+            e = f;
+        }
+        const uint32_t real = (uint32_t)groups.size();
+        for (int k = 0; k < 2 && real; ++k) groups.push_back(std::vector<Ent>(4, groups[real - 1][3]));
+        T[3 * h] = (uint32_t)rec.size() * 4u;
+        T[3 * h + 1] = real;
+        T[3 * h + 2] = T[3 * h] + 48u * real;
+        for (const auto &gr : groups) {
+            const uint32_t R = gr[3].sb / 32;   // the group's lowest row
+            uint32_t grp[12] = {};
+            for (uint32_t u = 0; u < 4; ++u) {
+                const Ent &en = gr[u];
+                grp[u] = ((8u * R) << 16) | (en.plane << 6) | ((en.sb / 32 - R) << 5) | (en.sb & 31u);
+                grp[4 + u] = en.g;
+            }
+            rec.insert(rec.end(), grp, grp + 12);
+        }
+    }
+    rec.resize(rec.size() + 3 * 12, 0u);   // what a lane of an empty last list reads past the end
+    T.insert(T.end(), rec.begin(), rec.end());
+    return T;
+}
+
+}  // namespace
 
 // Launch geometry and wheel pattern for the current parameters.
 gb_status setup_geometry(gb_ctx *c)
 {
     const gb_params &p = c->prm;
-    c->tile_n = 1u << p.tile_log2;
+    c->tile_n_odd = 1u << p.tile_log2;
     c->threads = p.wg_threads;
     c->np_search = count_le(c->h_primes, p.pmax);
     // The search reads each group of four probes' windows at once when, in
@@ -352,7 +459,7 @@ gb_status setup_geometry(gb_ctx *c)
     const uint32_t need = (p.pmax + 1) / 2;
     c->halo_bits = std::max<uint32_t>(64, (need + 63) / 64 * 64);
     c->k_first = count_le(c->h_primes, p.wheel_max);
-    const uint32_t nbits = c->tile_n + c->halo_bits;
+    const uint32_t nbits = c->tile_n_odd + c->halo_bits;
     // Marking classes by hits per tile, H = nbits/p.  A class pays a fixed
     // cost per prime (first strike, loop set-up) in every thread it uses:
     // - whole workgroup for p < nbits/(32 threads): H/threads >= 32 strides
@@ -363,7 +470,7 @@ gb_status setup_geometry(gb_ctx *c)
     // - one lane per prime above.
     c->k_wg_end = std::max(c->k_first, count_le(c->h_primes, nbits / (32 * c->threads)));
     c->k_wave_end = std::max(c->k_wg_end, count_le(c->h_primes, nbits / 256));
-    c->lds = gb_tile_lds_bytes(c->tile_n, c->halo_bits, c->np_search, c->k_wave_end - c->k_first);
+    c->lds = gb_tile_lds_bytes(c->tile_n_odd, c->halo_bits, c->np_search, c->k_wave_end - c->k_first);
     if (c->lds > 160 * 1024)
         return fail(c, GB_EINVAL, "tile does not fit in LDS (" + std::to_string(c->lds) +
                                       " bytes); lower tile_log2, wg_threads or pmax");
@@ -392,21 +499,78 @@ gb_status setup_geometry(gb_ctx *c)
     GB_HIP(c, hipMalloc(&c->d_wheel, pat.size() * 4));
     GB_HIP(c, hipMemcpy(c->d_wheel, pat.data(), pat.size() * 4, hipMemcpyHostToDevice));
     c->wheel_len = L;
+
+    // ---- search split by residue mod 6: stretches, class lists, planes ----
+    c->sb_per_tile = std::max<uint32_t>(1, (1u << p.tile_log2) / 192u);
+    c->tile_n = 192u * c->sb_per_tile;
+    c->k6_first = count_le(c->h_primes, std::max<uint32_t>(3, p.wheel_max));
+    // the class lists hold every odd prime <= P_max when they fit the LDS
+    // beside the planes, else the longest prefix that does; the exhaustive
+    // phase takes the n they leave from the next prime on
+    uint32_t np = c->np_search;
+    std::vector<uint32_t> T;
+    for (;;) {
+        T = class_table(c, np, c->hk);
+        const uint32_t Lk = c->hk + 64 * c->sb_per_tile;
+        // strikes per thread and plane: workgroup class Lk / ((threads/2) p),
+        // wave class Lk / (32 p), both at least two
+        c->k6_wg_end = std::max(c->k6_first, count_le(c->h_primes, Lk / c->threads));
+        c->k6_wave_end = std::max(c->k6_wg_end, count_le(c->h_primes, Lk / 64));
+        c->k6_single = std::max(c->k6_wave_end, count_le(c->h_primes, Lk - 1));
+        c->lds6 = gb_cls_lds_bytes(c->sb_per_tile, c->hk, (uint32_t)T.size(), c->k6_wg_end - c->k6_first);
+        if (c->lds6 <= 160 * 1024 || np == 0) break;
+        np -= std::max<uint32_t>(1, np / 16);
+    }
+    if (c->lds6 > 160 * 1024)
+        return fail(c, GB_EINVAL, "tile does not fit in LDS (" + std::to_string(c->lds6) + " bytes); lower tile_log2");
+    c->np_cls = np;
+    c->cls_words = (uint32_t)T.size();
+    if (c->d_cls) (void)hipFree(c->d_cls);
+    c->d_cls = nullptr;
+    GB_HIP(c, hipMalloc(&c->d_cls, T.size() * 4));
+    GB_HIP(c, hipMemcpy(c->d_cls, T.data(), T.size() * 4, hipMemcpyHostToDevice));
+    GB_HIP(c, gb_cls_prepare(c->threads, c->lds6));
+    occ = 0;
+    GB_HIP(c, gb_cls_occupancy(c->threads, c->lds6, &occ));
+    c->occ6 = std::max(occ, 1);
+    // plane i (c = 1, 5): bit k set iff 6k + c is prime to every wheel prime
+    // 5 .. wheel_max (period the product of those primes)
+    uint32_t P = 1;
+    for (uint32_t q : wp)
+        if (q >= 5 && q <= p.wheel_max) P *= q;
+    const uint32_t stride = (P + 64 + 31) / 32 + 1;
+    std::vector<uint32_t> pat6(2ull * stride, 0u);
+    for (uint32_t i = 0; i < 2; ++i)
+        for (uint32_t k = 0; k < P + 64; ++k) {
+            const uint64_t v = 6ull * (k % P) + (i ? 5 : 1);
+            bool ok = true;
+            for (uint32_t q : wp)
+                if (q >= 5 && q <= p.wheel_max && v % q == 0) ok = false;
+            if (ok) pat6[i * stride + (k >> 5)] |= 1u << (k & 31);
+        }
+    if (c->d_wheel6) (void)hipFree(c->d_wheel6);
+    c->d_wheel6 = nullptr;
+    GB_HIP(c, hipMalloc(&c->d_wheel6, pat6.size() * 4));
+    GB_HIP(c, hipMemcpy(c->d_wheel6, pat6.data(), pat6.size() * 4, hipMemcpyHostToDevice));
+    c->wheel6_len = P;
+    c->wheel6_stride = stride;
     c->ws.drop_graphs();
     return GB_OK;
 }
 
 // Split windows into tiles and fill the derived window fields; GB_ERANGE
-// when a window reaches past the resident sieving primes.  With `align`, each
-// window's first n moves down to a multiple of 128, the n added in front
-// counted in `lead` (the search kernels mask them).
-gb_status plan_windows(gb_ctx *c, Plan &pl, bool align)
+// when a window reaches past the resident sieving primes.  For the search
+// kernels each window's first n moves down to a multiple of 384 (the
+// search split by residue mod 6) or 128 (bulk), the n added in front
+// counted in `lead` (the kernels mask them).
+gb_status plan_windows(gb_ctx *c, Plan &pl, PlanKind kind)
 {
-    const uint64_t T = c->tile_n;
+    const uint64_t T = kind == kPlanClass ? c->tile_n : c->tile_n_odd;
+    const uint64_t A = kind == kPlanClass ? 384 : 128;
     uint64_t tb = 0, off = 0;
     for (auto &w : pl.w) {
         const uint64_t user_count = w.count;
-        w.lead = (align && user_count) ? (uint32_t)((w.first_n >> 1) & 63u) : 0u;
+        w.lead = (kind != kPlanSieve && user_count) ? (uint32_t)((w.first_n % A) / 2) : 0u;
         w.pad = 0;
         w.first_n -= 2ull * w.lead;
         w.count += w.lead;
@@ -485,7 +649,7 @@ gb_status enqueue_sieve(gb_ctx *c, Workspace &ws, uint64_t w0, uint64_t nbits, u
     pl.w[0].first_n = w0 - 1 + 2ull * c->halo_bits;  // makes the tile window start at w0
     pl.w[0].count = nbits;
     pl.w[0].slot = 0;
-    gb_status stt = plan_windows(c, pl, false);
+    gb_status stt = plan_windows(c, pl, kPlanSieve);
     if (stt != GB_OK) return stt;
     stt = ensure_workspace(c, ws, pl, 1, 1);
     if (stt != GB_OK) return stt;
@@ -496,6 +660,31 @@ gb_status enqueue_sieve(gb_ctx *c, Workspace &ws, uint64_t w0, uint64_t nbits, u
     a.tile0 = 0;
     a.sieve_out = bits;
     GB_HIP(c, gb_launch_tiles(a, (uint32_t)pl.ntiles, c->threads, c->lds, 0, false, true, false, st));
+    return GB_OK;
+}
+
+// The sieve of the search alone: planes over k in [k0, k0 + nk), as the
+// tiles of one window of 3 nk even n from 6 k0 (k0, nk multiples of 64).
+gb_status enqueue_sieve6(gb_ctx *c, Workspace &ws, uint64_t k0, uint64_t nk, uint32_t *planes, hipStream_t st)
+{
+    Plan pl;
+    pl.w.resize(1);
+    pl.w[0].first_n = 6ull * k0;
+    pl.w[0].count = 3ull * nk;
+    pl.w[0].slot = 0;
+    gb_status stt = plan_windows(c, pl, kPlanClass);
+    if (stt != GB_OK) return stt;
+    stt = ensure_workspace(c, ws, pl, 1, 1);
+    if (stt != GB_OK) return stt;
+    GB_HIP(c, hipMemcpyAsync(ws.win.p, pl.w.data(), sizeof(GbWindow), hipMemcpyHostToDevice, st));
+    GbTileArgs a = base_args(c, ws);
+    a.tile_n = c->tile_n;
+    a.win = ws.win.p;
+    a.nwin = 1;
+    a.tile0 = 0;
+    a.sieve_out = planes;
+    a.sieve_stride = nk / 32;
+    GB_HIP(c, gb_launch_cls(a, (uint32_t)pl.ntiles, c->threads, c->lds6, 0, false, true, st));
     return GB_OK;
 }
 
@@ -569,7 +758,7 @@ gb_status run_range(gb_ctx *c, uint64_t lo, uint64_t hi, gb_result *res, void *s
         pl.w[s].count = std::min(S, C - S * s);
         pl.w[s].slot = (uint32_t)s;
     }
-    gb_status stt = plan_windows(c, pl);
+    gb_status stt = plan_windows(c, pl, bulk ? kPlanOdd : kPlanClass);
     if (stt != GB_OK) return stt;
     const size_t hist_rows = res->seg_hist ? nseg : 1;
     stt = ensure_workspace(c, ws, pl, nseg, hist_rows);
@@ -849,6 +1038,20 @@ gb_status gb_sieve_window(gb_ctx *c, uint64_t w0, uint64_t nbits, uint32_t *bits
     const uint64_t top = w0 + 2 * nbits;
     if (top < w0 || top > c->prm.max_hi) return fail(c, GB_ERANGE, "window above the context's max_hi");
     gb_status stt = enqueue_sieve(c, c->ws, w0, nbits, bits, st);
+    if (stt != GB_OK) return stt;
+    GB_HIP(c, hipStreamSynchronize(st));
+    return GB_OK;
+}
+
+gb_status gb_sieve_planes(gb_ctx *c, uint64_t k0, uint64_t nk, uint32_t *planes, void *stream)
+{
+    if (!c || !planes) return fail(c, GB_EINVAL, "null argument");
+    if ((k0 & 63) || nk == 0 || (nk & 63)) return fail(c, GB_EINVAL, "k0 and nk must be multiples of 64, nk > 0");
+    if (hipSetDevice(c->prm.device) != hipSuccess) return fail(c, GB_EDEVICE, "hipSetDevice failed");
+    if (k0 > c->prm.max_hi / 6 || nk > c->prm.max_hi / 6 - k0)
+        return fail(c, GB_ERANGE, "planes above the context's max_hi");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    gb_status stt = enqueue_sieve6(c, c->ws, k0, nk, planes, st);
     if (stt != GB_OK) return stt;
     GB_HIP(c, hipStreamSynchronize(st));
     return GB_OK;

@@ -76,7 +76,40 @@ struct GbTileArgs {
     unsigned long long list_cap;
     unsigned long long *queue; // persistent work counter
     uint32_t *sieve_out;       // sieve-only mode: bitset dump
+    // the search split by residue mod 6 (gb_class.hip): tile_n = 192 sb_per_tile
+    const uint32_t *cls;       // class headers, sieve tables and probe records (GB_CLS_*)
+    uint32_t cls_words;
+    uint32_t np_cls;           // odd primes on the class lists (the first np_cls of the table)
+    uint32_t hk;               // plane bits below a tile's first stretch (a multiple of 64)
+    uint32_t sb_per_tile;      // stretches of 384 integers per full tile
+    const uint32_t *wheel6;    // two plane patterns of period wheel6_len, wheel6_stride words each
+    uint32_t wheel6_len;
+    uint32_t wheel6_stride;
+    uint32_t k6_first;         // first prime index above the wheel
+    uint32_t k6_wg_end;        // [k6_first, k6_wg_end): whole-workgroup marking
+    uint32_t k6_wave_end;      // [k6_wg_end, k6_wave_end): one wave per prime
+    uint32_t k6_single;        // from here on p >= plane bits of a full tile: one strike per plane at most
+    uint64_t sieve_stride;     // plane dump: words per plane in sieve_out
+    uint32_t pmax_fast;        // P_max: n with a larger p_min count as exhaustive
+    const uint4 *prime6;       // per odd prime of the table below 2^27: GB_PRIME6 entry
+    uint32_t n_prime6;         // entries of prime6 (the first n_prime6 odd primes)
 };
+
+// GbTileArgs::prime6 entry of the odd prime p: x = p, y = the least k >= 0
+// with p | 6 k + 1, (w:z) = the bits of the double nearest 1/p.  The least
+// k >= 0 with p | 6 k + 5 is then p - 1 - y.
+
+// Layout of GbTileArgs::cls (32-bit words).  Class h = a/2 (a = 0, 2, 4):
+// words 3h, 3h+1, 3h+2 = byte offset of its first probe record group from
+// the records, number of its groups with real entries, byte offset of the
+// end of the last of them (two more groups of copies follow).  Records from
+// GB_CLS_HDR: groups of four entries, 12 words each (four packed probe
+// words, four g = 2^16 - (p+1)/2, four hit counts).  A packed probe word
+// holds the funnel shift in bits 4..0, the probe's row within the group's
+// window in bit 5, its plane in bit 6 and, in bits 31..16, the byte offset
+// of the group's window (rows R .. R+3 of both planes) from the block's
+// first plane row.
+#define GB_CLS_HDR 12u
 
 struct GbMrArgs {
     GbExh *list;
@@ -90,6 +123,8 @@ struct GbMrArgs {
     GbSlot *slots;               // nullable (queries)
     unsigned long long *hist;
     uint32_t hist_per_slot;
+    uint32_t count_exh;          // count n_exhaustive here: an n whose p is 0 or above pmax_fast
+    uint64_t pmax_fast;
 };
 
 // Kernel launchers (gb_kernels.hip).
@@ -104,6 +139,12 @@ hipError_t gb_tile_occupancy(uint32_t threads, size_t lds_bytes, bool group_wind
 size_t gb_tile_lds_bytes(uint32_t tile_n, uint32_t halo_bits, uint32_t np_search,
                          uint32_t n_off);
 hipError_t gb_launch_mr(const GbMrArgs &a, uint32_t grid, hipStream_t st);
+// The kernel of the search split by residue mod 6 (gb_class.hip).
+size_t gb_cls_lds_bytes(uint32_t sb_per_tile, uint32_t hk, uint32_t cls_words, uint32_t n_wg_primes);
+hipError_t gb_cls_prepare(uint32_t threads, size_t lds_bytes);
+hipError_t gb_cls_occupancy(uint32_t threads, size_t lds_bytes, int *blocks_per_cu);
+hipError_t gb_launch_cls(const GbTileArgs &a, uint32_t grid, uint32_t threads, size_t lds_bytes, int pmin_bits,
+                         bool persistent, bool sieve_only, hipStream_t st);
 hipError_t gb_launch_argmax(GbSlot *slots, const GbTileRec *recs, const unsigned long long *rec_count,
                             unsigned long long rec_cap, const GbExh *list,
                             const unsigned long long *list_count, unsigned long long list_cap,

@@ -30,6 +30,7 @@
 #include <type_traits>
 
 #include "gb_internal.h"
+#include "gb_device.h"
 
 namespace {
 
@@ -78,14 +79,6 @@ __device__ __forceinline__ uint32_t first_index_rcp(double w0d, uint32_t p)
     return (uint32_t)d >> 1;
 }
 
-// p * (bits 15..0 of x) + acc, p < 2^16, in one v_mad_u32_u16.
-__device__ __forceinline__ uint32_t mad_lo16(uint32_t p, uint32_t x, uint32_t acc)
-{
-    uint32_t d;
-    asm("v_mad_u32_u16 %0, %1, %2, %3" : "=v"(d) : "v"(p), "v"(x), "v"(acc));
-    return d;
-}
-
 // Bit 16 of x copied to all 32 bits (v_bfe_i32).
 __device__ __forceinline__ uint32_t sext_bit16(uint32_t x)
 {
@@ -102,19 +95,6 @@ __device__ __forceinline__ uint32_t bitsel(uint32_t m, uint32_t a, uint32_t b)
     return d;
 }
 
-typedef __attribute__((address_space(3))) uint32_t lds_u32;
-typedef __attribute__((address_space(3))) unsigned long long lds_u64;
-typedef uint32_t v4u32 __attribute__((ext_vector_type(4)));
-typedef __attribute__((address_space(3))) v4u32 lds_v4;
-
-// LDS byte address bw + bits 31..16 of the packed prime word x.
-__device__ __forceinline__ const lds_u32 *probe_addr(uint32_t x, uint32_t bw)
-{
-    uint32_t d;
-    asm("v_mad_u32_u16 %0, 1, %1, %2 op_sel:[0,1,0,0]" : "=v"(d) : "v"(x), "v"(bw));
-    return reinterpret_cast<const lds_u32 *>(static_cast<uintptr_t>(d));
-}
-
 // Clear the bits of m's zeros in the LDS word at byte address addr.
 __device__ __forceinline__ void lds_and(uint32_t addr, uint32_t m)
 {
@@ -128,27 +108,24 @@ __device__ __forceinline__ void lds_and(uint32_t addr, uint32_t m)
 // of the probe's first word below the block's base word, biased to be >= 0.
 constexpr uint32_t PX_BIAS = 4096;   // 4 ceil(h/32) <= 4096 for h <= 32768
 
-// Checksum weight of an even n: 2^33 floor(n/128) + (2c+1) 2^i, where
-// (n/2) mod 64 = 32c + i.  The checksum is the sum of weight * p_min mod
-// 2^64; it is not in the paper, and this form is the one the bit-sliced
-// search can accumulate with two 32x32 -> 64-bit multiply-adds per hit.
+// Checksum weight of an even n: 2^33 b + (2c+1) 2^i with
+// b = 3 floor(n/384) + (n mod 6)/2 (the index of n's block of 64 n of one
+// class mod 6 in the minimal-p search) and floor(n/6) mod 64 = 32c + i (n's
+// bit in it).  The checksum is the sum of weight * p_min mod 2^64; it is
+// not in the paper, and this form is the one the bit-sliced search
+// accumulates with two 32x32 -> 64-bit multiply-adds per hit.
 __device__ __forceinline__ unsigned long long checksum_weight(unsigned long long n)
 {
-    const uint32_t j = (uint32_t)(n >> 1) & 63u;
-    return ((n >> 7) << 33) + ((unsigned long long)(2u * (j >> 5) + 1u) << (j & 31u));
+    const unsigned long long k = n / 6ull;
+    const uint32_t j = (uint32_t)k & 63u;
+    const unsigned long long b = 3ull * (k >> 6) + (n - 6ull * k) / 2ull;
+    return (b << 33) + ((unsigned long long)(2u * (j >> 5) + 1u) << (j & 31u));
 }
 
 __device__ __forceinline__ bool is_wheel_prime(long long v, uint32_t wmax)
 {
     return v <= (long long)wmax &&
            (v == 3 || v == 5 || v == 7 || v == 11 || v == 13 || v == 17 || v == 19);
-}
-
-template <int PB>
-__device__ __forceinline__ void store_p(void *out, unsigned long long idx, uint32_t p)
-{
-    if constexpr (PB == 16) static_cast<uint16_t *>(out)[idx] = (uint16_t)p;
-    if constexpr (PB == 32) static_cast<uint32_t *>(out)[idx] = p;
 }
 
 // Word offsets of prime i's packed word, g and hit count in TileLds::pr.
@@ -197,14 +174,6 @@ __device__ __forceinline__ TileLds carve(uint32_t *smem, const GbTileArgs &a)
     return L;
 }
 
-// The histogram row a workgroup's LDS hit counts belong to, and the n
-// counted into them since they were last flushed (the same in every thread).
-constexpr uint32_t kNoRow = 0xFFFFFFFFu;
-struct HistCarry {
-    uint32_t row = kNoRow;
-    unsigned long long n = 0;
-};
-
 // Fast-path prime list in LDS, once per workgroup: odd primes p <= P_max in
 // groups of four (packed words, g, hit counts), padded with copies of the last
 // prime through the end of the second group after the last prime's group (a
@@ -230,33 +199,6 @@ __device__ void setup_primes(const GbTileArgs &a, const TileLds &L)
         L.pr[pr_gl(i)] = VERIFY ? (65536u - h) << 16 : 65536u - h;
         L.pr[pr_lh(i)] = 0;
     }
-}
-
-// The slot summaries a workgroup carries from tile to tile (thread 0, in
-// LDS): one set of slot atomics and one argmax record per run of tiles of
-// one slot instead of per tile.
-constexpr unsigned long long kNoSlot = ~0ull;
-enum { CY_COUNT, CY_SUM, CY_EXH, CY_ARGN, CY_SLOT, CY_MAXP };
-
-__device__ void flush_slot(const GbTileArgs &a, unsigned long long *C)
-{
-    if (C[CY_SLOT] == kNoSlot) return;
-    GbSlot *S = a.slots + C[CY_SLOT];
-    atomicAdd(&S->count, C[CY_COUNT]);
-    if (C[CY_SUM]) atomicAdd(&S->checksum, C[CY_SUM]);
-    if (C[CY_EXH]) atomicAdd(&S->n_exhaustive, C[CY_EXH]);
-    if (C[CY_MAXP]) {
-        atomicMax(&S->max_p, C[CY_MAXP]);
-        const unsigned long long e = atomicAdd(a.rec_count, 1ull);
-        if (e < a.rec_cap) {
-            GbTileRec r;
-            r.argmax_n = C[CY_ARGN];
-            r.max_p = (uint32_t)C[CY_MAXP];
-            r.slot = (uint32_t)C[CY_SLOT];
-            a.recs[e] = r;
-        }
-    }
-    C[CY_SLOT] = kNoSlot;
 }
 
 // Add the workgroup's per-prime hit counts to histogram row `row` and clear
@@ -1037,6 +979,7 @@ __global__ __launch_bounds__(256) void k_mr(GbMrArgs a)
                     atomicAdd(&S->n_failed, 1ull);
                     atomicMin(&S->first_failed_n, n);
                 }
+                if (a.count_exh && (found == 0ull || found > a.pmax_fast)) atomicAdd(&S->n_exhaustive, 1ull);
             }
         }
     }

@@ -140,12 +140,28 @@ struct gb_ctx {
     std::vector<uint32_t> h_primes;  // odd primes 3, 5, 7, ...
     uint32_t *d_primes = nullptr;
     unsigned long long *d_magic = nullptr;
+    uint4 *d_prime6 = nullptr;       // sieve entries of the odd primes below 2^27
+    uint32_t n_prime6 = 0;
     uint64_t ntab = 0;
     uint64_t table_limit = 0;        // every odd prime <= table_limit is in the table
+    uint32_t threads = 0;
+    // minimal-p search split by residue mod 6 (gb_class.hip): tiles of
+    // tile_n = 192 sb_per_tile even n, windows aligned to 384
+    uint32_t tile_n = 0, sb_per_tile = 0, hk = 0;
+    uint32_t np_cls = 0;             // odd primes on the class probe lists
+    uint32_t *d_cls = nullptr;       // class headers, sieve tables, probe records
+    uint32_t cls_words = 0;
+    uint32_t *d_wheel6 = nullptr;    // two plane patterns
+    uint32_t wheel6_len = 0, wheel6_stride = 0;
+    uint32_t k6_first = 0, k6_wg_end = 0, k6_wave_end = 0, k6_single = 0;
+    size_t lds6 = 0;
+    int occ6 = 1;
+    // bulk verification and the sieve dump, consecutive odd numbers
+    // (gb_kernels.hip): tiles of tile_n_odd even n, windows aligned to 128
+    uint32_t tile_n_odd = 0;
     uint32_t np_search = 0, k_first = 0, halo_bits = 0;
     uint32_t *d_wheel = nullptr;
     uint32_t wheel_len = 0;
-    uint32_t tile_n = 0, threads = 0;
     uint32_t k_wg_end = 0, k_wave_end = 0;
     size_t lds = 0;
     bool group_window = false;       // search form: one window read per group of four probes
@@ -170,8 +186,11 @@ gb_status apply_params(gb_ctx *c, const gb_params *in);
 gb_status setup_geometry(gb_ctx *c);
 gb_status build_tables(gb_ctx *c);
 void free_tables(gb_ctx *c);
-// align = true for the search kernels, false for the sieve dump
-gb_status plan_windows(gb_ctx *c, Plan &pl, bool align = true);
+// How a plan splits windows: the minimal-p search (tiles of tile_n, first
+// n moved down to a multiple of 384), the bulk form (tiles of
+// tile_n_odd, multiples of 128) or the odd-number sieve dump (no move).
+enum PlanKind { kPlanClass, kPlanOdd, kPlanSieve };
+gb_status plan_windows(gb_ctx *c, Plan &pl, PlanKind kind = kPlanClass);
 gb_status ensure_workspace(gb_ctx *c, Workspace &ws, const Plan &pl, size_t nslots, size_t hist_rows);
 // init + tiles + exhaustive phase + argmax + summary copies, on `st`,
 // with ws.evt0/evt1 around the tile launches; with use_graph each phase is a

@@ -112,7 +112,9 @@ uint64_t pow2_at_least(uint64_t x)
 uint64_t request_bytes(const gb_server *s, const gb_request &r)
 {
     if (r.kind == GB_REQ_ONE) return 48;
-    const uint64_t tiles = (r.len + s->tile_n - 1) / s->tile_n;
+    // the planner moves a range's first n down to a multiple of 384 (up to
+    // 191 n in front)
+    const uint64_t tiles = (r.len + 191 + s->tile_n - 1) / s->tile_n;
     return 64 + 40 + 16 * tiles + (r.pmin ? 2 * r.len : 0);
 }
 

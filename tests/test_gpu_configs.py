@@ -117,10 +117,12 @@ def test_config4_bench_configuration(gpu, orc):
             sum_p += int(p.sum(dtype=torch.int64))
             pmax = max(pmax, int(p.max()))
             n = 2 * (torch.arange(a, a + p.numel(), device="cuda", dtype=torch.int64) + lo // 2)
-            j = (n >> 1) & 63
-            w = ((n >> 7) << 33) + ((2 * (j >> 5) + 1) << (j & 31))
+            k = torch.div(n, 6, rounding_mode="floor")
+            j = k & 63
+            b = 3 * (k >> 6) + ((n - 6 * k) >> 1)
+            w = (b << 33) + ((2 * (j >> 5) + 1) << (j & 31))
             cs += (w * p.to(torch.int64)).sum()   # int64 arithmetic wraps mod 2^64
-            del p, n, j, w
+            del p, n, k, j, b, w
         assert sum_p == sum_p_hist
         assert int(cs) % 2**64 == batched["checksum"]
         assert pmax == batched["max_p"]

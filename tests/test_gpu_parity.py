@@ -80,6 +80,34 @@ def test_sieve_window_vs_oracle(orc, w0, nbits):
     v.close()
 
 
+@pytest.mark.parametrize("k0,nk,kw", [
+    (0, 64 * 300, {}),                                      # 1, the wheel primes, small squares
+    (10**12 // 6 // 64 * 64 - 64 * 9000, 64 * 11000, {}),  # near 10^12, several tiles, ragged
+    ((1_000_003**2 // 6) // 64 * 64 - 64 * 3000, 64 * 7000, dict(tile_log2=16, wheel_max=19)),
+    ((1 << 50) // 6 // 64 * 64 - 64 * 6000, 64 * 5500, dict(tile_log2=20, wheel_max=7, wg_threads=256)),
+    (((1 << 53) // 6) // 64 * 64 - 64 * 3000, 64 * 6000, dict(max_hi=1 << 54)),   # both sides of 2^53
+])
+def test_sieve_planes_vs_oracle(orc, k0, nk, kw):
+    # the planes of the minimal-p search: bit k of plane i is 6 (k0 + k) + c_i
+    # prime, c = (1, 5); the oracle's odd-number sieve picked apart
+    _gpu()
+    from paper_2603_02621_amd import Verifier
+    kw = dict(kw)
+    kw.setdefault("max_hi", 1 << 50)
+    v = Verifier(0, **kw)
+    out = torch.zeros(2 * nk // 32, dtype=torch.int32, device="cuda")
+    v.sieve_planes(k0, nk, out)
+    torch.cuda.synchronize()
+    got = _unpack(out, 2 * nk).reshape(2, nk)
+    w0 = 6 * k0 + 1
+    ref_odd = orc.odd_primality(w0, 3 * nk)
+    for i, c in enumerate((1, 5)):
+        ref = ref_odd[3 * np.arange(nk) + (c - 1) // 2]
+        bad = np.nonzero(got[i] != ref)[0]
+        assert bad.size == 0, [(int(6 * (k0 + k) + c), int(got[i][k]), int(ref[k])) for k in bad[:10]]
+    v.close()
+
+
 # --------------------------------------------------------------------------
 # ranges
 # --------------------------------------------------------------------------

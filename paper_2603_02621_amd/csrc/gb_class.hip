@@ -184,17 +184,28 @@ __device__ __forceinline__ uint32_t strikes_clamped(const GbTileArgs &a, bool fa
 }
 
 // Hit counts of the workgroup's probe records into histogram row `row`, then
-// cleared (threads stride over every record of every class).
-__device__ void flush_hist_cls(const GbTileArgs &a, const ClsLds &L, uint32_t row)
+// cleared (threads stride over every record of every class).  The first
+// flush of a persistent workgroup stores them, zeros included, as its own
+// row of a.wg_hist (plain coalesced stores: 4 bytes per record instead of a
+// device-scope atomic per record with hits); later ones, and every flush
+// without wg_hist, add them to the histogram with 64-bit atomics.
+__device__ void flush_hist_cls(const GbTileArgs &a, const ClsLds &L, uint32_t row, HistCarry &hc)
 {
     unsigned long long *hist = a.hist + (unsigned long long)row * GB_HIST_BINS_I;
     uint32_t *rec = L.cls + GB_CLS_HDR;
+    const bool store = a.wg_hist != nullptr && !hc.stored;
+    uint32_t *own = store ? a.wg_hist + (unsigned long long)blockIdx.x * a.wg_hist_stride : nullptr;
+    if (store && threadIdx.x == 0) own[0] = row;
+    uint32_t r0 = 1;   // record index in class order, after the row word
     for (uint32_t h = 0; h < 3u; ++h) {
         const uint32_t first = L.cls[3u * h] / 4u, groups = L.cls[3u * h + 1u];
         for (uint32_t e = threadIdx.x; e < 4u * groups; e += blockDim.x) {
             const uint32_t wo = first + 12u * (e >> 2) + (e & 3u);
             const uint32_t c = rec[wo + 8u];
-            if (c) {
+            if (store) {
+                own[r0 + e] = c;
+                rec[wo + 8u] = 0u;
+            } else if (c) {
                 // the prime from g = 2^16 - (p+1)/2, its index by bisection
                 const uint32_t p = 131071u - 2u * rec[wo + 4u];
                 uint32_t lo = 0, hi = a.np_cls;
@@ -206,7 +217,9 @@ __device__ void flush_hist_cls(const GbTileArgs &a, const ClsLds &L, uint32_t ro
                 rec[wo + 8u] = 0u;
             }
         }
+        r0 += 4u * groups;
     }
+    if (store) hc.stored = true;
 }
 
 template <int NT, int PB, bool SIEVE_ONLY>
@@ -255,7 +268,7 @@ __device__ void cls_tile(const GbTileArgs &a, unsigned long long g, const ClsLds
         if (tid == 0) *L.next = NT;
         const uint32_t row = a.hist_per_slot ? W.slot : 0u;
         if (row != hc.row || hc.n + cnt > 0x7FFFFFFFull) {
-            if (hc.row != kNoRow) flush_hist_cls(a, L, hc.row);
+            if (hc.row != kNoRow) flush_hist_cls(a, L, hc.row, hc);
             hc.row = row;
             hc.n = 0;
         }
@@ -745,8 +758,13 @@ __global__ __launch_bounds__(NT) void k_cls(GbTileArgs a)
     for (uint32_t i = threadIdx.x; i < a.cls_words; i += NT) L.cls[i] = a.cls[i];
     if (threadIdx.x == 0) L.carry[CY_SLOT] = kNoSlot;
     if constexpr (PERS) {
+        // the workgroup's share of the first static_tiles tiles, then the
+        // queue (one device-scope atomic per tile taken from it)
+        __syncthreads();
+        for (unsigned long long g = blockIdx.x; g < a.static_tiles && g < a.ntiles; g += gridDim.x)
+            cls_tile<NT, PB, SIEVE_ONLY>(a, g, L, hc);
         for (;;) {
-            if (threadIdx.x == 0) *L.tile = atomicAdd(a.queue, 1ull);
+            if (threadIdx.x == 0) *L.tile = a.static_tiles + atomicAdd(a.queue, 1ull);
             __syncthreads();
             const unsigned long long g = *L.tile;
             if (g >= a.ntiles) break;
@@ -757,7 +775,10 @@ __global__ __launch_bounds__(NT) void k_cls(GbTileArgs a)
         cls_tile<NT, PB, SIEVE_ONLY>(a, a.tile0 + blockIdx.x, L, hc);
     }
     if constexpr (!SIEVE_ONLY) {
-        if (hc.row != kNoRow) flush_hist_cls(a, L, hc.row);
+        if (hc.row != kNoRow) flush_hist_cls(a, L, hc.row, hc);
+        // a row that holds nothing of this launch is marked so
+        if (a.wg_hist != nullptr && !hc.stored && threadIdx.x == 0)
+            a.wg_hist[(unsigned long long)blockIdx.x * a.wg_hist_stride] = kNoRow;
         if (threadIdx.x == 0) flush_slot(a, L.carry);
     }
 }

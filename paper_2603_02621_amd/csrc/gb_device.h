@@ -42,6 +42,7 @@ constexpr uint32_t kNoRow = 0xFFFFFFFFu;
 struct HistCarry {
     uint32_t row = kNoRow;
     unsigned long long n = 0;
+    bool stored = false;   // the counts went to the workgroup's own row once
 };
 
 // The slot summaries a workgroup carries from tile to tile (thread 0, in

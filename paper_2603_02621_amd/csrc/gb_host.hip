@@ -144,6 +144,12 @@ hipError_t ensure_plain_streams(gb_ctx *c)
     return hipEventCreateWithFlags(&c->plain_fork, hipEventDisableTiming);
 }
 
+// Workgroups of a persistent launch of the class kernel.
+uint64_t cls_grid(const gb_ctx *c, const Plan &pl)
+{
+    return std::min<uint64_t>(pl.ntiles, (uint64_t)c->num_cu * c->occ6);
+}
+
 gb_status enqueue_tiles(gb_ctx *c, Workspace &ws, const Job &j, hipStream_t st)
 {
     GbTileArgs a = base_args(c, ws);
@@ -167,7 +173,13 @@ gb_status enqueue_tiles(gb_ctx *c, Workspace &ws, const Job &j, hipStream_t st)
         a.win = ws.win.p;
         a.nwin = (uint32_t)pl.w.size();
         a.ntiles = pl.ntiles;
-        const uint64_t g = std::min<uint64_t>(pl.ntiles, (uint64_t)c->num_cu * (bulk ? c->occupancy : c->occ6));
+        const uint64_t g = bulk ? std::min<uint64_t>(pl.ntiles, (uint64_t)c->num_cu * c->occupancy) : cls_grid(c, pl);
+        if (!bulk) {
+            a.wg_hist = ws.wgh.p;   // num_cu * occ6 rows, at least g
+            a.wg_hist_stride = c->wgh_stride;
+            // the first 7/8 of the tiles round-robin, the rest from the queue
+            a.static_tiles = g * ((pl.ntiles - pl.ntiles / 8) / g);
+        }
         GB_HIP(c, launch(a, (uint32_t)g, true, st));
     } else {
         // One launch per segment.  A segment of S even n is S/T tiles, fewer
@@ -212,6 +224,9 @@ gb_status enqueue_rest(gb_ctx *c, Workspace &ws, const Job &j, hipStream_t st)
     // below P_max when they do not fit the LDS)
     m.count_exh = j.pmin_bits == 1 ? 0u : 1u;
     m.pmax_fast = c->prm.pmax;
+    if (j.persistent && j.pmin_bits != 1)
+        GB_HIP(c, gb_launch_hist_reduce(ws.wgh.p, (uint32_t)cls_grid(c, *j.pl), c->wgh_stride, c->cls_recs,
+                                        c->d_rec_bin, ws.hist.p, st));
     GB_HIP(c, gb_launch_mr(m, mr_grid(c), st));
     GB_HIP(c, gb_launch_argmax(ws.slots.p, ws.recs.p, ws.counters.p + 2, ws.recs.cap, ws.list.p,
                                ws.counters.p, c->prm.max_unresolved, st));
@@ -277,6 +292,7 @@ void Workspace::release()
     slots.release();
     hist.release();
     recs.release();
+    wgh.release();
     list.release();
     counters.release();
     pmin.release();
@@ -364,8 +380,9 @@ gb_status build_tables(gb_ctx *c)
 void free_tables(gb_ctx *c)
 {
     for (void *q : {(void *)c->d_primes, (void *)c->d_magic, (void *)c->d_prime6, (void *)c->d_wheel,
-                    (void *)c->d_cls, (void *)c->d_wheel6})
+                    (void *)c->d_cls, (void *)c->d_wheel6, (void *)c->d_rec_bin})
         if (q) (void)hipFree(q);
+    c->d_rec_bin = nullptr;
     c->d_primes = nullptr;
     c->d_magic = nullptr;
     c->d_prime6 = nullptr;
@@ -525,6 +542,26 @@ gb_status setup_geometry(gb_ctx *c)
         return fail(c, GB_EINVAL, "tile does not fit in LDS (" + std::to_string(c->lds6) + " bytes); lower tile_log2");
     c->np_cls = np;
     c->cls_words = (uint32_t)T.size();
+    // the histogram bin of every probe record of the real groups, in the
+    // order in which a workgroup stores its counts
+    {
+        std::vector<uint32_t> bins;
+        for (uint32_t h = 0; h < 3; ++h) {
+            const uint32_t first = T[3 * h] / 4, groups = T[3 * h + 1];
+            for (uint32_t e = 0; e < 4 * groups; ++e) {
+                const uint32_t wo = first + 12 * (e >> 2) + (e & 3);
+                const uint32_t pr = 131071u - 2u * T[GB_CLS_HDR + wo + 4];
+                bins.push_back(count_le(c->h_primes, pr - 1) + 1);   // 2 -> 0, 3 -> 1, ...
+            }
+        }
+        c->cls_recs = (uint32_t)bins.size();
+        c->wgh_stride = (c->cls_recs + 1 + 15) / 16 * 16;   // 64-byte rows
+        if (c->d_rec_bin) (void)hipFree(c->d_rec_bin);
+        c->d_rec_bin = nullptr;
+        GB_HIP(c, hipMalloc(&c->d_rec_bin, std::max<size_t>(bins.size(), 1) * 4));
+        if (!bins.empty())
+            GB_HIP(c, hipMemcpy(c->d_rec_bin, bins.data(), bins.size() * 4, hipMemcpyHostToDevice));
+    }
     if (c->d_cls) (void)hipFree(c->d_cls);
     c->d_cls = nullptr;
     GB_HIP(c, hipMalloc(&c->d_cls, T.size() * 4));
@@ -596,6 +633,7 @@ gb_status ensure_workspace(gb_ctx *c, Workspace &ws, const Plan &pl, size_t nslo
     GB_HIP(c, ws.slots.ensure(nslots));
     GB_HIP(c, ws.hist.ensure(hist_rows * GB_HIST_BINS_I));
     GB_HIP(c, ws.recs.ensure(std::max<uint64_t>(pl.ntiles, 1)));
+    GB_HIP(c, ws.wgh.ensure((size_t)c->num_cu * (size_t)c->occ6 * c->wgh_stride));
     GB_HIP(c, ws.h_slots.ensure(nslots));
     GB_HIP(c, ws.h_hist.ensure(hist_rows * GB_HIST_BINS_I));
     return GB_OK;
@@ -751,17 +789,22 @@ gb_status run_range(gb_ctx *c, uint64_t lo, uint64_t hi, gb_result *res, void *s
     const uint64_t S = 1ull << c->prm.seg_log2;
     const uint64_t nseg = (C + S - 1) / S;
     if (res->seg_hist && res->seg_hist_rows < nseg) return fail(c, GB_EINVAL, "seg_hist has fewer rows than segments");
+    // Segments share one summary slot unless the caller wants their
+    // histograms apart: the host merges the slots anyway, and with one slot a
+    // persistent workgroup flushes its slot sums once for all its tiles
+    // instead of once per tile (its tiles lie in different segments).
+    const uint64_t nslots = res->seg_hist ? nseg : 1;
     Plan pl;
     pl.w.resize(nseg);
     for (uint64_t s = 0; s < nseg; ++s) {
         pl.w[s].first_n = lo + 2 * S * s;
         pl.w[s].count = std::min(S, C - S * s);
-        pl.w[s].slot = (uint32_t)s;
+        pl.w[s].slot = res->seg_hist ? (uint32_t)s : 0u;
     }
     gb_status stt = plan_windows(c, pl, bulk ? kPlanOdd : kPlanClass);
     if (stt != GB_OK) return stt;
     const size_t hist_rows = res->seg_hist ? nseg : 1;
-    stt = ensure_workspace(c, ws, pl, nseg, hist_rows);
+    stt = ensure_workspace(c, ws, pl, nslots, hist_rows);
     if (stt != GB_OK) return stt;
     const int pb = bulk ? 1 : (res->pmin ? (int)res->pmin_bits : 0);
     void *pmin_dev = nullptr;
@@ -786,7 +829,7 @@ gb_status run_range(gb_ctx *c, uint64_t lo, uint64_t hi, gb_result *res, void *s
     key.stream = st;
     Job j;
     j.pl = &pl;
-    j.nslots = nseg;
+    j.nslots = nslots;
     j.hist_rows = hist_rows;
     j.pmin_dev = pmin_dev;
     j.pmin_bits = pb;
@@ -802,7 +845,7 @@ gb_status run_range(gb_ctx *c, uint64_t lo, uint64_t hi, gb_result *res, void *s
     res->tile_ms = ms;
     res->tile_launches = batched ? 1 : nseg;
     gb_summary tot{};
-    for (uint64_t s = 0; s < nseg; ++s) merge_slot(tot, ws.h_slots.p[s]);
+    for (uint64_t s = 0; s < nslots; ++s) merge_slot(tot, ws.h_slots.p[s]);
     res->count = tot.count;
     res->max_p = tot.max_p;
     res->argmax_n = tot.argmax_n;

@@ -93,6 +93,17 @@ struct GbTileArgs {
     uint32_t pmax_fast;        // P_max: n with a larger p_min count as exhaustive
     const uint4 *prime6;       // per odd prime of the table below 2^27: GB_PRIME6 entry
     uint32_t n_prime6;         // entries of prime6 (the first n_prime6 odd primes)
+    // persistent k_cls: each workgroup's first histogram flush is stored (no
+    // atomics) as row blockIdx.x of wg_hist, wg_hist_stride words each: the
+    // histogram row it belongs to, then the hit count of every probe record
+    // in class order (GB_CLS_*); k_hist_reduce adds the rows up.  Null: every
+    // flush is a set of 64-bit atomics into hist.
+    uint32_t *wg_hist;
+    uint32_t wg_hist_stride;
+    // persistent k_cls: tiles [0, static_tiles) go to workgroup t mod
+    // gridDim.x in turn (static_tiles a multiple of gridDim.x), the rest to
+    // whichever workgroup asks the queue first
+    unsigned long long static_tiles;
 };
 
 // GbTileArgs::prime6 entry of the odd prime p: x = p, y = the least k >= 0
@@ -145,6 +156,11 @@ hipError_t gb_cls_prepare(uint32_t threads, size_t lds_bytes);
 hipError_t gb_cls_occupancy(uint32_t threads, size_t lds_bytes, int *blocks_per_cu);
 hipError_t gb_launch_cls(const GbTileArgs &a, uint32_t grid, uint32_t threads, size_t lds_bytes, int pmin_bits,
                          bool persistent, bool sieve_only, hipStream_t st);
+// Sum of the rows of GbTileArgs::wg_hist into the histogram rows they name
+// (rows whose first word is 0xFFFFFFFF are skipped); rec_bin[r] is the
+// histogram bin of probe record r.
+hipError_t gb_launch_hist_reduce(const uint32_t *wg_hist, uint32_t nwg, uint32_t stride, uint32_t nrec,
+                                 const uint32_t *rec_bin, unsigned long long *hist, hipStream_t st);
 hipError_t gb_launch_argmax(GbSlot *slots, const GbTileRec *recs, const unsigned long long *rec_count,
                             unsigned long long rec_cap, const GbExh *list,
                             const unsigned long long *list_count, unsigned long long list_cap,

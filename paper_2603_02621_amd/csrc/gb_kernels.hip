@@ -985,6 +985,31 @@ __global__ __launch_bounds__(256) void k_mr(GbMrArgs a)
     }
 }
 
+// One thread per probe record: the record's counts of every workgroup row,
+// summed while consecutive rows name the same histogram row, each sum added
+// with one 64-bit atomic.
+__global__ void k_hist_reduce(const uint32_t *wg_hist, uint32_t nwg, uint32_t stride, uint32_t nrec,
+                              const uint32_t *rec_bin, unsigned long long *hist)
+{
+    const uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= nrec) return;
+    const uint32_t bin = rec_bin[r];
+    uint32_t cur = 0xFFFFFFFFu;
+    unsigned long long sum = 0;
+    for (uint32_t w = 0; w < nwg; ++w) {
+        const uint32_t *row = wg_hist + (unsigned long long)w * stride;
+        const uint32_t hr = row[0];
+        if (hr == 0xFFFFFFFFu) continue;
+        if (hr != cur) {
+            if (sum) atomicAdd(&hist[(unsigned long long)cur * GB_HIST_BINS_I + bin], sum);
+            cur = hr;
+            sum = 0;
+        }
+        sum += row[1u + r];
+    }
+    if (sum) atomicAdd(&hist[(unsigned long long)cur * GB_HIST_BINS_I + bin], sum);
+}
+
 __global__ void k_argmax(GbSlot *slots, const GbTileRec *recs, const unsigned long long *rec_count,
                          unsigned long long rec_cap, const GbExh *list,
                          const unsigned long long *list_count, unsigned long long cap)
@@ -1162,6 +1187,15 @@ hipError_t gb_launch_tiles(const GbTileArgs &a, uint32_t grid, uint32_t threads,
 hipError_t gb_launch_mr(const GbMrArgs &a, uint32_t grid, hipStream_t st)
 {
     hipLaunchKernelGGL(k_mr, dim3(grid), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t gb_launch_hist_reduce(const uint32_t *wg_hist, uint32_t nwg, uint32_t stride, uint32_t nrec,
+                                 const uint32_t *rec_bin, unsigned long long *hist, hipStream_t st)
+{
+    if (nrec == 0 || nwg == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_hist_reduce, dim3((nrec + 255) / 256), dim3(256), 0, st, wg_hist, nwg, stride, nrec,
+                       rec_bin, hist);
     return hipGetLastError();
 }
 

@@ -86,6 +86,7 @@ struct Workspace {
     DevBuf<GbSlot> slots;
     DevBuf<unsigned long long> hist;
     DevBuf<GbTileRec> recs;
+    DevBuf<uint32_t> wgh;                // per workgroup of a persistent launch: its stored histogram row
     DevBuf<GbExh> list;
     DevBuf<unsigned long long> counters;
     DevBuf<unsigned char> pmin;          // per-n output staging
@@ -151,6 +152,9 @@ struct gb_ctx {
     uint32_t np_cls = 0;             // odd primes on the class probe lists
     uint32_t *d_cls = nullptr;       // class headers, sieve tables, probe records
     uint32_t cls_words = 0;
+    uint32_t cls_recs = 0;           // probe records of the three class lists (the real groups)
+    uint32_t *d_rec_bin = nullptr;   // histogram bin of each probe record, class order
+    uint32_t wgh_stride = 0;         // words per workgroup row of Workspace::wgh
     uint32_t *d_wheel6 = nullptr;    // two plane patterns
     uint32_t wheel6_len = 0, wheel6_stride = 0;
     uint32_t k6_first = 0, k6_wg_end = 0, k6_wave_end = 0, k6_single = 0;

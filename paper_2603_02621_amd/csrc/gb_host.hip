@@ -518,8 +518,13 @@ gb_status setup_geometry(gb_ctx *c)
     c->wheel_len = L;
 
     // ---- search split by residue mod 6: stretches, class lists, planes ----
-    c->sb_per_tile = std::max<uint32_t>(1, (1u << p.tile_log2) / 192u);
-    c->tile_n = 192u * c->sb_per_tile;
+    // A class tile spends 2/3 of a plane bit per n, so it takes the LDS of an
+    // odd-number tile of 2^tile_log2 bits with 2^tile_log2 / 128 stretches
+    // (1.5 times the n), and shrinks towards 2^tile_log2 / 192 stretches when
+    // the lists do not fit beside it.
+    const uint32_t sb_max = std::max<uint32_t>(1, (1u << p.tile_log2) / 128u);
+    const uint32_t sb_min = std::max<uint32_t>(1, (1u << p.tile_log2) / 192u);
+    c->sb_per_tile = sb_max;
     c->k6_first = count_le(c->h_primes, std::max<uint32_t>(3, p.wheel_max));
     // the class lists hold every odd prime <= P_max when they fit the LDS
     // beside the planes, else the longest prefix that does; the exhaustive
@@ -536,8 +541,12 @@ gb_status setup_geometry(gb_ctx *c)
         c->k6_single = std::max(c->k6_wave_end, count_le(c->h_primes, Lk - 1));
         c->lds6 = gb_cls_lds_bytes(c->sb_per_tile, c->hk, (uint32_t)T.size(), c->k6_wg_end - c->k6_first);
         if (c->lds6 <= 160 * 1024 || np == 0) break;
-        np -= std::max<uint32_t>(1, np / 16);
+        if (c->sb_per_tile > sb_min)
+            c->sb_per_tile = std::max(sb_min, c->sb_per_tile - std::max<uint32_t>(1, c->sb_per_tile / 32));
+        else
+            np -= std::max<uint32_t>(1, np / 16);
     }
+    c->tile_n = 192u * c->sb_per_tile;
     if (c->lds6 > 160 * 1024)
         return fail(c, GB_EINVAL, "tile does not fit in LDS (" + std::to_string(c->lds6) + " bytes); lower tile_log2");
     c->np_cls = np;

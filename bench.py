@@ -192,7 +192,8 @@ def main():
         params.update({k: int(v) for k, v in json.loads(args.params).items()})
     v = Verifier(0, **params)
     p = v.params
-    print(f"# params {p}", file=sys.stderr, flush=True)
+    geo = v.geometry
+    print(f"# params {p} geometry {geo}", file=sys.stderr, flush=True)
 
     # ---- batched (timed) --------------------------------------------------
     for _ in range(args.warmup):
@@ -411,7 +412,8 @@ def main():
         "config": {"workload": "all even n in [1e12-2^36, 1e12], summaries only",
                    "n_per_step": count, "pmax": p["pmax"], "seg_log2": p["seg_log2"],
                    "tile_log2": p["tile_log2"], "wg_threads": p["wg_threads"],
-                   "wheel_max": p["wheel_max"], "parallelism": "1 GPU"},
+                   "wheel_max": p["wheel_max"], "tile_n": geo["cls_tile_n"],
+                   "tile_lds_bytes": geo["cls_lds_bytes"], "parallelism": "1 GPU"},
         "plain": plain,
         "batched_windows": windows,
         "bulk_verify": bulk,

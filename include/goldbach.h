@@ -146,6 +146,16 @@ void      gb_destroy(gb_ctx *ctx);
 /* The parameters in effect (defaults resolved). */
 gb_status gb_get_params(const gb_ctx *ctx, gb_params *out);
 
+/* The tile geometry the parameters resolve to (host values; no device
+ * work): even n per tile of the minimal-p search (n split by residue mod 6:
+ * the largest multiple of 192 whose two planes and probe lists fit the LDS,
+ * from twice 2^tile_log2 down; the paper's tile is one segment, subsection
+ * "Correct segmentation"), the LDS bytes of its workgroup, the odd primes on
+ * its probe lists (P_max's, or fewer when LDS is short), and even n per tile
+ * of the bulk form.  Any pointer may be NULL.  GB_EINVAL for a NULL ctx. */
+gb_status gb_tile_geometry(const gb_ctx *ctx, uint64_t *cls_tile_n, uint64_t *cls_lds_bytes,
+                           uint64_t *cls_list_primes, uint64_t *bulk_tile_n);
+
 /* Plain form: p_min for every even n in [max(lo,4), hi], one kernel launch
  * per segment of S even n, in order, on `stream`; then the exhaustive phase
  * and the summary reduction.  (Problem statement: section "Methods"; the

@@ -73,6 +73,14 @@ class Verifier:
         return p.as_dict()
 
     @property
+    def geometry(self) -> dict:
+        """Tile geometry the parameters resolve to (see gb_tile_geometry)."""
+        v = [ctypes.c_uint64() for _ in range(4)]
+        self._check(self._lib.gb_tile_geometry(self._h, *[ctypes.byref(x) for x in v]))
+        return dict(zip(("cls_tile_n", "cls_lds_bytes", "cls_list_primes", "bulk_tile_n"),
+                        (int(x.value) for x in v)))
+
+    @property
     def last_error(self) -> str:
         return self._lib.gb_last_error(self._h).decode()
 

@@ -98,6 +98,8 @@ SIGNATURES = {
     "gb_create": ([ctypes.POINTER(vp), ctypes.POINTER(Params)], i32),
     "gb_destroy": ([vp], None),
     "gb_get_params": ([vp, ctypes.POINTER(Params)], i32),
+    "gb_tile_geometry": ([vp, ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_uint64),
+                          ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_uint64)], i32),
     "gb_verify_range": ([vp, u64, u64, ctypes.POINTER(Result), vp], i32),
     "gb_verify_range_batched": ([vp, u64, u64, ctypes.POINTER(Result), vp], i32),
     "gb_verify_range_bulk": ([vp, u64, u64, ctypes.POINTER(Result), vp], i32),

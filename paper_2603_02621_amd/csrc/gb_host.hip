@@ -518,11 +518,13 @@ gb_status setup_geometry(gb_ctx *c)
     c->wheel_len = L;
 
     // ---- search split by residue mod 6: stretches, class lists, planes ----
-    // A class tile spends 2/3 of a plane bit per n, so it takes the LDS of an
-    // odd-number tile of 2^tile_log2 bits with 2^tile_log2 / 128 stretches
-    // (1.5 times the n), and shrinks towards 2^tile_log2 / 192 stretches when
-    // the lists do not fit beside it.
-    const uint32_t sb_max = std::max<uint32_t>(1, (1u << p.tile_log2) / 128u);
+    // A class tile spends 2/3 of a plane bit per n.  It is the largest that
+    // fits the LDS beside the lists, from 2^tile_log2 / 96 stretches (twice
+    // the n of an odd-number tile of 2^tile_log2 bits) down in steps of
+    // 1/64, and at least 2^tile_log2 / 192 stretches (the n of that tile):
+    // per-tile costs (first strikes of every sieving prime, the search's
+    // tail, barriers) then spread over more n.
+    const uint32_t sb_max = std::max<uint32_t>(1, (1u << p.tile_log2) / 96u);
     const uint32_t sb_min = std::max<uint32_t>(1, (1u << p.tile_log2) / 192u);
     c->sb_per_tile = sb_max;
     c->k6_first = count_le(c->h_primes, std::max<uint32_t>(3, p.wheel_max));
@@ -542,7 +544,7 @@ gb_status setup_geometry(gb_ctx *c)
         c->lds6 = gb_cls_lds_bytes(c->sb_per_tile, c->hk, (uint32_t)T.size(), c->k6_wg_end - c->k6_first);
         if (c->lds6 <= 160 * 1024 || np == 0) break;
         if (c->sb_per_tile > sb_min)
-            c->sb_per_tile = std::max(sb_min, c->sb_per_tile - std::max<uint32_t>(1, c->sb_per_tile / 32));
+            c->sb_per_tile = std::max(sb_min, c->sb_per_tile - std::max<uint32_t>(1, c->sb_per_tile / 64));
         else
             np -= std::max<uint32_t>(1, np / 16);
     }
@@ -947,6 +949,17 @@ gb_status gb_get_params(const gb_ctx *c, gb_params *out)
 {
     if (!c || !out) return GB_EINVAL;
     *out = c->prm;
+    return GB_OK;
+}
+
+gb_status gb_tile_geometry(const gb_ctx *c, uint64_t *cls_tile_n, uint64_t *cls_lds_bytes,
+                           uint64_t *cls_list_primes, uint64_t *bulk_tile_n)
+{
+    if (!c) return GB_EINVAL;
+    if (cls_tile_n) *cls_tile_n = c->tile_n;
+    if (cls_lds_bytes) *cls_lds_bytes = c->lds6;
+    if (cls_list_primes) *cls_list_primes = c->np_cls;
+    if (bulk_tile_n) *bulk_tile_n = c->tile_n_odd;
     return GB_OK;
 }
 

@@ -156,6 +156,28 @@ def test_range_near_2p53_vs_oracle(orc, lo, hi):
     v.close()
 
 
+@pytest.mark.parametrize("tile_log2,pmax", [(20, 4096), (16, 4096), (20, 16384), (12, 1024)])
+def test_tile_geometry(tile_log2, pmax):
+    # the class tile: a multiple of 192 n between the n of an odd-number
+    # tile of 2^tile_log2 bits and twice that, within the LDS; its lists hold
+    # the odd primes up to P_max unless the LDS is short at the smallest tile
+    v = _make(tile_log2=tile_log2, pmax=pmax)
+    try:
+        g = v.geometry
+        t = 1 << tile_log2
+        assert g["cls_tile_n"] % 192 == 0
+        assert 192 * max(1, t // 192) <= g["cls_tile_n"] <= 192 * (t // 96)
+        assert g["cls_lds_bytes"] <= 160 * 1024
+        assert g["bulk_tile_n"] == t
+        n_odd = sum(1 for q in range(3, pmax + 1, 2) if all(q % d for d in range(3, int(q**0.5) + 1, 2)))
+        if g["cls_tile_n"] > 192 * max(1, t // 192):
+            assert g["cls_list_primes"] == n_odd
+        else:
+            assert 0 < g["cls_list_primes"] <= n_odd
+    finally:
+        v.close()
+
+
 def test_empty_range(V):
     got = V.verify_range(10, 8)
     assert got["count"] == 0 and got["status"] == 0

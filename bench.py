@@ -24,6 +24,12 @@ import time
 
 import numpy as np
 
+# The plain form runs as many segments side by side as the process has
+# hardware queues (the library reads GPU_MAX_HW_QUEUES, HIP's default 4);
+# eight fill the device with its tiles.  Raised before HIP starts.
+if int(os.environ.get("GPU_MAX_HW_QUEUES") or 4) < 8:
+    os.environ["GPU_MAX_HW_QUEUES"] = "8"
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 

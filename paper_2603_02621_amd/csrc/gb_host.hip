@@ -4,6 +4,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -164,10 +165,22 @@ gb_status enqueue_tiles(gb_ctx *c, Workspace &ws, const Job &j, hipStream_t st)
     // the bulk form runs on consecutive odd numbers, the minimal-p search in
     // the residue-class layout
     const bool bulk = j.pmin_bits == 1;
-    if (!bulk) a.tile_n = c->tile_n;
+    size_t lds6 = c->lds6;
+    if (!bulk) {
+        a.tile_n = c->tile_n;
+        if (!j.persistent) {
+            // the plain form's geometry (its plan was cut with kPlanClassPlain)
+            a.tile_n = c->tile_np;
+            a.sb_per_tile = c->sbp;
+            a.k6_wg_end = c->k6p_wg_end;
+            a.k6_wave_end = c->k6p_wave_end;
+            a.k6_single = c->k6p_single;
+            lds6 = c->lds6p;
+        }
+    }
     auto launch = [&](const GbTileArgs &b, uint32_t grid, bool pers, hipStream_t ls) -> hipError_t {
         return bulk ? gb_launch_tiles(b, grid, c->threads, c->lds, j.pmin_bits, pers, false, c->group_window, ls)
-                    : gb_launch_cls(b, grid, c->threads, c->lds6, j.pmin_bits, pers, false, ls);
+                    : gb_launch_cls(b, grid, c->threads, lds6, j.pmin_bits, pers, false, ls);
     };
     if (j.persistent) {
         a.win = ws.win.p;
@@ -187,7 +200,7 @@ gb_status enqueue_tiles(gb_ctx *c, Workspace &ws, const Job &j, hipStream_t st)
         // the caller's stream and up to three more in turn and run side by
         // side; each segment writes only its own slot, histogram row, tile
         // records and per-n output.
-        const int lanes = (int)std::min<size_t>(gb_ctx::kPlainLanes, pl.w.size());
+        const int lanes = (int)std::min<size_t>((size_t)c->plain_lanes, pl.w.size());
         if (lanes > 1) {
             GB_HIP(c, ensure_plain_streams(c));
             GB_HIP(c, hipEventRecord(c->plain_fork, st));
@@ -494,6 +507,11 @@ gb_status setup_geometry(gb_ctx *c)
     hipDeviceProp_t prop;
     GB_HIP(c, hipGetDeviceProperties(&prop, p.device));
     c->num_cu = prop.multiProcessorCount;
+    {
+        const char *q = std::getenv("GPU_MAX_HW_QUEUES");
+        const long hw = q ? std::strtol(q, nullptr, 10) : 4;
+        c->plain_lanes = (int)std::max<long>(1, std::min<long>(gb_ctx::kPlainLanes, hw > 0 ? hw : 4));
+    }
     GB_HIP(c, gb_prepare_tiles(c->threads, c->lds));
     int occ = 0;
     GB_HIP(c, gb_tile_occupancy(c->threads, c->lds, c->group_window, &occ));
@@ -549,6 +567,22 @@ gb_status setup_geometry(gb_ctx *c)
             np -= std::max<uint32_t>(1, np / 16);
     }
     c->tile_n = 192u * c->sb_per_tile;
+    // The plain form launches one grid per segment of S even n, with up to
+    // plain_lanes segments in flight: its tiles are cut so that a segment
+    // makes num_cu / plain_lanes of them (never more n than a batched tile).
+    {
+        const uint64_t S = 1ull << p.seg_log2;
+        const uint64_t want = std::max<uint64_t>(1, (uint64_t)c->num_cu / (uint64_t)c->plain_lanes);
+        // a segment with its lead (< 192 n) in exactly `want` tiles
+        const uint64_t sbw = (S + 191 + 192 * want - 1) / (192 * want);
+        c->sbp = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(c->sb_per_tile, sbw));
+        c->tile_np = 192u * c->sbp;
+        const uint32_t Lk = c->hk + 64 * c->sbp;
+        c->k6p_wg_end = std::max(c->k6_first, count_le(c->h_primes, Lk / c->threads));
+        c->k6p_wave_end = std::max(c->k6p_wg_end, count_le(c->h_primes, Lk / 64));
+        c->k6p_single = std::max(c->k6p_wave_end, count_le(c->h_primes, Lk - 1));
+        c->lds6p = gb_cls_lds_bytes(c->sbp, c->hk, (uint32_t)T.size(), c->k6p_wg_end - c->k6_first);
+    }
     if (c->lds6 > 160 * 1024)
         return fail(c, GB_EINVAL, "tile does not fit in LDS (" + std::to_string(c->lds6) + " bytes); lower tile_log2");
     c->np_cls = np;
@@ -613,8 +647,9 @@ gb_status setup_geometry(gb_ctx *c)
 // counted in `lead` (the kernels mask them).
 gb_status plan_windows(gb_ctx *c, Plan &pl, PlanKind kind)
 {
-    const uint64_t T = kind == kPlanClass ? c->tile_n : c->tile_n_odd;
-    const uint64_t A = kind == kPlanClass ? 384 : 128;
+    const bool cls = kind == kPlanClass || kind == kPlanClassPlain;
+    const uint64_t T = kind == kPlanClass ? c->tile_n : kind == kPlanClassPlain ? c->tile_np : c->tile_n_odd;
+    const uint64_t A = cls ? 384 : 128;
     uint64_t tb = 0, off = 0;
     for (auto &w : pl.w) {
         const uint64_t user_count = w.count;
@@ -812,7 +847,7 @@ gb_status run_range(gb_ctx *c, uint64_t lo, uint64_t hi, gb_result *res, void *s
         pl.w[s].count = std::min(S, C - S * s);
         pl.w[s].slot = res->seg_hist ? (uint32_t)s : 0u;
     }
-    gb_status stt = plan_windows(c, pl, bulk ? kPlanOdd : kPlanClass);
+    gb_status stt = plan_windows(c, pl, bulk ? kPlanOdd : batched ? kPlanClass : kPlanClassPlain);
     if (stt != GB_OK) return stt;
     const size_t hist_rows = res->seg_hist ? nseg : 1;
     stt = ensure_workspace(c, ws, pl, nslots, hist_rows);

@@ -158,6 +158,10 @@ struct gb_ctx {
     uint32_t *d_wheel6 = nullptr;    // two plane patterns
     uint32_t wheel6_len = 0, wheel6_stride = 0;
     uint32_t k6_first = 0, k6_wg_end = 0, k6_wave_end = 0, k6_single = 0;
+    // the plain form's class tiles (one launch per segment, four in flight):
+    // small enough that a segment fills a quarter of the device
+    uint32_t sbp = 0, tile_np = 0, k6p_wg_end = 0, k6p_wave_end = 0, k6p_single = 0;
+    size_t lds6p = 0;
     size_t lds6 = 0;
     int occ6 = 1;
     // bulk verification and the sieve dump, consecutive odd numbers
@@ -173,7 +177,11 @@ struct gb_ctx {
     // plain form: segment launches go round-robin to the caller's stream and
     // these (created on first use), forked after the init kernel and joined
     // before the exhaustive phase
-    static constexpr int kPlainLanes = 4;
+    // The plain form runs up to kPlainLanes segments side by side, one per
+    // stream: as many as the process has hardware queues (GPU_MAX_HW_QUEUES,
+    // 4 when unset), since streams beyond that share queues and run in turn.
+    static constexpr int kPlainLanes = 8;
+    int plain_lanes = 4;
     hipStream_t plain_st[kPlainLanes - 1] = {};
     hipEvent_t plain_fork = nullptr, plain_join[kPlainLanes - 1] = {};
     gbrt::Workspace ws;              // scratch of the synchronous calls
@@ -193,7 +201,7 @@ void free_tables(gb_ctx *c);
 // How a plan splits windows: the minimal-p search (tiles of tile_n, first
 // n moved down to a multiple of 384), the bulk form (tiles of
 // tile_n_odd, multiples of 128) or the odd-number sieve dump (no move).
-enum PlanKind { kPlanClass, kPlanOdd, kPlanSieve };
+enum PlanKind { kPlanClass, kPlanClassPlain, kPlanOdd, kPlanSieve };
 gb_status plan_windows(gb_ctx *c, Plan &pl, PlanKind kind = kPlanClass);
 gb_status ensure_workspace(gb_ctx *c, Workspace &ws, const Plan &pl, size_t nslots, size_t hist_rows);
 // init + tiles + exhaustive phase + argmax + summary copies, on `st`,

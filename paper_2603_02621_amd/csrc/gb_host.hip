@@ -510,7 +510,7 @@ gb_status setup_geometry(gb_ctx *c)
     {
         const char *q = std::getenv("GPU_MAX_HW_QUEUES");
         const long hw = q ? std::strtol(q, nullptr, 10) : 4;
-        c->plain_lanes = (int)std::max<long>(1, std::min<long>(gb_ctx::kPlainLanes, hw > 0 ? hw : 4));
+        c->plain_hwq = (int)std::max<long>(1, std::min<long>(gb_ctx::kPlainLanes, hw > 0 ? hw : 4));
     }
     GB_HIP(c, gb_prepare_tiles(c->threads, c->lds));
     int occ = 0;
@@ -568,14 +568,22 @@ gb_status setup_geometry(gb_ctx *c)
     }
     c->tile_n = 192u * c->sb_per_tile;
     // The plain form launches one grid per segment of S even n, with up to
-    // plain_lanes segments in flight: its tiles are cut so that a segment
-    // makes num_cu / plain_lanes of them (never more n than a batched tile).
+    // plain_hwq segments in flight: its tiles are cut so that a segment
+    // makes num_cu / plain_hwq of them (never more n than a batched tile);
+    // then the segments in flight are cut to the number whose tiles exceed
+    // the CUs by at most 1/8 (a larger backlog delays each segment's last
+    // tiles, and with them the next launch of its stream).
     {
         const uint64_t S = 1ull << p.seg_log2;
-        const uint64_t want = std::max<uint64_t>(1, (uint64_t)c->num_cu / (uint64_t)c->plain_lanes);
-        // a segment with its lead (< 192 n) in exactly `want` tiles
-        const uint64_t sbw = (S + 191 + 192 * want - 1) / (192 * want);
-        c->sbp = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(c->sb_per_tile, sbw));
+        const uint64_t want = std::max<uint64_t>(1, ((uint64_t)c->num_cu + c->plain_hwq - 1) / (uint64_t)c->plain_hwq);
+        // a segment with its lead (< 192 n) in `want` tiles, or in as many
+        // more as batched-size tiles need, all of one size (no sliver tile:
+        // it would pay every sieving prime's first strikes for a few n)
+        const uint64_t span = S + 191;
+        const uint64_t k = std::max<uint64_t>(want, (span + 192ull * c->sb_per_tile - 1) / (192ull * c->sb_per_tile));
+        c->sbp = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(c->sb_per_tile, (span + 192 * k - 1) / (192 * k)));
+        const uint64_t fit = ((uint64_t)c->num_cu + c->num_cu / 8) / k;
+        c->plain_lanes = (int)std::max<uint64_t>(1, std::min<uint64_t>((uint64_t)c->plain_hwq, fit));
         c->tile_np = 192u * c->sbp;
         const uint32_t Lk = c->hk + 64 * c->sbp;
         c->k6p_wg_end = std::max(c->k6_first, count_le(c->h_primes, Lk / c->threads));

@@ -985,29 +985,58 @@ __global__ __launch_bounds__(256) void k_mr(GbMrArgs a)
     }
 }
 
-// One thread per probe record: the record's counts of every workgroup row,
-// summed while consecutive rows name the same histogram row, each sum added
-// with one 64-bit atomic.
-__global__ void k_hist_reduce(const uint32_t *wg_hist, uint32_t nwg, uint32_t stride, uint32_t nrec,
-                              const uint32_t *rec_bin, unsigned long long *hist)
+// One block per probe record, its threads over the workgroup rows.  When
+// every row names the same histogram row (a range or windows call without
+// per-segment histograms) the block sums the record's counts and adds them
+// with one 64-bit atomic; otherwise each thread adds its own partial sums.
+__global__ __launch_bounds__(256) void k_hist_reduce(const uint32_t *wg_hist, uint32_t nwg, uint32_t stride,
+                                                     uint32_t nrec, const uint32_t *rec_bin,
+                                                     unsigned long long *hist)
 {
-    const uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+    __shared__ unsigned long long part[4];
+    __shared__ uint32_t lo_row, hi_row;
+    const uint32_t r = blockIdx.x;
     if (r >= nrec) return;
+    if (threadIdx.x == 0) {
+        lo_row = 0xFFFFFFFFu;
+        hi_row = 0u;
+    }
+    __syncthreads();
     const uint32_t bin = rec_bin[r];
-    uint32_t cur = 0xFFFFFFFFu;
+    uint32_t mine = 0xFFFFFFFFu;
     unsigned long long sum = 0;
-    for (uint32_t w = 0; w < nwg; ++w) {
+    for (uint32_t w = threadIdx.x; w < nwg; w += blockDim.x) {
         const uint32_t *row = wg_hist + (unsigned long long)w * stride;
         const uint32_t hr = row[0];
         if (hr == 0xFFFFFFFFu) continue;
-        if (hr != cur) {
-            if (sum) atomicAdd(&hist[(unsigned long long)cur * GB_HIST_BINS_I + bin], sum);
-            cur = hr;
+        const uint32_t c = row[1u + r];
+        if (mine != 0xFFFFFFFFu && hr != mine) {   // a second histogram row in this thread's share
+            if (sum) atomicAdd(&hist[(unsigned long long)mine * GB_HIST_BINS_I + bin], sum);
             sum = 0;
+            hi_row = 0xFFFFFFFEu;                   // forces the per-thread path below
         }
-        sum += row[1u + r];
+        mine = hr;
+        sum += c;
     }
-    if (sum) atomicAdd(&hist[(unsigned long long)cur * GB_HIST_BINS_I + bin], sum);
+    if (mine != 0xFFFFFFFFu) {
+        atomicMin(&lo_row, mine);
+        atomicMax(&hi_row, mine);
+    }
+    __syncthreads();
+    if (lo_row == 0xFFFFFFFFu) return;   // no row holds anything
+    if (lo_row != hi_row) {
+        if (sum) atomicAdd(&hist[(unsigned long long)mine * GB_HIST_BINS_I + bin], sum);
+        return;
+    }
+    // one histogram row: wave sums, then the block's
+    for (int o = 32; o > 0; o >>= 1) sum += __shfl_down(sum, o, 64);
+    if ((threadIdx.x & 63u) == 0) part[threadIdx.x >> 6] = sum;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long t = 0;
+        for (uint32_t k = 0; k < (blockDim.x + 63u) / 64u; ++k) t += part[k];
+        if (t) atomicAdd(&hist[(unsigned long long)lo_row * GB_HIST_BINS_I + bin], t);
+    }
 }
 
 __global__ void k_argmax(GbSlot *slots, const GbTileRec *recs, const unsigned long long *rec_count,
@@ -1194,8 +1223,7 @@ hipError_t gb_launch_hist_reduce(const uint32_t *wg_hist, uint32_t nwg, uint32_t
                                  const uint32_t *rec_bin, unsigned long long *hist, hipStream_t st)
 {
     if (nrec == 0 || nwg == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_hist_reduce, dim3((nrec + 255) / 256), dim3(256), 0, st, wg_hist, nwg, stride, nrec,
-                       rec_bin, hist);
+    hipLaunchKernelGGL(k_hist_reduce, dim3(nrec), dim3(256), 0, st, wg_hist, nwg, stride, nrec, rec_bin, hist);
     return hipGetLastError();
 }
 

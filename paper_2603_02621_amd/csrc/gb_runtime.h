@@ -178,9 +178,12 @@ struct gb_ctx {
     // these (created on first use), forked after the init kernel and joined
     // before the exhaustive phase
     // The plain form runs up to kPlainLanes segments side by side, one per
-    // stream: as many as the process has hardware queues (GPU_MAX_HW_QUEUES,
-    // 4 when unset), since streams beyond that share queues and run in turn.
+    // stream: no more than the process has hardware queues (plain_hwq, from
+    // GPU_MAX_HW_QUEUES, 4 when unset; streams beyond that share queues and
+    // run in turn), and no more than keep the tiles in flight within 1/8 of
+    // the CU count (plain_lanes, set with the plain tile size).
     static constexpr int kPlainLanes = 8;
+    int plain_hwq = 4;
     int plain_lanes = 4;
     hipStream_t plain_st[kPlainLanes - 1] = {};
     hipEvent_t plain_fork = nullptr, plain_join[kPlainLanes - 1] = {};

@@ -152,7 +152,8 @@ gb_status gb_get_params(const gb_ctx *ctx, gb_params *out);
  * from twice 2^tile_log2 down; the paper's tile is one segment, subsection
  * "Correct segmentation"), the LDS bytes of its workgroup, the odd primes on
  * its probe lists (P_max's, or fewer when LDS is short), and even n per tile
- * of the bulk form.  Any pointer may be NULL.  GB_EINVAL for a NULL ctx. */
+ * of the batched bulk form (the same tiles).  Any pointer may be NULL.
+ * GB_EINVAL for a NULL ctx. */
 gb_status gb_tile_geometry(const gb_ctx *ctx, uint64_t *cls_tile_n, uint64_t *cls_lds_bytes,
                            uint64_t *cls_list_primes, uint64_t *bulk_tile_n);
 

@@ -522,7 +522,7 @@ __device__ void cls_tile(const GbTileArgs &a, unsigned long long g, const ClsLds
         const uint32_t sp = special_p(bb);
         if (sp) {
             lastkey = sp == 2u ? 0xFFFF0000u : ((65536u - 2u) << 16);
-            atomicAdd(&hist[sp == 2u ? 0u : 1u], 1ull);
+            if constexpr (PB != 1) atomicAdd(&hist[sp == 2u ? 0u : 1u], 1ull);
             if constexpr (PB != 0)
                 if (a.pmin) store_p<PB>(a.pmin, outb + (bb == 2u ? 2u : 3u), sp);
         }
@@ -567,6 +567,13 @@ __device__ void cls_tile(const GbTileArgs &a, unsigned long long g, const ClsLds
                 const uint32_t w0 = bsel(mr, v4[1], v4[0]), w1 = bsel(mr, v4[2], v4[1]), w2 = bsel(mr, v4[3], v4[2]);
                 const uint32_t hlo = __builtin_amdgcn_alignbit(w1, w0, x) & Ulo;
                 const uint32_t hhi = __builtin_amdgcn_alignbit(w2, w1, x) & Uhi;
+                if constexpr (PB == 1) {
+                    // bulk: only the unresolved mask and the key of the last hit
+                    lastkey = (hlo | hhi) != 0u ? gs[u] << 16 : lastkey;
+                    Ulo ^= hlo;
+                    Uhi ^= hhi;
+                    continue;
+                }
                 pcs[u] = __popc(hlo) + __popc(hhi);
                 if (pcs[u] != 0u) {
                     const uint32_t pc = pcs[u];
@@ -588,11 +595,13 @@ __device__ void cls_tile(const GbTileArgs &a, unsigned long long g, const ClsLds
                     Uhi ^= hhi;
                 }
             }
-            lds_u64 *lh2 = reinterpret_cast<lds_u64 *>(static_cast<uintptr_t>(ka + 32u));
-            const unsigned long long c01 = (unsigned long long)pcs[0] | ((unsigned long long)pcs[1] << 32);
-            const unsigned long long c23 = (unsigned long long)pcs[2] | ((unsigned long long)pcs[3] << 32);
-            if (c01 != 0ull) __hip_atomic_fetch_add(&lh2[0], c01, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-            if (c23 != 0ull) __hip_atomic_fetch_add(&lh2[1], c23, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            if constexpr (PB != 1) {
+                lds_u64 *lh2 = reinterpret_cast<lds_u64 *>(static_cast<uintptr_t>(ka + 32u));
+                const unsigned long long c01 = (unsigned long long)pcs[0] | ((unsigned long long)pcs[1] << 32);
+                const unsigned long long c23 = (unsigned long long)pcs[2] | ((unsigned long long)pcs[3] << 32);
+                if (c01 != 0ull) __hip_atomic_fetch_add(&lh2[0], c01, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                if (c23 != 0ull) __hip_atomic_fetch_add(&lh2[1], c23, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            }
             ka += 48u;
         }
         // lanes that finish a block take the next blocks of their wave's
@@ -803,6 +812,8 @@ hipError_t allow_cls_nt(size_t lds)
     hipError_t e = hipSuccess, r;
     if ((r = allow_cls<NT, 0, false, true>(lds)) != hipSuccess) e = r;
     if ((r = allow_cls<NT, 0, true, false>(lds)) != hipSuccess) e = r;
+    if ((r = allow_cls<NT, 1, true, false>(lds)) != hipSuccess) e = r;
+    if ((r = allow_cls<NT, 1, false, false>(lds)) != hipSuccess) e = r;
     if ((r = allow_cls<NT, 16, true, false>(lds)) != hipSuccess) e = r;
     if ((r = allow_cls<NT, 32, true, false>(lds)) != hipSuccess) e = r;
     if ((r = allow_cls<NT, 0, false, false>(lds)) != hipSuccess) e = r;
@@ -816,10 +827,12 @@ hipError_t launch_cls_nt(const GbTileArgs &a, uint32_t grid, size_t lds, int pb,
 {
     if (so) return launch_cls_one<NT, 0, false, true>(a, grid, lds, st);
     if (pers) {
+        if (pb == 1) return launch_cls_one<NT, 1, true, false>(a, grid, lds, st);
         if (pb == 16) return launch_cls_one<NT, 16, true, false>(a, grid, lds, st);
         if (pb == 32) return launch_cls_one<NT, 32, true, false>(a, grid, lds, st);
         return launch_cls_one<NT, 0, true, false>(a, grid, lds, st);
     }
+    if (pb == 1) return launch_cls_one<NT, 1, false, false>(a, grid, lds, st);
     if (pb == 16) return launch_cls_one<NT, 16, false, false>(a, grid, lds, st);
     if (pb == 32) return launch_cls_one<NT, 32, false, false>(a, grid, lds, st);
     return launch_cls_one<NT, 0, false, false>(a, grid, lds, st);

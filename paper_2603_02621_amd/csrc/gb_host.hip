@@ -162,36 +162,33 @@ gb_status enqueue_tiles(gb_ctx *c, Workspace &ws, const Job &j, hipStream_t st)
     a.rec_cap = ws.recs.cap;
     a.pmin = j.pmin_dev;
     const Plan &pl = *j.pl;
-    // the bulk form runs on consecutive odd numbers, the minimal-p search in
-    // the residue-class layout
+    // minimal p and bulk verification both run the residue-class layout
+    // (pmin_bits 1: bulk, no per-n output, hit counts or checksum)
     const bool bulk = j.pmin_bits == 1;
     size_t lds6 = c->lds6;
-    if (!bulk) {
-        a.tile_n = c->tile_n;
-        if (!j.persistent) {
-            // the plain form's geometry (its plan was cut with kPlanClassPlain)
-            a.tile_n = c->tile_np;
-            a.sb_per_tile = c->sbp;
-            a.k6_wg_end = c->k6p_wg_end;
-            a.k6_wave_end = c->k6p_wave_end;
-            a.k6_single = c->k6p_single;
-            lds6 = c->lds6p;
-        }
+    a.tile_n = c->tile_n;
+    if (!j.persistent) {
+        // the plain form's geometry (its plan was cut with kPlanClassPlain)
+        a.tile_n = c->tile_np;
+        a.sb_per_tile = c->sbp;
+        a.k6_wg_end = c->k6p_wg_end;
+        a.k6_wave_end = c->k6p_wave_end;
+        a.k6_single = c->k6p_single;
+        lds6 = c->lds6p;
     }
     auto launch = [&](const GbTileArgs &b, uint32_t grid, bool pers, hipStream_t ls) -> hipError_t {
-        return bulk ? gb_launch_tiles(b, grid, c->threads, c->lds, j.pmin_bits, pers, false, c->group_window, ls)
-                    : gb_launch_cls(b, grid, c->threads, lds6, j.pmin_bits, pers, false, ls);
+        return gb_launch_cls(b, grid, c->threads, lds6, j.pmin_bits, pers, false, ls);
     };
     if (j.persistent) {
         a.win = ws.win.p;
         a.nwin = (uint32_t)pl.w.size();
         a.ntiles = pl.ntiles;
-        const uint64_t g = bulk ? std::min<uint64_t>(pl.ntiles, (uint64_t)c->num_cu * c->occupancy) : cls_grid(c, pl);
+        const uint64_t g = cls_grid(c, pl);
+        // the first 7/8 of the tiles round-robin, the rest from the queue
+        a.static_tiles = g * ((pl.ntiles - pl.ntiles / 8) / g);
         if (!bulk) {
             a.wg_hist = ws.wgh.p;   // num_cu * occ6 rows, at least g
             a.wg_hist_stride = c->wgh_stride;
-            // the first 7/8 of the tiles round-robin, the rest from the queue
-            a.static_tiles = g * ((pl.ntiles - pl.ntiles / 8) / g);
         }
         GB_HIP(c, launch(a, (uint32_t)g, true, st));
     } else {
@@ -235,7 +232,7 @@ gb_status enqueue_rest(gb_ctx *c, Workspace &ws, const Job &j, hipStream_t st)
     // the class search leaves n_exhaustive to this phase: an n counts when
     // no prime up to P_max gives it a partition (the class lists may stop
     // below P_max when they do not fit the LDS)
-    m.count_exh = j.pmin_bits == 1 ? 0u : 1u;
+    m.count_exh = 1u;
     m.pmax_fast = c->prm.pmax;
     if (j.persistent && j.pmin_bits != 1)
         GB_HIP(c, gb_launch_hist_reduce(ws.wgh.p, (uint32_t)cls_grid(c, *j.pl), c->wgh_stride, c->cls_recs,
@@ -650,14 +647,14 @@ gb_status setup_geometry(gb_ctx *c)
 
 // Split windows into tiles and fill the derived window fields; GB_ERANGE
 // when a window reaches past the resident sieving primes.  For the search
-// kernels each window's first n moves down to a multiple of 384 (the
-// search split by residue mod 6) or 128 (bulk), the n added in front
-// counted in `lead` (the kernels mask them).
+// (minimal p and bulk, split by residue mod 6) each window's first n moves
+// down to a multiple of 384, the n added in front counted in `lead` (the
+// kernel masks them).
 gb_status plan_windows(gb_ctx *c, Plan &pl, PlanKind kind)
 {
-    const bool cls = kind == kPlanClass || kind == kPlanClassPlain;
+    // the sieve dump cuts odd-number tiles; the searches residue-class ones
     const uint64_t T = kind == kPlanClass ? c->tile_n : kind == kPlanClassPlain ? c->tile_np : c->tile_n_odd;
-    const uint64_t A = cls ? 384 : 128;
+    const uint64_t A = 384;
     uint64_t tb = 0, off = 0;
     for (auto &w : pl.w) {
         const uint64_t user_count = w.count;
@@ -855,7 +852,7 @@ gb_status run_range(gb_ctx *c, uint64_t lo, uint64_t hi, gb_result *res, void *s
         pl.w[s].count = std::min(S, C - S * s);
         pl.w[s].slot = res->seg_hist ? (uint32_t)s : 0u;
     }
-    gb_status stt = plan_windows(c, pl, bulk ? kPlanOdd : batched ? kPlanClass : kPlanClassPlain);
+    gb_status stt = plan_windows(c, pl, batched ? kPlanClass : kPlanClassPlain);
     if (stt != GB_OK) return stt;
     const size_t hist_rows = res->seg_hist ? nseg : 1;
     stt = ensure_workspace(c, ws, pl, nslots, hist_rows);
@@ -1002,7 +999,7 @@ gb_status gb_tile_geometry(const gb_ctx *c, uint64_t *cls_tile_n, uint64_t *cls_
     if (cls_tile_n) *cls_tile_n = c->tile_n;
     if (cls_lds_bytes) *cls_lds_bytes = c->lds6;
     if (cls_list_primes) *cls_list_primes = c->np_cls;
-    if (bulk_tile_n) *bulk_tile_n = c->tile_n_odd;
+    if (bulk_tile_n) *bulk_tile_n = c->tile_n;
     return GB_OK;
 }
 

@@ -8,17 +8,17 @@
 
 // One window of consecutive even n.  A range call uses one window per
 // segment; the batched forms put many windows in one table.
-// The planner moves first_n down to a multiple of 128 and masks the `lead`
-// n it adds in front, so a 64-n block always covers one residue class of
-// floor(n/128).
+// The planner moves first_n down to a multiple of 384 and masks the `lead`
+// n it adds in front, so a block of 64 n of one class mod 6 always lies in
+// one stretch of 384 integers.
 struct GbWindow {
-    uint64_t first_n;    // even; a multiple of 128 for the search kernels
+    uint64_t first_n;    // even; a multiple of 384 for the search
     uint64_t count;      // even n in the window, the lead included
     uint64_t tile_base;  // global index of the window's first tile
     uint64_t out_off;    // per-n output index of the first n after the lead
     uint32_t slot;       // summary slot of the window
     uint32_t np_sieve;   // odd primes p of the table with p*p <= window top
-    uint32_t lead;       // masked n in front of the window (0..63)
+    uint32_t lead;       // masked n in front of the window (0..191)
     uint32_t pad;
 };
 

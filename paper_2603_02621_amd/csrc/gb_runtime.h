@@ -204,7 +204,7 @@ void free_tables(gb_ctx *c);
 // How a plan splits windows: the minimal-p search (tiles of tile_n, first
 // n moved down to a multiple of 384), the bulk form (tiles of
 // tile_n_odd, multiples of 128) or the odd-number sieve dump (no move).
-enum PlanKind { kPlanClass, kPlanClassPlain, kPlanOdd, kPlanSieve };
+enum PlanKind { kPlanClass, kPlanClassPlain, kPlanSieve };
 gb_status plan_windows(gb_ctx *c, Plan &pl, PlanKind kind = kPlanClass);
 gb_status ensure_workspace(gb_ctx *c, Workspace &ws, const Plan &pl, size_t nslots, size_t hist_rows);
 // init + tiles + exhaustive phase + argmax + summary copies, on `st`,

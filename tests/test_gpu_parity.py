@@ -168,7 +168,7 @@ def test_tile_geometry(tile_log2, pmax):
         assert g["cls_tile_n"] % 192 == 0
         assert 192 * max(1, t // 192) <= g["cls_tile_n"] <= 192 * (t // 96)
         assert g["cls_lds_bytes"] <= 160 * 1024
-        assert g["bulk_tile_n"] == t
+        assert g["bulk_tile_n"] == g["cls_tile_n"]
         n_odd = sum(1 for q in range(3, pmax + 1, 2) if all(q % d for d in range(3, int(q**0.5) + 1, 2)))
         if g["cls_tile_n"] > 192 * max(1, t // 192):
             assert g["cls_list_primes"] == n_odd

@@ -51,7 +51,7 @@ struct HistCarry {
 constexpr unsigned long long kNoSlot = ~0ull;
 enum { CY_COUNT, CY_SUM, CY_EXH, CY_ARGN, CY_SLOT, CY_MAXP };
 
-__device__ void flush_slot(const GbTileArgs &a, unsigned long long *C)
+__device__ inline void flush_slot(const GbTileArgs &a, unsigned long long *C)
 {
     if (C[CY_SLOT] == kNoSlot) return;
     GbSlot *S = a.slots + C[CY_SLOT];

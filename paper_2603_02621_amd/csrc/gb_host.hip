@@ -81,13 +81,11 @@ GbTileArgs base_args(gb_ctx *c, Workspace &ws)
     GbTileArgs a{};
     a.tile_n = c->tile_n_odd;
     a.halo_bits = c->halo_bits;
-    a.np_search = c->np_search;
     a.primes = c->d_primes;
     a.magic = c->d_magic;
     a.k_first = c->k_first;
     a.k_wg_end = c->k_wg_end;
     a.k_wave_end = c->k_wave_end;
-    a.n_off = c->k_wave_end - c->k_first;
     a.wheel = c->d_wheel;
     a.wheel_len = c->wheel_len;
     a.wheel_max = c->prm.wheel_max;
@@ -469,20 +467,6 @@ gb_status setup_geometry(gb_ctx *c)
     c->tile_n_odd = 1u << p.tile_log2;
     c->threads = p.wg_threads;
     c->np_search = count_le(c->h_primes, p.pmax);
-    // The search reads each group of four probes' windows at once when, in
-    // every group of the (padded) prime list, a probe starts at most one word
-    // above the base word of the group's last prime.
-    {
-        const uint32_t n = c->np_search;
-        auto hof = [&](uint32_t i) { return (c->h_primes[i < n ? i : n - 1] + 1) / 2; };
-        bool ok = n > 0;
-        for (uint32_t k = 0; ok && k < n; k += 4) {
-            const uint32_t w3 = (hof(k + 3) + 31) / 32;
-            for (uint32_t u = 0; u < 3; ++u)
-                if (w3 - (hof(k + u) + 31) / 32 > 1) ok = false;
-        }
-        c->group_window = ok;
-    }
     const uint32_t need = (p.pmax + 1) / 2;
     c->halo_bits = std::max<uint32_t>(64, (need + 63) / 64 * 64);
     c->k_first = count_le(c->h_primes, p.wheel_max);
@@ -497,7 +481,7 @@ gb_status setup_geometry(gb_ctx *c)
     // - one lane per prime above.
     c->k_wg_end = std::max(c->k_first, count_le(c->h_primes, nbits / (32 * c->threads)));
     c->k_wave_end = std::max(c->k_wg_end, count_le(c->h_primes, nbits / 256));
-    c->lds = gb_tile_lds_bytes(c->tile_n_odd, c->halo_bits, c->np_search, c->k_wave_end - c->k_first);
+    c->lds = gb_tile_lds_bytes(c->tile_n_odd, c->halo_bits, c->k_wave_end - c->k_first);
     if (c->lds > 160 * 1024)
         return fail(c, GB_EINVAL, "tile does not fit in LDS (" + std::to_string(c->lds) +
                                       " bytes); lower tile_log2, wg_threads or pmax");
@@ -510,9 +494,6 @@ gb_status setup_geometry(gb_ctx *c)
         c->plain_hwq = (int)std::max<long>(1, std::min<long>(gb_ctx::kPlainLanes, hw > 0 ? hw : 4));
     }
     GB_HIP(c, gb_prepare_tiles(c->threads, c->lds));
-    int occ = 0;
-    GB_HIP(c, gb_tile_occupancy(c->threads, c->lds, c->group_window, &occ));
-    c->occupancy = std::max(occ, 1);
     // wheel pattern over (v-1)/2 for odd v: bit g set iff 2g+1 is coprime to the wheel
     static const uint32_t wp[] = {3, 5, 7, 11, 13, 17, 19};
     uint32_t L = 1;
@@ -617,7 +598,7 @@ gb_status setup_geometry(gb_ctx *c)
     GB_HIP(c, hipMalloc(&c->d_cls, T.size() * 4));
     GB_HIP(c, hipMemcpy(c->d_cls, T.data(), T.size() * 4, hipMemcpyHostToDevice));
     GB_HIP(c, gb_cls_prepare(c->threads, c->lds6));
-    occ = 0;
+    int occ = 0;
     GB_HIP(c, gb_cls_occupancy(c->threads, c->lds6, &occ));
     c->occ6 = std::max(occ, 1);
     // plane i (c = 1, 5): bit k set iff 6k + c is prime to every wheel prime
@@ -748,7 +729,7 @@ gb_status enqueue_sieve(gb_ctx *c, Workspace &ws, uint64_t w0, uint64_t nbits, u
     a.nwin = 1;
     a.tile0 = 0;
     a.sieve_out = bits;
-    GB_HIP(c, gb_launch_tiles(a, (uint32_t)pl.ntiles, c->threads, c->lds, 0, false, true, false, st));
+    GB_HIP(c, gb_launch_tiles(a, (uint32_t)pl.ntiles, c->threads, c->lds, st));
     return GB_OK;
 }
 

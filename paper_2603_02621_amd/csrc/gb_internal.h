@@ -54,13 +54,11 @@ struct GbTileArgs {
     uint64_t ntiles;        // tiles in the whole table (persistent mode)
     uint64_t tile0;         // first tile of this launch (non-persistent)
     uint32_t halo_bits;     // HB: bits below the tile's first n (multiple of 64)
-    uint32_t np_search;     // odd primes <= P_max
     const uint32_t *primes; // odd primes 3, 5, 7, ... ascending
     const unsigned long long *magic;  // floor((2^64-1)/p) per prime
     uint32_t k_first;       // first prime index above the wheel
     uint32_t k_wg_end;      // primes [k_first, k_wg_end): whole-workgroup marking
     uint32_t k_wave_end;    // primes [k_wg_end, k_wave_end): one wave per prime
-    uint32_t n_off;         // LDS slots for first strikes: k_wave_end - k_first
     const uint32_t *wheel;  // wheel pattern bits, period wheel_len, padded by 64
     uint32_t wheel_len;     // product of the odd wheel primes
     uint32_t wheel_max;     // largest wheel prime
@@ -139,16 +137,10 @@ struct GbMrArgs {
 };
 
 // Kernel launchers (gb_kernels.hip).
-// group_window: the search form that reads each group of four probes'
-// window words at once (needs every group of the prime list to span at
-// most 63 bits of offset from its last prime's base word)
-hipError_t gb_launch_tiles(const GbTileArgs &a, uint32_t grid, uint32_t threads,
-                           size_t lds_bytes, int pmin_bits, bool persistent,
-                           bool sieve_only, bool group_window, hipStream_t st);
+// The odd-number sieve dump (non-persistent, one workgroup per tile).
+hipError_t gb_launch_tiles(const GbTileArgs &a, uint32_t grid, uint32_t threads, size_t lds_bytes, hipStream_t st);
 hipError_t gb_prepare_tiles(uint32_t threads, size_t lds_bytes);
-hipError_t gb_tile_occupancy(uint32_t threads, size_t lds_bytes, bool group_window, int *blocks_per_cu);
-size_t gb_tile_lds_bytes(uint32_t tile_n, uint32_t halo_bits, uint32_t np_search,
-                         uint32_t n_off);
+size_t gb_tile_lds_bytes(uint32_t tile_n, uint32_t halo_bits, uint32_t n_off);
 hipError_t gb_launch_mr(const GbMrArgs &a, uint32_t grid, hipStream_t st);
 // The kernel of the search split by residue mod 6 (gb_class.hip).
 size_t gb_cls_lds_bytes(uint32_t sb_per_tile, uint32_t hk, uint32_t cls_words, uint32_t n_wg_primes);

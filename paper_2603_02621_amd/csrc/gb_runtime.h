@@ -158,26 +158,23 @@ struct gb_ctx {
     uint32_t *d_wheel6 = nullptr;    // two plane patterns
     uint32_t wheel6_len = 0, wheel6_stride = 0;
     uint32_t k6_first = 0, k6_wg_end = 0, k6_wave_end = 0, k6_single = 0;
-    // the plain form's class tiles (one launch per segment, four in flight):
-    // small enough that a segment fills a quarter of the device
+    // the plain form's class tiles (one launch per segment, plain_lanes
+    // segments in flight): small enough that those segments fill the device
     uint32_t sbp = 0, tile_np = 0, k6p_wg_end = 0, k6p_wave_end = 0, k6p_single = 0;
     size_t lds6p = 0;
     size_t lds6 = 0;
     int occ6 = 1;
-    // bulk verification and the sieve dump, consecutive odd numbers
-    // (gb_kernels.hip): tiles of tile_n_odd even n, windows aligned to 128
+    // the odd-number sieve dump (gb_kernels.hip): tiles of tile_n_odd bits
+    // behind a halo of halo_bits
     uint32_t tile_n_odd = 0;
     uint32_t np_search = 0, k_first = 0, halo_bits = 0;
     uint32_t *d_wheel = nullptr;
     uint32_t wheel_len = 0;
     uint32_t k_wg_end = 0, k_wave_end = 0;
     size_t lds = 0;
-    bool group_window = false;       // search form: one window read per group of four probes
-    int occupancy = 1;
     // plain form: segment launches go round-robin to the caller's stream and
     // these (created on first use), forked after the init kernel and joined
-    // before the exhaustive phase
-    // The plain form runs up to kPlainLanes segments side by side, one per
+    // before the exhaustive phase.  It runs up to kPlainLanes segments side by side, one per
     // stream: no more than the process has hardware queues (plain_hwq, from
     // GPU_MAX_HW_QUEUES, 4 when unset; streams beyond that share queues and
     // run in turn), and no more than keep the tiles in flight within 1/8 of

@@ -531,6 +531,7 @@ __device__ void cls_tile(const GbTileArgs &a, unsigned long long g, const ClsLds
         if (Ulo | Uhi) push_unresolved(bb, Ulo, Uhi);
         Ulo = Uhi = 0u;
     };
+    constexpr uint32_t kChunk = 128u;
     uint32_t c_next = 0, c_end = 0;
     if (b < nblk) {
         set_block(b);
@@ -605,7 +606,8 @@ __device__ void cls_tile(const GbTileArgs &a, unsigned long long g, const ClsLds
             ka += 48u;
         }
         // lanes that finish a block take the next blocks of their wave's
-        // chunk; a wave whose chunk runs short takes a new one
+        // chunk; a wave whose chunk runs short takes a new one of kChunk
+        // blocks (at least 64, so that one refill serves every lane)
         const unsigned long long dm =
             __builtin_amdgcn_uicmp(Ulo | Uhi, 0u, 32) | __builtin_amdgcn_uicmp(ka, ka_end, 35);  // ==, >=
         if (dm != 0ull) {
@@ -621,13 +623,13 @@ __device__ void cls_tile(const GbTileArgs &a, unsigned long long g, const ClsLds
                 if (lane == leader) {
                     uint32_t na = (uint32_t)(uintptr_t)(lds_u32 *)L.next;
                     asm volatile("" : "+v"(na));
-                    cn = __hip_atomic_fetch_add(reinterpret_cast<lds_u32 *>(static_cast<uintptr_t>(na)), 64u,
+                    cn = __hip_atomic_fetch_add(reinterpret_cast<lds_u32 *>(static_cast<uintptr_t>(na)), kChunk,
                                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
                 }
                 cn = __builtin_amdgcn_readlane(cn, leader);
                 nb = r < rm ? nb : cn + (r - rm);
                 c_next = cn + (cn2 - rm);
-                c_end = cn + 64u;
+                c_end = cn + kChunk;
             }
             if ((Ulo | Uhi) == 0u || ka >= ka_end) {
                 accbg += (unsigned long long)(long long)((int)b - (int)nb) * sumg;

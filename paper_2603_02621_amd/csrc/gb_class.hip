@@ -36,15 +36,17 @@
 // Sieve.  The planes are cleared of the multiples m p (m = 1 or 5 mod 6,
 // m p >= p^2) of every sieving prime above the wheel (the wheel pattern
 // removes the multiples of 5 .. wheel_max; 2 and 3 never occur): for each
-// plane the multiples form one progression of stride p in k.  Small primes
-// stride with the whole workgroup, medium ones with one wave, large ones
-// with one lane per prime (both planes).  Planes are marked with
+// plane the multiples form one progression of stride p in k.  Primes up to
+// the plane length / 64 stride with one wave each, larger ones with one lane
+// per prime (both planes).  Planes are marked with
 // 1 = composite (LDS OR atomics) and inverted before the search.
 //
-// The hit bookkeeping, the block hand-out and the tile summary follow the
-// kernel for consecutive n (gb_kernels.hip); the checksum weight of n is
-// 2^33 b(n) + (2c+1) 2^i with b(n) = N0/128 + the block index 3 K + a/2 and
-// j = 32 c + i.
+// A hit (prime p, mask h of the n it settles) adds the popcount of h to
+// p's hit counter and three multiply-adds to the checksum sums; a block
+// keeps the key of its last hit, which carries its largest p_min.  The
+// checksum weight of n is 2^33 b(n) + (2c+1) 2^i with b(n) = N0/128 + the
+// block index 3 K + a/2 and j = 32 c + i.  Lanes take blocks as they finish
+// them, from chunks their wave takes off a workgroup counter.
 #include <type_traits>
 
 #include "gb_internal.h"
@@ -84,7 +86,6 @@ __device__ __forceinline__ uint32_t plane_off(uint32_t k, uint32_t i) { return (
 struct ClsLds {
     uint32_t *planes;          // 2 (Lk/32 + 4) words: the planes and padding rows
     uint32_t *cls;             // class headers and probe records (GB_CLS_*)
-    uint32_t *woff;            // per workgroup-class prime: first strike in plane 0, p, in plane 1, p
     unsigned long long *red;   // 7: checksum, n_exhaustive, max key, OR words, deficits
     unsigned long long *carry; // 6: the slot carry
     unsigned long long *tile;  // persistent mode: the tile just taken
@@ -101,9 +102,7 @@ __device__ __forceinline__ ClsLds carve_cls(uint32_t *smem, const GbTileArgs &a)
     o = (o + 3u) & ~3u;   // records are read 16 bytes at a time
     L.cls = smem + o;
     o += a.cls_words;
-    o = (o + 1u) & ~1u;   // woff pairs are read 8 bytes at a time
-    L.woff = smem + o;
-    o += 4u * (a.k6_wg_end - a.k6_first);
+    o = (o + 1u) & ~1u;   // 64-bit reductions
     L.red = reinterpret_cast<unsigned long long *>(smem + o);
     o += 2u * 7u;
     L.carry = reinterpret_cast<unsigned long long *>(smem + o);
@@ -275,22 +274,6 @@ __device__ void cls_tile(const GbTileArgs &a, unsigned long long g, const ClsLds
         hc.n += cnt;
     }
 
-    // ---- first strikes of the workgroup-class primes, both planes ----------
-    const uint32_t kwg = min(a.k6_wg_end, np);
-    for (uint32_t e = tid; e < a.k6_wg_end - a.k6_first; e += NT) {
-        const uint32_t k = a.k6_first + e;
-        uint32_t f0 = 0xFFFFFFFFu, f1 = 0xFFFFFFFFu, p = 0u;
-        if (k < kwg) {
-            p = strikes_clamped(a, fast, Kb, kbd, k, Lk, f0, f1);
-            if (f0 >= Lk) f0 = 0xFFFFFFFFu;
-            if (f1 >= Lk) f1 = 0xFFFFFFFFu;
-        }
-        L.woff[4u * e] = f0;
-        L.woff[4u * e + 1u] = p;
-        L.woff[4u * e + 2u] = f1;
-        L.woff[4u * e + 3u] = p;
-    }
-
     // ---- wheel pattern, 1 = composite --------------------------------------
     // Word w of plane i holds k = Kb + 32 w + b; pattern bit (Kb + 32 w + b)
     // mod P is 1 when 6 k + c_i is prime to every wheel prime 5 .. wheel_max.
@@ -327,31 +310,12 @@ __device__ void cls_tile(const GbTileArgs &a, unsigned long long g, const ClsLds
     __syncthreads();
 
     // ---- marking -------------------------------------------------------------
-    // small primes: the whole workgroup, half the threads per plane; the
-    // thread stride (NT/2) p bits is a multiple of 32, so the bit stays put
-    {
-        const uint32_t i = tid & 1u;
-        const uint32_t nwg = kwg > a.k6_first ? kwg - a.k6_first : 0u;
-        const unsigned long long *sp = reinterpret_cast<const unsigned long long *>(L.woff) + i;
-        for (uint32_t e = 0; e < nwg; ++e) {
-            const unsigned long long v = sp[2u * e];   // first strike in plane i, p
-            const uint32_t s = (uint32_t)v, p = (uint32_t)(v >> 32);
-            if (s != 0xFFFFFFFFu) {
-                const uint32_t kk = s + __umul24(tid >> 1, p);
-                if (kk < Lk) {
-                    const uint32_t m = 1u << (kk & 31u);
-                    const uint32_t stride = (NT / 2u) * p / 4u;   // bytes: (NT/2) p / 32 rows of 8 bytes
-                    for (uint32_t wa = base_a + plane_off(kk, i); wa < end_a; wa += stride) lds_or(wa, m);
-                }
-            }
-        }
-    }
     // medium primes: one wave per prime, 32 lanes per plane, lane stride
     // 32 p.  Rounds of NT primes: lane j of wave w finds the first strikes
     // of prime w + NWAVES j of the round, then the wave takes its primes in
     // turn, each broadcast from its lane.
     {
-        const uint32_t kbeg = max(a.k6_wg_end, a.k6_first);
+        const uint32_t kbeg = a.k6_first;
         const uint32_t kend = min(a.k6_wave_end, np);
         const uint32_t i = lane & 1u;
         for (uint32_t kr = kbeg + __builtin_amdgcn_readfirstlane(wave); kr < kend; kr += NT) {
@@ -842,14 +806,13 @@ hipError_t launch_cls_nt(const GbTileArgs &a, uint32_t grid, size_t lds, int pb,
 
 }  // namespace
 
-size_t gb_cls_lds_bytes(uint32_t sb_per_tile, uint32_t hk, uint32_t cls_words, uint32_t n_wg_primes)
+size_t gb_cls_lds_bytes(uint32_t sb_per_tile, uint32_t hk, uint32_t cls_words)
 {
     // the same carve-up as carve_cls()
     size_t words = 2 * ((size_t)(hk + 64 * sb_per_tile) / 32 + 4);
     words = (words + 3) & ~(size_t)3;
     words += cls_words;
     words = (words + 1) & ~(size_t)1;
-    words += 4 * (size_t)n_wg_primes;
     words += 2 * 7 + 2 * 6 + 2 + 2 + 7;
     return words * 4;
 }

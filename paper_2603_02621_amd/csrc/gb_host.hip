@@ -102,7 +102,6 @@ GbTileArgs base_args(gb_ctx *c, Workspace &ws)
     a.wheel6_len = c->wheel6_len;
     a.wheel6_stride = c->wheel6_stride;
     a.k6_first = c->k6_first;
-    a.k6_wg_end = c->k6_wg_end;
     a.k6_wave_end = c->k6_wave_end;
     a.k6_single = c->k6_single;
     a.pmax_fast = c->prm.pmax;
@@ -169,7 +168,6 @@ gb_status enqueue_tiles(gb_ctx *c, Workspace &ws, const Job &j, hipStream_t st)
         // the plain form's geometry (its plan was cut with kPlanClassPlain)
         a.tile_n = c->tile_np;
         a.sb_per_tile = c->sbp;
-        a.k6_wg_end = c->k6p_wg_end;
         a.k6_wave_end = c->k6p_wave_end;
         a.k6_single = c->k6p_single;
         lds6 = c->lds6p;
@@ -532,12 +530,13 @@ gb_status setup_geometry(gb_ctx *c)
     for (;;) {
         T = class_table(c, np, c->hk);
         const uint32_t Lk = c->hk + 64 * c->sb_per_tile;
-        // strikes per thread and plane: workgroup class Lk / ((threads/2) p),
-        // wave class Lk / (32 p), both at least two
-        c->k6_wg_end = std::max(c->k6_first, count_le(c->h_primes, Lk / c->threads));
-        c->k6_wave_end = std::max(c->k6_wg_end, count_le(c->h_primes, Lk / 64));
+        // one wave per prime up to Lk/64 (at least two strikes per lane and
+        // plane); no whole-workgroup class: at 10^12 striding a workgroup over
+        // each prime up to Lk/threads took 28.15 ms a launch, up to
+        // Lk/(8 threads) 27.58 ms, and none 27.28 ms (same box)
+        c->k6_wave_end = std::max(c->k6_first, count_le(c->h_primes, Lk / 64));
         c->k6_single = std::max(c->k6_wave_end, count_le(c->h_primes, Lk - 1));
-        c->lds6 = gb_cls_lds_bytes(c->sb_per_tile, c->hk, (uint32_t)T.size(), c->k6_wg_end - c->k6_first);
+        c->lds6 = gb_cls_lds_bytes(c->sb_per_tile, c->hk, (uint32_t)T.size());
         if (c->lds6 <= 160 * 1024 || np == 0) break;
         if (c->sb_per_tile > sb_min)
             c->sb_per_tile = std::max(sb_min, c->sb_per_tile - std::max<uint32_t>(1, c->sb_per_tile / 64));
@@ -564,10 +563,9 @@ gb_status setup_geometry(gb_ctx *c)
         c->plain_lanes = (int)std::max<uint64_t>(1, std::min<uint64_t>((uint64_t)c->plain_hwq, fit));
         c->tile_np = 192u * c->sbp;
         const uint32_t Lk = c->hk + 64 * c->sbp;
-        c->k6p_wg_end = std::max(c->k6_first, count_le(c->h_primes, Lk / c->threads));
-        c->k6p_wave_end = std::max(c->k6p_wg_end, count_le(c->h_primes, Lk / 64));
+        c->k6p_wave_end = std::max(c->k6_first, count_le(c->h_primes, Lk / 64));
         c->k6p_single = std::max(c->k6p_wave_end, count_le(c->h_primes, Lk - 1));
-        c->lds6p = gb_cls_lds_bytes(c->sbp, c->hk, (uint32_t)T.size(), c->k6p_wg_end - c->k6_first);
+        c->lds6p = gb_cls_lds_bytes(c->sbp, c->hk, (uint32_t)T.size());
     }
     if (c->lds6 > 160 * 1024)
         return fail(c, GB_EINVAL, "tile does not fit in LDS (" + std::to_string(c->lds6) + " bytes); lower tile_log2");

@@ -84,8 +84,7 @@ struct GbTileArgs {
     uint32_t wheel6_len;
     uint32_t wheel6_stride;
     uint32_t k6_first;         // first prime index above the wheel
-    uint32_t k6_wg_end;        // [k6_first, k6_wg_end): whole-workgroup marking
-    uint32_t k6_wave_end;      // [k6_wg_end, k6_wave_end): one wave per prime
+    uint32_t k6_wave_end;      // [k6_first, k6_wave_end): one wave per prime
     uint32_t k6_single;        // from here on p >= plane bits of a full tile: one strike per plane at most
     uint64_t sieve_stride;     // plane dump: words per plane in sieve_out
     uint32_t pmax_fast;        // P_max: n with a larger p_min count as exhaustive
@@ -143,7 +142,7 @@ hipError_t gb_prepare_tiles(uint32_t threads, size_t lds_bytes);
 size_t gb_tile_lds_bytes(uint32_t tile_n, uint32_t halo_bits, uint32_t n_off);
 hipError_t gb_launch_mr(const GbMrArgs &a, uint32_t grid, hipStream_t st);
 // The kernel of the search split by residue mod 6 (gb_class.hip).
-size_t gb_cls_lds_bytes(uint32_t sb_per_tile, uint32_t hk, uint32_t cls_words, uint32_t n_wg_primes);
+size_t gb_cls_lds_bytes(uint32_t sb_per_tile, uint32_t hk, uint32_t cls_words);
 hipError_t gb_cls_prepare(uint32_t threads, size_t lds_bytes);
 hipError_t gb_cls_occupancy(uint32_t threads, size_t lds_bytes, int *blocks_per_cu);
 hipError_t gb_launch_cls(const GbTileArgs &a, uint32_t grid, uint32_t threads, size_t lds_bytes, int pmin_bits,

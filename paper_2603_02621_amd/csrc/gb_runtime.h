@@ -157,10 +157,10 @@ struct gb_ctx {
     uint32_t wgh_stride = 0;         // words per workgroup row of Workspace::wgh
     uint32_t *d_wheel6 = nullptr;    // two plane patterns
     uint32_t wheel6_len = 0, wheel6_stride = 0;
-    uint32_t k6_first = 0, k6_wg_end = 0, k6_wave_end = 0, k6_single = 0;
+    uint32_t k6_first = 0, k6_wave_end = 0, k6_single = 0;
     // the plain form's class tiles (one launch per segment, plain_lanes
     // segments in flight): small enough that those segments fill the device
-    uint32_t sbp = 0, tile_np = 0, k6p_wg_end = 0, k6p_wave_end = 0, k6p_single = 0;
+    uint32_t sbp = 0, tile_np = 0, k6p_wave_end = 0, k6p_single = 0;
     size_t lds6p = 0;
     size_t lds6 = 0;
     int occ6 = 1;

@@ -158,8 +158,10 @@ gb_status gb_tile_geometry(const gb_ctx *ctx, uint64_t *cls_tile_n, uint64_t *cl
                            uint64_t *cls_list_primes, uint64_t *bulk_tile_n);
 
 /* Plain form: p_min for every even n in [max(lo,4), hi], one kernel launch
- * per segment of S even n, in order, on `stream`; then the exhaustive phase
- * and the summary reduction.  (Problem statement: section "Methods"; the
+ * per segment of S even n; consecutive segments go round-robin to `stream`
+ * and up to seven library streams forked from it (no more than the process
+ * has hardware queues, GPU_MAX_HW_QUEUES, 4 when unset) and joined back into
+ * `stream`; then the exhaustive phase and the summary reduction.  (Problem statement: section "Methods"; the
  * segment loop: subsection "Correct segmentation".)  Returns GB_EUNRESOLVED
  * when some n has no partition within the budget. */
 gb_status gb_verify_range(gb_ctx *ctx, uint64_t lo, uint64_t hi,
